@@ -1,0 +1,170 @@
+"""Seeded synthetic scenes, cameras and trajectories.
+
+This module only draws inputs: Gaussian parameter tables, pinhole cameras
+and camera paths.  It holds none of the rasterizer's, the loss's or the
+optimizer's arithmetic, so that the FP64 oracle and the GPU path can share
+it without sharing any of the method.
+
+Parameter rows have 59 float32 columns (the degree-3 SH parameterisation of
+Sec. 2, "Per-Gaussian parameter table"):
+
+    [0:3]   mean xyz (world)
+    [3:6]   log scale
+    [6:10]  rotation quaternion (w, x, y, z), not necessarily unit length
+    [10]    opacity logit
+    [11:14] SH DC coefficient (r, g, b)
+    [14:59] 15 higher SH coefficients, coefficient-major, (r, g, b) each
+
+Cameras are dicts with world-to-camera ``R`` (3x3, row-major) and ``t``
+(p_cam = R @ p_world + t, x right, y down, z forward), focal lengths,
+principal point, image size and the near/far planes.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+D = 59
+
+
+def _attributes(rng: np.random.Generator, n: int, logscale_mu: float,
+                logscale_sigma: float) -> np.ndarray:
+    """Everything except the means, drawn as the tiny-scene recipe states."""
+    th = np.empty((n, D), dtype=np.float64)
+    th[:, 3:6] = rng.normal(logscale_mu, logscale_sigma, size=(n, 3))
+    q = rng.normal(0.0, 1.0, size=(n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    th[:, 6:10] = q
+    th[:, 10] = rng.normal(0.0, 1.0, size=n)
+    th[:, 11:14] = rng.normal(0.0, 0.3, size=(n, 3))
+    th[:, 14:59] = rng.normal(0.0, 0.05, size=(n, 45))
+    return th
+
+
+def tiny_scene(n: int = 1000, seed: int = 0) -> np.ndarray:
+    """Tiny scene: means U[-1,1]^3, log-scale N(-4, 0.5)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mu = rng.uniform(-1.0, 1.0, size=(n, 3))
+    th = _attributes(rng, n, -4.0, 0.5)
+    th[:, 0:3] = mu
+    return th.astype(np.float32)
+
+
+def blob_scene(n_blobs: int, per_blob: int, half_extent: float,
+               height: tuple[float, float], sigma: float, seed: int,
+               logscale_mu: float = -1.0, logscale_sigma: float = 0.7) -> np.ndarray:
+    """Aerial-style scene: Gaussian blobs (std ``sigma``) whose centres are
+    uniform over a [-half_extent, half_extent]^2 ground square with heights
+    U(height); world z is up."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cx = rng.uniform(-half_extent, half_extent, size=n_blobs)
+    cy = rng.uniform(-half_extent, half_extent, size=n_blobs)
+    cz = rng.uniform(height[0], height[1], size=n_blobs)
+    centres = np.stack([cx, cy, cz], axis=1)
+    n = n_blobs * per_blob
+    mu = np.repeat(centres, per_blob, axis=0) + rng.normal(0.0, sigma, size=(n, 3))
+    th = _attributes(rng, n, logscale_mu, logscale_sigma)
+    th[:, 0:3] = mu
+    return th.astype(np.float32)
+
+
+def perturbed(theta: np.ndarray, sigma: float, seed: int) -> np.ndarray:
+    """theta + N(0, sigma^2) on every column (the seeded target parameters)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return (theta.astype(np.float64) + rng.normal(0.0, sigma, size=theta.shape)).astype(np.float32)
+
+
+@dataclass
+class Camera:
+    R: np.ndarray          # 3x3 world->camera
+    t: np.ndarray          # 3
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    width: int
+    height: int
+    z_near: float = 0.2
+    z_far: float = 1.0e4
+
+    def as_row(self) -> np.ndarray:
+        """Flat float64 row: R(9) t(3) fx fy cx cy W H z_near z_far."""
+        return np.concatenate([
+            np.asarray(self.R, np.float64).reshape(9), np.asarray(self.t, np.float64).reshape(3),
+            [self.fx, self.fy, self.cx, self.cy, float(self.width), float(self.height),
+             self.z_near, self.z_far]]).astype(np.float64)
+
+
+def cams_array(cams: list[Camera]) -> np.ndarray:
+    return np.stack([c.as_row() for c in cams], axis=0)
+
+
+def look_at(eye, target, up, width: int, height: int, f: float,
+            z_near: float = 0.2, z_far: float = 1.0e4,
+            cx: float | None = None, cy: float | None = None) -> Camera:
+    eye = np.asarray(eye, np.float64)
+    fwd = np.asarray(target, np.float64) - eye
+    fwd /= np.linalg.norm(fwd)
+    right = np.cross(fwd, np.asarray(up, np.float64))
+    right /= np.linalg.norm(right)
+    down = np.cross(fwd, right)
+    R = np.stack([right, down, fwd], axis=0)
+    t = -R @ eye
+    return Camera(R, t, f, f, width / 2.0 if cx is None else cx,
+                  height / 2.0 if cy is None else cy, width, height, z_near, z_far)
+
+
+def tiny_camera() -> Camera:
+    """64x64, f = 64, principal point (32, 32), identity rotation, centre (0,0,-3)."""
+    return Camera(np.eye(3), np.array([0.0, 0.0, 3.0]), 64.0, 64.0, 32.0, 32.0, 64, 64)
+
+
+def focal_for_hfov(width: int, hfov_deg: float) -> float:
+    return (width / 2.0) / math.tan(math.radians(hfov_deg) / 2.0)
+
+
+def orbit_cameras(n_views: int, radius: float, altitude: float, look: tuple,
+                  width: int = 1920, height: int = 1080, hfov_deg: float = 60.0,
+                  z_far: float = 1.0e4) -> list[Camera]:
+    """Views evenly spaced on a circle at ``altitude`` looking at ``look``."""
+    f = focal_for_hfov(width, hfov_deg)
+    out = []
+    for k in range(n_views):
+        a = 2.0 * math.pi * k / n_views
+        eye = (radius * math.cos(a), radius * math.sin(a), altitude)
+        out.append(look_at(eye, look, (0.0, 0.0, 1.0), width, height, f, 0.2, z_far))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Workloads used by tests and the benchmark
+# ---------------------------------------------------------------------------
+
+def tiny_workload():
+    """Tiny scene, 1000 Gaussians, one 64x64 camera (seed 0, target seed 1)."""
+    theta = tiny_scene(1000, 0)
+    return theta, [tiny_camera()], perturbed(theta, 0.05, 1)
+
+
+def aerial_workload(n_blobs: int = 200, per_blob: int = 5000, seed: int = 10,
+                    n_views: int = 400, width: int = 1920, height: int = 1080):
+    """Resident aerial training: 200 blobs x 5000 Gaussians (sigma 5 m) over a
+    500 x 500 m plane, heights U(0, 40) m, log-scale N(-1, 0.7); 1920x1080
+    views (60 deg horizontal fov) on a radius-250 m orbit at 150 m altitude
+    looking at (0, 0, 20)."""
+    theta = blob_scene(n_blobs, per_blob, 250.0, (0.0, 40.0), 5.0, seed)
+    cams = orbit_cameras(n_views, 250.0, 150.0, (0.0, 0.0, 20.0), width, height)
+    return theta, cams
+
+
+def dense_scene(n: int, seed: int, extent: float = 1.0, logscale_mu: float = -2.5,
+                logscale_sigma: float = 0.5) -> np.ndarray:
+    """A denser variant of the tiny scene (larger footprints, deeper lists):
+    exercises early termination and long per-tile lists at small sizes."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mu = rng.uniform(-extent, extent, size=(n, 3))
+    th = _attributes(rng, n, logscale_mu, logscale_sigma)
+    th[:, 0:3] = mu
+    return th.astype(np.float32)
