@@ -1,0 +1,257 @@
+/* tide.h -- C ABI of the MI355X (gfx950) training hot path of out-of-core
+ * 3D Gaussian Splatting (TideGS, arXiv 2605.20150).
+ *
+ * The paper keeps the standard 3DGS forward/backward on the resident
+ * Gaussians (Sec. 3.3, "Level 2") and adds a block tier around it (Sec. 3.3
+ * to 3.5, Alg. 1).  This header exposes both halves:
+ *
+ *   per iteration, on the GPU          tide_preprocess -> tide_bin_sort ->
+ *                                      tide_render_fwd -> tide_loss ->
+ *                                      tide_render_bwd -> tide_adam_sparse
+ *   around it, on the host             tide_cull_blocks, tide_stream_delta,
+ *                                      tide_ensure_resident, ...
+ *   learned prefetch predictor         tide_mlp_*
+ *
+ * Conventions shared by every call
+ *   - Device memory is owned by the caller.  Pointers documented as "device"
+ *     must be device (HBM) pointers; "host" pointers are ordinary memory.
+ *     The library never allocates device memory on the per-iteration path;
+ *     calls that need scratch take a caller workspace (ws, ws_bytes) and
+ *     report the size they need.
+ *   - Device work is enqueued on the HIP stream passed as `stream`
+ *     (a hipStream_t; NULL = the default stream) and is asynchronous unless a
+ *     call says it blocks.
+ *   - Every call returns a tide_status; nothing throws across the ABI.
+ *     Arguments are validated on the host before anything is launched.
+ *     tide_last_error() returns a thread-local message for the last failure.
+ *   - Parameter rows have TIDE_D = 59 columns: mean(3), log-scale(3),
+ *     quaternion w,x,y,z (4), opacity logit (1), SH degree-3 coefficients
+ *     16 x (r,g,b) coefficient-major (48).  (Sec. 2, D = 59.)
+ *   - dtype TIDE_F32 is the training path; TIDE_F64 is the same kernels
+ *     instantiated in double precision for gradient checks.
+ */
+#ifndef TIDE_H
+#define TIDE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tide_status;
+#define TIDE_OK 0
+#define TIDE_EINVAL (-1)     /* bad argument (null, misaligned, size, dtype) */
+#define TIDE_ECAPACITY (-2)  /* a caller buffer is too small; the call says which size it needs */
+#define TIDE_EHIP (-3)       /* a HIP runtime call failed */
+#define TIDE_EIO (-4)        /* file I/O failed (block store) */
+#define TIDE_ESTATE (-5)     /* call out of order / object in the wrong state */
+
+#define TIDE_F32 0
+#define TIDE_F64 1
+#define TIDE_D 59
+#define TIDE_TILE 16
+#define TIDE_MAX_CAMS 8
+
+const char* tide_last_error(void);
+int32_t tide_abi_version(void);
+
+/* ------------------------------------------------------------------------
+ * Cameras (host structs).  World-to-camera p_cam = R p_world + t, R
+ * row-major, OpenCV axes (x right, y down, z forward).  Pixel (i, j) is
+ * sampled at (i + 0.5, j + 0.5).  Tiles are 16 x 16, ceil(W/16) x ceil(H/16).
+ * z_near / z_far cull a Gaussian whose camera depth is <= z_near or > z_far;
+ * the same planes bound the block frustum test of tide_cull_blocks.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  double R[9];
+  double t[3];
+  double fx, fy, cx, cy;
+  int32_t width, height;
+  double z_near, z_far;
+} tide_camera;
+
+/* ------------------------------------------------------------------------
+ * Resident parameter pool (Sec. 3.3, Eq. block_def: Block(k) = rows
+ * [kB, (k+1)B) of the table).  GPU memory is a set of block slots, stored
+ * block-SoA: X[slot][col][row], so every column of a block is contiguous.
+ *   params, exp_avg, exp_avg_sq  device, [n_slots][59][block_rows], dtype
+ *   step        device u32 [n_slots][block_rows]: Adam steps taken per row
+ *   slot_block  device i32 [n_slots]: global block id held by the slot, -1 free
+ *   slot_rows   device i32 [n_slots]: valid rows in the slot (the last block
+ *               of the table may be partial)
+ *   order       device i32 [n_order]: slots to render, in ascending block id.
+ *               Processing index pidx = k * block_rows + row for order[k];
+ *               global id gid = slot_block[order[k]] * block_rows + row, so
+ *               pidx order is global-id order wherever the blocks sit.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  void* params;
+  void* exp_avg;
+  void* exp_avg_sq;
+  uint32_t* step;
+  const int32_t* slot_block;
+  const int32_t* slot_rows;
+  const int32_t* order;
+  int32_t n_slots;
+  int32_t block_rows;
+  int32_t n_order;
+  int32_t dtype;
+} tide_pool;
+
+/* ------------------------------------------------------------------------
+ * Per (camera, Gaussian) projection records written by tide_preprocess;
+ * all device, caller allocated, n_pidx = n_order * block_rows.
+ *   rec     [n_cams][n_pidx][12] dtype: u, v, conic A, B, C, opacity,
+ *           r, g, b, depth, footprint radius (px), 0
+ *           (valid where tiles_touched > 0)
+ *   depth   f32 [n_cams][n_pidx] camera-space depth (the sort key)
+ *   rect    u32 [n_cams][n_pidx][2]: x0 | y0 << 16, x1 | y1 << 16 (tiles,
+ *           half-open)
+ *   tiles_touched u32 [n_cams][n_pidx]: 0 = culled for that camera
+ *   active  u32 [n_pidx]: 1 if kept by any camera of the batch
+ *   act_idx u32 [n_pidx]: exclusive prefix sum of active (compact row index)
+ *   n_active device u32 [1]: number of active rows
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  void* rec;
+  float* depth;
+  uint32_t* rect;
+  uint32_t* tiles_touched;
+  uint32_t* active;
+  uint32_t* act_idx;
+  uint32_t* n_active;
+  int64_t n_pidx;
+  int32_t n_cams;
+  int32_t dtype;
+} tide_proj;
+
+/* Bytes of device workspace tide_preprocess needs (for the active scan). */
+size_t tide_preprocess_ws_bytes(int64_t n_pidx);
+
+/* Projection, culling, EWA footprint, tile rectangle and SH-degree-3 colour
+ * of every resident Gaussian for each of the n_cams cameras (standard 3DGS
+ * preprocessing, Sec. 3.3 Level 2), plus the active set I_t (Sec. 2: Gaussians
+ * kept by some camera of the batch) and its compaction in pidx order.
+ * cams: host array of n_cams (1..TIDE_MAX_CAMS). Asynchronous. */
+tide_status tide_preprocess(const tide_pool* pool, const tide_camera* cams, int32_t n_cams,
+                            tide_proj* out, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Tile binning and depth sort.  Every kept (camera, Gaussian) pair is
+ * duplicated once per covered tile and the instances are ordered by
+ * (camera, tile, depth, pidx): first the visible pairs are sorted stably by
+ * depth (LSD radix, 8-bit digits), then the instances, emitted in that depth
+ * order, are sorted stably by global tile id (camera * tiles + tile).
+ * Results live in the caller's workspace; tide_bins points into it.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  /* outputs (device pointers into ws) */
+  const uint32_t* vis_rec;     /* [n_vis] record index c*n_pidx+pidx, depth order */
+  const uint32_t* inst_off;    /* [n_vis+1] first instance of each vis entry */
+  const uint32_t* inst_e;      /* [n_inst] emission index of the j-th sorted instance */
+  const uint32_t* inst_rec;    /* [n_inst] record index of emission index e */
+  const uint32_t* ranges;      /* [n_cams*n_tiles][2] sorted-instance [start, end) */
+  int64_t n_vis;
+  int64_t n_inst;
+  int32_t n_cams;
+  int32_t tiles_x, tiles_y;
+  int64_t n_pidx;
+  /* set on TIDE_ECAPACITY: the workspace bytes this call needs */
+  size_t ws_required;
+} tide_bins;
+
+/* Bytes of workspace for given sizes (n_inst_cap = instance capacity). */
+size_t tide_bin_sort_ws_bytes(int32_t n_cams, int64_t n_pidx, int32_t tiles_x, int32_t tiles_y,
+                              int64_t n_inst_cap);
+
+/* Blocks once: it reads the visible-pair and instance counts back to the
+ * host.  On TIDE_ECAPACITY, out->ws_required holds the size to retry with
+ * (the projection records are unchanged and may be reused). */
+tide_status tide_bin_sort(const tide_proj* proj, int32_t tiles_x, int32_t tiles_y, void* ws,
+                          size_t ws_bytes, tide_bins* out, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Front-to-back alpha compositing per 16x16 tile (standard 3DGS forward;
+ * Sec. 3.2 Stage 3).  For each pixel: alpha = min(0.99, opacity * exp(power)),
+ * entries with power > 0 or alpha < 1/255 are skipped, and the walk stops
+ * before an entry that would take the transmittance below 1e-4.
+ *   image   device dtype [n_cams][3][H][W]; out = colour + T * bg
+ *   t_final device dtype [n_cams][H][W]
+ *   last    device u32 [n_cams][H][W]: 1 + position (in the tile list) of
+ *           the last contributing entry, 0 if none
+ *   visits  device u64 [n_cams]: entries evaluated, summed over pixels
+ *           (the entry that stops a pixel is counted); accumulated, so
+ *           zero it first.
+ * bg: host float[3]. All cameras share W = width, H = height. */
+typedef struct {
+  void* image;
+  void* t_final;
+  uint32_t* last;
+  unsigned long long* visits;
+  int32_t width, height;
+} tide_frame;
+
+tide_status tide_render_fwd(const tide_proj* proj, const tide_bins* bins, const float* bg,
+                            tide_frame* frame, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Photometric loss 0.8 L1 + 0.2 (1 - SSIM) averaged over views (the paper's
+ * per-view photometric loss f_i, Appendix A; weights and SSIM as standard in
+ * 3DGS: 11x11 Gaussian window, sigma 1.5, zero padding, C1 = 1e-4,
+ * C2 = 9e-4).
+ *   image, target  device dtype [n_views][3][H][W]
+ *   d_loss         device double [1] (written)
+ *   d_dimage       device dtype [n_views][3][H][W]: dL/dimage (written)
+ * Needs tide_loss_ws_bytes() of workspace. */
+size_t tide_loss_ws_bytes(int32_t n_views, int32_t height, int32_t width, int32_t dtype);
+tide_status tide_loss(const void* image, const void* target, int32_t n_views, int32_t height,
+                      int32_t width, int32_t dtype, double* d_loss, void* d_dimage, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Backward of the rasterizer: the compositing adjoint per tile (reverse walk
+ * from each pixel's last contributor), a fixed-order sum of per-instance
+ * 2-D gradients per (camera, Gaussian), then the adjoint of projection,
+ * EWA, activations and SH, summed over cameras in order.  Deterministic:
+ * no floating-point atomics.
+ *   d_dimage  device dtype [n_cams][3][H][W]
+ *   grad      device dtype [59][grad_ld]: column-major compact gradient,
+ *             row a = the a-th active pidx (act_idx); grad_ld >= n_pidx
+ *   ws        tide_render_bwd_ws_bytes(bins) bytes
+ * ---------------------------------------------------------------------- */
+size_t tide_render_bwd_ws_bytes(const tide_bins* bins, int32_t dtype);
+tide_status tide_render_bwd(const tide_pool* pool, const tide_camera* cams, int32_t n_cams,
+                            const tide_proj* proj, const tide_bins* bins, const tide_frame* frame,
+                            const float* bg, const void* d_dimage, void* grad, int64_t grad_ld,
+                            void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Masked (sparse) Adam on the active rows only (Appendix A, masked update
+ * equation): for each active row, step += 1, then per column j
+ *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
+ *   p -= lr[j] * (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
+ * Inactive rows are not touched.  Each updated block is marked dirty
+ * (Sec. 3.5, "GPU-side training on the resident set") and its bounding
+ * sphere radius is raised to cover the updated rows (Sec. 3.3: bounds are
+ * refreshed conservatively as centres move):
+ *   r_k = max(r_k, |mu_i - c_k| + 3 kappa max(exp(log-scale_i))).
+ *   spheres  device f32 [n_blocks][4] (cx, cy, cz, r), indexed by global block
+ *   dirty    device u8 [n_blocks]
+ * Either may be NULL to skip that bookkeeping.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  float lr[TIDE_D];
+  float beta1, beta2, eps;
+  float kappa;
+} tide_adam_cfg;
+
+tide_status tide_adam_sparse(tide_pool* pool, const tide_proj* proj, const void* grad,
+                             int64_t grad_ld, const tide_adam_cfg* cfg, float* spheres,
+                             uint8_t* dirty, int64_t n_blocks, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TIDE_H */

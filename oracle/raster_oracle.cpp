@@ -252,7 +252,9 @@ void project_one(const double* th, const Cam& c, Fwd& f) {
   const double lam1 = m + std::sqrt(std::max(0.0, m * m - f.det));
   const double rr = 3.0 * std::sqrt(lam1);
   f.rr = rr;
-  f.r = (int)std::ceil(rr);
+  // radius cap of 2^21 px (a footprint that large covers any image; it keeps
+  // 16 t +- r exactly representable in single precision on the GPU side)
+  f.r = (int)std::ceil(std::min(rr, 2097152.0));
   f.margin = std::min(f.margin, rel_int_dist(rr) / std::max(rr, 1.0));
   tile_rect(f.u, f.v, f.r, c.tx(), c.ty(), f.rect);
   f.margin = std::min(f.margin, rect_margin(f.u, f.v, f.r));

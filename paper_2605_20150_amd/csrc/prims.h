@@ -1,0 +1,129 @@
+// Device-wide exclusive scan and stable LSD radix sort for wave64 (gfx950).
+//
+// Scan: reduce-then-scan over tiles of 4096 elements (256 lanes x 16
+// consecutive items), block partials scanned by one workgroup.
+// Radix sort: 8-bit digits; per tile a 256-bin LDS histogram, a bin-major
+// scan of the per-tile histograms, then a stable scatter whose in-tile ranks
+// come from ballot-based peer masks (a wave sees 64 consecutive keys per
+// round, so rank = keys of the same digit in earlier waves + earlier rounds +
+// lower lanes).  Equal keys keep their input order, which is what makes the
+// (tile, depth, pidx) order of the binning total.
+#pragma once
+
+#include "common.h"
+
+namespace tide {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;  // 4096
+
+constexpr int kSortThreads = 256;
+constexpr int kSortWaves = kSortThreads / kWave;       // 4
+constexpr int kSortRounds = 16;
+constexpr int kSortTile = kSortThreads * kSortRounds;  // 4096
+
+// ------------------------------------------------------------------ scan
+// Input functors: value of element i as u32.
+struct ArrayIn {
+  const uint32_t* a;
+  __device__ uint32_t operator()(int64_t i) const { return a[i]; }
+};
+struct NonzeroIn {
+  const uint32_t* a;
+  __device__ uint32_t operator()(int64_t i) const { return a[i] != 0u ? 1u : 0u; }
+};
+struct GatherIn {  // a[idx[i]]
+  const uint32_t* a;
+  const uint32_t* idx;
+  __device__ uint32_t operator()(int64_t i) const { return a[idx[i]]; }
+};
+
+template <typename In>
+__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(In in, int64_t n,
+                                                              unsigned long long* partial) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  unsigned long long s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k)
+    if (base + k < n) s += in(base + k);
+  s = wave_sum(s);
+  __shared__ unsigned long long ws[kScanThreads / kWave];
+  if (__lane_id() == 0) ws[threadIdx.x / kWave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int w = 0; w < kScanThreads / kWave; ++w) t += ws[w];
+    partial[blockIdx.x] = t;
+  }
+}
+
+// One workgroup scans partial[0..nb) in place (exclusive) and writes the total.
+__global__ void __launch_bounds__(1024) k_scan_partials(unsigned long long* partial, int64_t nb,
+                                                        unsigned long long* total);
+
+template <typename In>
+__global__ void __launch_bounds__(kScanThreads) k_scan_down(In in, int64_t n,
+                                                            const unsigned long long* partial,
+                                                            uint32_t* out) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = (base + k < n) ? in(base + k) : 0u;
+    s += v[k];
+  }
+  // exclusive scan of the 256 thread sums
+  const uint32_t inc = wave_incl_scan(s);
+  __shared__ uint32_t wtot[kScanThreads / kWave];
+  const int w = threadIdx.x / kWave;
+  if (__lane_id() == kWave - 1) wtot[w] = inc;
+  __syncthreads();
+  uint32_t wpre = 0;
+  for (int q = 0; q < w; ++q) wpre += wtot[q];
+  uint32_t run = (uint32_t)partial[blockIdx.x] + wpre + inc - s;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) out[base + k] = run;
+    run += v[k];
+  }
+}
+
+// Exclusive scan of in(0..n) into out; total (u64, device) receives the sum.
+// partial needs ceil(n/4096) u64 entries.
+template <typename In>
+inline void scan_exclusive(In in, int64_t n, uint32_t* out, unsigned long long* partial,
+                           unsigned long long* total, hipStream_t st) {
+  const int64_t nb = ceil_div(n > 0 ? n : 1, kScanTile);
+  hipLaunchKernelGGL(k_scan_reduce<In>, dim3((uint32_t)nb), dim3(kScanThreads), 0, st, in, n, partial);
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, partial, nb, total);
+  hipLaunchKernelGGL(k_scan_down<In>, dim3((uint32_t)nb), dim3(kScanThreads), 0, st, in, n,
+                     (const unsigned long long*)partial, out);
+}
+
+inline size_t scan_partial_count(int64_t n) { return (size_t)ceil_div(n > 0 ? n : 1, kScanTile); }
+
+// ------------------------------------------------------------- radix sort
+__global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint32_t* keys, int64_t n, int shift,
+                                                             uint32_t* ghist, int64_t nb);
+__global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint32_t* keys_in,
+                                                                const uint32_t* vals_in, int64_t n,
+                                                                int shift, const uint32_t* gofs,
+                                                                int64_t nb, uint32_t* keys_out,
+                                                                uint32_t* vals_out);
+
+inline size_t radix_hist_count(int64_t n) { return 256 * (size_t)ceil_div(n > 0 ? n : 1, kSortTile); }
+
+// Sorts (keys, vals) stably by bits [0, bits) of the key, 8 bits per pass.
+// Input in (ka, va); with identity_vals the input values are taken to be
+// the input indices and va is only used as storage.  Buffers (ka, va) and
+// (kb, vb) ping-pong; the sorted result pointers are returned through
+// *keys_res / *vals_res.  hist needs radix_hist_count(n) u32, partial
+// scan_partial_count(radix_hist_count(n)) u64, total one u64.
+void radix_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int64_t n, int bits,
+                      bool identity_vals, uint32_t* hist, unsigned long long* partial,
+                      unsigned long long* total, hipStream_t st, uint32_t** keys_res,
+                      uint32_t** vals_res);
+
+}  // namespace tide

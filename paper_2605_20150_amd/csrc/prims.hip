@@ -1,0 +1,129 @@
+// Non-template parts of the scan and radix sort (see prims.h).
+#include "prims.h"
+
+namespace tide {
+
+__global__ void __launch_bounds__(1024) k_scan_partials(unsigned long long* partial, int64_t nb,
+                                                        unsigned long long* total) {
+  __shared__ unsigned long long wtot[1024 / kWave];
+  __shared__ unsigned long long carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  const int lane = __lane_id(), w = threadIdx.x / kWave;
+  for (int64_t b0 = 0; b0 < nb; b0 += 1024) {
+    const int64_t i = b0 + threadIdx.x;
+    const unsigned long long x = i < nb ? partial[i] : 0ull;
+    unsigned long long inc = x;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const unsigned long long y = __shfl_up(inc, off, kWave);
+      if (lane >= off) inc += y;
+    }
+    if (lane == kWave - 1) wtot[w] = inc;
+    __syncthreads();
+    unsigned long long pre = carry;
+    for (int q = 0; q < w; ++q) pre += wtot[q];
+    if (i < nb) partial[i] = pre + inc - x;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry = pre + inc;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint32_t* keys, int64_t n, int shift,
+                                                             uint32_t* ghist, int64_t nb) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+#pragma unroll 4
+  for (int r = 0; r < kSortRounds; ++r) {
+    const int64_t i = base + (int64_t)r * kSortThreads + threadIdx.x;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  ghist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint32_t* keys_in,
+                                                                const uint32_t* vals_in, int64_t n,
+                                                                int shift, const uint32_t* gofs,
+                                                                int64_t nb, uint32_t* keys_out,
+                                                                uint32_t* vals_out) {
+  __shared__ uint32_t wcnt[kSortWaves][256];
+  __shared__ uint32_t gbase[256];
+  for (int k = threadIdx.x; k < kSortWaves * 256; k += kSortThreads) (&wcnt[0][0])[k] = 0;
+  gbase[threadIdx.x] = gofs[(int64_t)threadIdx.x * nb + blockIdx.x];
+  __syncthreads();
+  const int w = threadIdx.x / kWave, lane = __lane_id();
+  const uint64_t lt = lanemask_lt();
+  const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)w * (kWave * kSortRounds);
+  uint32_t key[kSortRounds], val[kSortRounds], rank[kSortRounds];
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    const int64_t i = base + (int64_t)r * kWave + lane;
+    const bool ok = i < n;
+    key[r] = ok ? keys_in[i] : 0u;
+    val[r] = ok ? (vals_in ? vals_in[i] : (uint32_t)i) : 0u;
+    const uint32_t d = (key[r] >> shift) & 255u;
+    uint64_t peers = __ballot(ok);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t m = __ballot(bit);
+      peers &= bit ? m : ~m;
+    }
+    uint32_t r0 = 0;
+    if (ok) r0 = wcnt[w][d];
+    rank[r] = r0 + (uint32_t)__popcll(peers & lt);
+    // the lowest lane of each digit group advances the wave's counter
+    if (ok && (peers & lt) == 0) wcnt[w][d] = r0 + (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  {
+    const int d = threadIdx.x;
+    uint32_t run = 0;
+#pragma unroll
+    for (int q = 0; q < kSortWaves; ++q) {
+      const uint32_t c = wcnt[q][d];
+      wcnt[q][d] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    const int64_t i = base + (int64_t)r * kWave + lane;
+    if (i < n) {
+      const uint32_t d = (key[r] >> shift) & 255u;
+      const uint32_t pos = gbase[d] + wcnt[w][d] + rank[r];
+      keys_out[pos] = key[r];
+      vals_out[pos] = val[r];
+    }
+  }
+}
+
+void radix_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int64_t n, int bits,
+                      bool identity_vals, uint32_t* hist, unsigned long long* partial,
+                      unsigned long long* total, hipStream_t st, uint32_t** keys_res,
+                      uint32_t** vals_res) {
+  uint32_t *ki = ka, *vi = va, *ko = kb, *vo = vb;
+  bool ident = identity_vals;
+  const int64_t nb = ceil_div(n > 0 ? n : 1, kSortTile);
+  if (n > 0) {
+    for (int shift = 0; shift < bits; shift += 8) {
+      hipLaunchKernelGGL(k_radix_hist, dim3((uint32_t)nb), dim3(kSortThreads), 0, st, ki, n, shift, hist, nb);
+      scan_exclusive(ArrayIn{hist}, 256 * nb, hist, partial, total, st);
+      hipLaunchKernelGGL(k_radix_scatter, dim3((uint32_t)nb), dim3(kSortThreads), 0, st, ki,
+                         ident ? nullptr : vi, n, shift, hist, nb, ko, vo);
+      ident = false;
+      uint32_t* t = ki; ki = ko; ko = t;
+      t = vi; vi = vo; vo = t;
+    }
+  }
+  *keys_res = ki;
+  *vals_res = vi;
+}
+
+}  // namespace tide

@@ -1,0 +1,442 @@
+// Backward half of the rasterizer: compositing adjoint per tile, per-pair
+// reduction of the per-instance 2-D gradients in a fixed order, and the
+// adjoint of projection / EWA / activations / SH.  No floating-point atomics:
+// every sum has one fixed order, so two runs give identical bits.
+#include "prims.h"
+#include "raster.h"
+
+namespace tide {
+
+constexpr int kG2 = 9;  // du, dv, dA, dB, dC, dopacity, dr, dg, db
+
+// ----------------------------------------------------- compositing adjoint
+// Same lane/pixel layout as the forward.  Each pixel walks back from its
+// last contributor, recovering T_i = T_{i+1} / (1 - alpha_i) and the
+// normalised colour behind the entry (r_{i-1} = alpha_i c_i + (1-alpha_i) r_i,
+// starting from the background).  The four pixels of a lane are summed in
+// registers and the wave is reduced once per entry; entries that no pixel of
+// the tile reaches get zero partials.
+template <typename T>
+__global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ ranges,
+                                                   const uint32_t* __restrict__ inst_e,
+                                                   const uint32_t* __restrict__ inst_rec, const T* __restrict__ rec,
+                                                   int32_t Tx, int32_t Ty, int32_t W, int32_t H, T bg0, T bg1,
+                                                   T bg2, const T* __restrict__ tfin,
+                                                   const uint32_t* __restrict__ last_in,
+                                                   const T* __restrict__ dimg, T* __restrict__ partial) {
+  const int nt = Tx * Ty;
+  const int g = blockIdx.x;
+  const int c = g / nt, t = g - c * nt;
+  const int tx = t % Tx, ty = t / Tx;
+  const int lane = threadIdx.x;
+  const int px = tx * kTile + (lane & 15);
+  const int py0 = ty * kTile + (lane >> 4);
+  const T fxp = (T)px + (T)0.5;
+  const int64_t HW = (int64_t)H * W;
+  T fyp[4], Tr[4], g0[4], g1[4], g2[4], rb0[4], rb1[4], rb2[4];
+  uint32_t lst[4];
+  uint32_t maxl = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int py = py0 + 4 * q;
+    fyp[q] = (T)py + (T)0.5;
+    rb0[q] = bg0; rb1[q] = bg1; rb2[q] = bg2;
+    if (px < W && py < H) {
+      const int64_t p = (int64_t)py * W + px;
+      Tr[q] = tfin[(int64_t)c * HW + p];
+      lst[q] = last_in[(int64_t)c * HW + p];
+      g0[q] = dimg[((int64_t)c * 3 + 0) * HW + p];
+      g1[q] = dimg[((int64_t)c * 3 + 1) * HW + p];
+      g2[q] = dimg[((int64_t)c * 3 + 2) * HW + p];
+    } else {
+      Tr[q] = 1; lst[q] = 0; g0[q] = g1[q] = g2[q] = 0;
+    }
+    maxl = lst[q] > maxl ? lst[q] : maxl;
+  }
+  // wave max of the last contributors
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const uint32_t o = __shfl_xor(maxl, off, kWave);
+    maxl = o > maxl ? o : maxl;
+  }
+  const uint32_t start = ranges[2 * g], end = ranges[2 * g + 1];
+  // entries beyond every pixel's last contributor receive nothing
+  for (uint32_t j = start + maxl + lane; j < end; j += 64) {
+    T* P = partial + (int64_t)inst_e[j] * kG2;
+#pragma unroll
+    for (int m = 0; m < kG2; ++m) P[m] = 0;
+  }
+  __shared__ T s_u[64], s_v[64], s_A[64], s_B[64], s_C[64], s_o[64], s_r[64], s_g[64], s_b[64];
+  __shared__ uint32_t s_e[64];
+  for (int32_t hi = (int32_t)maxl; hi > 0; hi -= 64) {
+    const int32_t lo = hi - 64 > 0 ? hi - 64 : 0;
+    const int32_t n = hi - lo;
+    if (lane < n) {
+      const uint32_t e = inst_e[start + lo + lane];
+      const T* q = rec + (int64_t)inst_rec[e] * kRec;
+      s_e[lane] = e;
+      s_u[lane] = q[0]; s_v[lane] = q[1];
+      s_A[lane] = (T)-0.5 * q[2]; s_B[lane] = -q[3]; s_C[lane] = (T)-0.5 * q[4];
+      s_o[lane] = q[5]; s_r[lane] = q[6]; s_g[lane] = q[7]; s_b[lane] = q[8];
+    }
+    __syncthreads();
+    for (int k = n - 1; k >= 0; --k) {
+      const uint32_t pos = (uint32_t)(lo + k);
+      const T u = s_u[k], v = s_v[k], Ah = s_A[k], Bh = s_B[k], Ch = s_C[k], op = s_o[k];
+      const T cr = s_r[k], cg = s_g[k], cb = s_b[k];
+      const T dx = fxp - u;
+      T a_u = 0, a_v = 0, a_A = 0, a_B = 0, a_C = 0, a_o = 0, a_r = 0, a_g = 0, a_b = 0;
+      bool hit = false;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (pos >= lst[q]) continue;
+        const T dy = fyp[q] - v;
+        T G, araw, alpha;
+        if (!entry_alpha<T>(Ah, Bh, Ch, op, dx, dy, G, araw, alpha)) continue;
+        hit = true;
+        Tr[q] = Tr[q] / ((T)1 - alpha);
+        const T w = alpha * Tr[q];
+        a_r += w * g0[q]; a_g += w * g1[q]; a_b += w * g2[q];
+        const T dal = Tr[q] * ((cr - rb0[q]) * g0[q] + (cg - rb1[q]) * g1[q] + (cb - rb2[q]) * g2[q]);
+        const T om = (T)1 - alpha;
+        rb0[q] = alpha * cr + om * rb0[q];
+        rb1[q] = alpha * cg + om * rb1[q];
+        rb2[q] = alpha * cb + om * rb2[q];
+        if (araw < (T)0.99) {
+          a_o += dal * G;
+          const T dp = dal * araw;
+          // A = -2 Ah, B = -Bh, C = -2 Ch
+          a_u += dp * ((T)-2 * Ah * dx - Bh * dy);
+          a_v += dp * (-Bh * dx + (T)-2 * Ch * dy);
+          a_A += dp * ((T)-0.5 * dx * dx);
+          a_B += dp * (-dx * dy);
+          a_C += dp * ((T)-0.5 * dy * dy);
+        }
+      }
+      T* P = partial + (int64_t)s_e[k] * kG2;
+      if (__ballot(hit) == 0) {
+        if (lane == 0) {
+#pragma unroll
+          for (int m = 0; m < kG2; ++m) P[m] = 0;
+        }
+        continue;
+      }
+      a_u = wave_sum(a_u); a_v = wave_sum(a_v); a_A = wave_sum(a_A); a_B = wave_sum(a_B);
+      a_C = wave_sum(a_C); a_o = wave_sum(a_o); a_r = wave_sum(a_r); a_g = wave_sum(a_g);
+      a_b = wave_sum(a_b);
+      if (lane == 0) {
+        P[0] = a_u; P[1] = a_v; P[2] = a_A; P[3] = a_B; P[4] = a_C;
+        P[5] = a_o; P[6] = a_r; P[7] = a_g; P[8] = a_b;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------- per-pair reduction (fixed order)
+// Thread s sums the contiguous partials of the s-th depth-ordered visible
+// pair (its tiles in row-major order) and stores them SoA by record index.
+template <typename T>
+__global__ void k_reduce_pairs(const uint32_t* __restrict__ vis_rec, const uint32_t* __restrict__ inst_off,
+                               int64_t n_vis, int64_t n_rec, const T* __restrict__ partial, T* __restrict__ g2d) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_vis) return;
+  const uint32_t r = vis_rec[s];
+  const uint32_t e0 = inst_off[s], e1 = inst_off[s + 1];
+  T acc[kG2];
+#pragma unroll
+  for (int m = 0; m < kG2; ++m) acc[m] = 0;
+  for (uint32_t e = e0; e < e1; ++e) {
+    const T* P = partial + (int64_t)e * kG2;
+#pragma unroll
+    for (int m = 0; m < kG2; ++m) acc[m] += P[m];
+  }
+#pragma unroll
+  for (int m = 0; m < kG2; ++m) g2d[(int64_t)m * n_rec + r] = acc[m];
+}
+
+// --------------------------------------------------- preprocess adjoint
+// Thread per processing index; only active rows work.  Recomputes the
+// forward quantities of each camera that kept the Gaussian, chains the 2-D
+// gradients back to mean, log-scale, quaternion, opacity logit and SH, sums
+// the cameras in index order and writes the compact gradient row.
+template <typename T>
+__global__ void __launch_bounds__(128) k_adjoint(const T* __restrict__ params, const int32_t* __restrict__ order,
+                                                 int32_t B, int64_t n_pidx, CamSet<T> cs,
+                                                 const uint32_t* __restrict__ tt, const uint32_t* __restrict__ active,
+                                                 const uint32_t* __restrict__ act_idx, const T* __restrict__ g2d,
+                                                 T* __restrict__ grad, int64_t ld) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_pidx || !active[i]) return;
+  const int64_t k = i / B;
+  const int32_t row = (int32_t)(i - k * B);
+  const int32_t slot = order[k];
+  const T* P = params + (int64_t)slot * kD * B + row;
+  const int64_t nrec = (int64_t)cs.n * n_pidx;
+  const T mu0 = P[0], mu1 = P[B], mu2 = P[2 * (int64_t)B];
+  const T s0 = Mth<T>::exp(P[3 * (int64_t)B]), s1 = Mth<T>::exp(P[4 * (int64_t)B]),
+          s2 = Mth<T>::exp(P[5 * (int64_t)B]);
+  const T qw0 = P[6 * (int64_t)B], qx0 = P[7 * (int64_t)B], qy0 = P[8 * (int64_t)B], qz0 = P[9 * (int64_t)B];
+  const T qn = Mth<T>::sqrt(qw0 * qw0 + qx0 * qx0 + qy0 * qy0 + qz0 * qz0);
+  const T iq = (T)1 / qn;
+  const T qw = qw0 * iq, qx = qx0 * iq, qy = qy0 * iq, qz = qz0 * iq;
+  const T op = (T)1 / ((T)1 + Mth<T>::exp(-P[10 * (int64_t)B]));
+  const T Rq[9] = {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy),
+                   2 * (qx * qy + qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qw * qx),
+                   2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)};
+  const T sv[3] = {s0, s1, s2};
+  T M[9];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) M[3 * a + b] = Rq[3 * a + b] * sv[b];
+  T Sg[9];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) Sg[3 * a + b] = M[3 * a] * M[3 * b] + M[3 * a + 1] * M[3 * b + 1] + M[3 * a + 2] * M[3 * b + 2];
+
+  T gsh[48];
+#pragma unroll
+  for (int m = 0; m < 48; ++m) gsh[m] = 0;
+  T dmu0 = 0, dmu1 = 0, dmu2 = 0, dlogit = 0;
+  T dSig[9];
+#pragma unroll
+  for (int m = 0; m < 9; ++m) dSig[m] = 0;
+
+#pragma unroll 1
+  for (int c = 0; c < cs.n; ++c) {
+    const int64_t o = (int64_t)c * n_pidx + i;
+    if (tt[o] == 0) continue;
+    const DevCam<T>& cm = cs.c[c];
+    const T gu = g2d[0 * nrec + o], gv = g2d[1 * nrec + o], gA = g2d[2 * nrec + o], gB = g2d[3 * nrec + o],
+            gC = g2d[4 * nrec + o], gop = g2d[5 * nrec + o];
+    const T gcol[3] = {g2d[6 * nrec + o], g2d[7 * nrec + o], g2d[8 * nrec + o]};
+    // ---- colour
+    T dx = mu0 - cm.pos[0], dy = mu1 - cm.pos[1], dz = mu2 - cm.pos[2];
+    const T len = Mth<T>::sqrt(dx * dx + dy * dy + dz * dz);
+    const T il = (T)1 / len;
+    dx *= il; dy *= il; dz *= il;
+    T Y[16];
+    sh_eval<T>(cs.sh, dx, dy, dz, Y);
+    T graw[3];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      T raw = (T)0.5;
+#pragma unroll
+      for (int m = 0; m < 16; ++m) raw += Y[m] * P[(int64_t)(11 + 3 * m + ch) * B];
+      graw[ch] = raw < 0 ? (T)0 : gcol[ch];
+    }
+    T wk[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      gsh[3 * m] += Y[m] * graw[0];
+      gsh[3 * m + 1] += Y[m] * graw[1];
+      gsh[3 * m + 2] += Y[m] * graw[2];
+      wk[m] = P[(int64_t)(11 + 3 * m) * B] * graw[0] + P[(int64_t)(12 + 3 * m) * B] * graw[1] +
+              P[(int64_t)(13 + 3 * m) * B] * graw[2];
+    }
+    {
+      const ShK<T>& K = cs.sh;
+      const T x = dx, y = dy, z = dz, xx = x * x, yy = y * y, zz = z * z;
+      T gx = 0, gy = 0, gz = 0;
+      gy += -K.c1 * wk[1];
+      gz += K.c1 * wk[2];
+      gx += -K.c1 * wk[3];
+      gx += K.c2a * y * wk[4]; gy += K.c2a * x * wk[4];
+      gy += -K.c2a * z * wk[5]; gz += -K.c2a * y * wk[5];
+      gx += -2 * K.c2b * x * wk[6]; gy += -2 * K.c2b * y * wk[6]; gz += 4 * K.c2b * z * wk[6];
+      gx += -K.c2a * z * wk[7]; gz += -K.c2a * x * wk[7];
+      gx += 2 * K.c2c * x * wk[8]; gy += -2 * K.c2c * y * wk[8];
+      gx += -K.c3a * 6 * x * y * wk[9]; gy += -K.c3a * (3 * xx - 3 * yy) * wk[9];
+      gx += K.c3b * y * z * wk[10]; gy += K.c3b * x * z * wk[10]; gz += K.c3b * x * y * wk[10];
+      gx += 2 * K.c3c * x * y * wk[11]; gy += -K.c3c * (4 * zz - xx - 3 * yy) * wk[11];
+      gz += -8 * K.c3c * y * z * wk[11];
+      gx += -6 * K.c3d * x * z * wk[12]; gy += -6 * K.c3d * y * z * wk[12];
+      gz += K.c3d * (6 * zz - 3 * xx - 3 * yy) * wk[12];
+      gx += -K.c3c * (4 * zz - 3 * xx - yy) * wk[13]; gy += 2 * K.c3c * x * y * wk[13];
+      gz += -8 * K.c3c * x * z * wk[13];
+      gx += 2 * K.c3e * x * z * wk[14]; gy += -2 * K.c3e * y * z * wk[14]; gz += K.c3e * (xx - yy) * wk[14];
+      gx += -K.c3a * (3 * xx - 3 * yy) * wk[15]; gy += 6 * K.c3a * x * y * wk[15];
+      const T dd = gx * x + gy * y + gz * z;
+      dmu0 += (gx - dd * x) * il;
+      dmu1 += (gy - dd * y) * il;
+      dmu2 += (gz - dd * z) * il;
+    }
+    // ---- opacity
+    dlogit += gop * op * ((T)1 - op);
+    // ---- geometry: recompute p, J, T, Sigma', conic
+    const T px = cm.R[0] * mu0 + cm.R[1] * mu1 + cm.R[2] * mu2 + cm.t[0];
+    const T py = cm.R[3] * mu0 + cm.R[4] * mu1 + cm.R[5] * mu2 + cm.t[1];
+    const T pz = cm.R[6] * mu0 + cm.R[7] * mu1 + cm.R[8] * mu2 + cm.t[2];
+    const T iz = (T)1 / pz;
+    const T txz = px * iz, tyz = py * iz;
+    const bool clx = txz < -cm.limx || txz > cm.limx;
+    const bool cly = tyz < -cm.limy || tyz > cm.limy;
+    const T xi = txz < -cm.limx ? -cm.limx : (txz > cm.limx ? cm.limx : txz);
+    const T eta = tyz < -cm.limy ? -cm.limy : (tyz > cm.limy ? cm.limy : tyz);
+    const T J00 = cm.fx * iz, J02 = -cm.fx * xi * iz, J11 = cm.fy * iz, J12 = -cm.fy * eta * iz;
+    T Tm[6];
+    Tm[0] = J00 * cm.R[0] + J02 * cm.R[6]; Tm[1] = J00 * cm.R[1] + J02 * cm.R[7]; Tm[2] = J00 * cm.R[2] + J02 * cm.R[8];
+    Tm[3] = J11 * cm.R[3] + J12 * cm.R[6]; Tm[4] = J11 * cm.R[4] + J12 * cm.R[7]; Tm[5] = J11 * cm.R[5] + J12 * cm.R[8];
+    T TS[6];  // T Sigma (2x3)
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+        TS[3 * a + b] = Tm[3 * a] * Sg[b] + Tm[3 * a + 1] * Sg[3 + b] + Tm[3 * a + 2] * Sg[6 + b];
+    const T c00 = TS[0] * Tm[0] + TS[1] * Tm[1] + TS[2] * Tm[2] + (T)0.3;
+    const T c01 = TS[0] * Tm[3] + TS[1] * Tm[4] + TS[2] * Tm[5];
+    const T c11 = TS[3] * Tm[3] + TS[4] * Tm[4] + TS[5] * Tm[5] + (T)0.3;
+    const T idet = (T)1 / (c00 * c11 - c01 * c01);
+    const T A = c11 * idet, Bc = -c01 * idet, C = c00 * idet;
+    // dL/dSigma' = -Q Gq Q, Q = [[A, B], [B, C]], Gq = [[gA, gB/2], [gB/2, gC]]
+    const T hB = (T)0.5 * gB;
+    const T q00 = A * gA + Bc * hB, q01 = A * hB + Bc * gC, q10 = Bc * gA + C * hB, q11 = Bc * hB + C * gC;
+    const T d00 = -(q00 * A + q01 * Bc), d01 = -(q00 * Bc + q01 * C), d11 = -(q10 * Bc + q11 * C);
+    const T dS[4] = {d00, d01, d01, d11};
+    // dL/dSigma += T^T dS T
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+        dSig[3 * a + b] += Tm[a] * (dS[0] * Tm[b] + dS[1] * Tm[3 + b]) + Tm[3 + a] * (dS[2] * Tm[b] + dS[3] * Tm[3 + b]);
+    // dL/dT = 2 dS T Sigma = 2 dS TS
+    T dT[6];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      dT[b] = 2 * (dS[0] * TS[b] + dS[1] * TS[3 + b]);
+      dT[3 + b] = 2 * (dS[2] * TS[b] + dS[3] * TS[3 + b]);
+    }
+    // dL/dJ = dT W^T (entries 00, 02, 11, 12)
+    const T dJ00 = dT[0] * cm.R[0] + dT[1] * cm.R[1] + dT[2] * cm.R[2];
+    const T dJ02 = dT[0] * cm.R[6] + dT[1] * cm.R[7] + dT[2] * cm.R[8];
+    const T dJ11 = dT[3] * cm.R[3] + dT[4] * cm.R[4] + dT[5] * cm.R[5];
+    const T dJ12 = dT[3] * cm.R[6] + dT[4] * cm.R[7] + dT[5] * cm.R[8];
+    const T iz2 = iz * iz;
+    T dpx = gu * cm.fx * iz, dpy = gv * cm.fy * iz;
+    T dpz = -(gu * cm.fx * px + gv * cm.fy * py) * iz2;
+    dpz += -dJ00 * cm.fx * iz2 - dJ11 * cm.fy * iz2;
+    if (!clx) {
+      dpx += dJ02 * (-cm.fx * iz2);
+      dpz += dJ02 * ((T)2 * cm.fx * px * iz2 * iz);
+    } else {
+      dpz += dJ02 * (cm.fx * xi * iz2);
+    }
+    if (!cly) {
+      dpy += dJ12 * (-cm.fy * iz2);
+      dpz += dJ12 * ((T)2 * cm.fy * py * iz2 * iz);
+    } else {
+      dpz += dJ12 * (cm.fy * eta * iz2);
+    }
+    dmu0 += cm.R[0] * dpx + cm.R[3] * dpy + cm.R[6] * dpz;
+    dmu1 += cm.R[1] * dpx + cm.R[4] * dpy + cm.R[7] * dpz;
+    dmu2 += cm.R[2] * dpx + cm.R[5] * dpy + cm.R[8] * dpz;
+  }
+  // Sigma = M M^T: dM = 2 dSig M (dSig symmetric)
+  T dM[9];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+      dM[3 * a + b] = 2 * (dSig[3 * a] * M[b] + dSig[3 * a + 1] * M[3 + b] + dSig[3 * a + 2] * M[6 + b]);
+  T gls[3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) gls[b] = (dM[b] * Rq[b] + dM[3 + b] * Rq[3 + b] + dM[6 + b] * Rq[6 + b]) * sv[b];
+  T g9[9];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) g9[3 * a + b] = dM[3 * a + b] * sv[b];
+  const T w = qw, x = qx, y = qy, z = qz;
+  T dq[4];
+  dq[0] = 2 * (-z * g9[1] + y * g9[2] + z * g9[3] - x * g9[5] - y * g9[6] + x * g9[7]);
+  dq[1] = 2 * (y * g9[1] + z * g9[2] + y * g9[3] - 2 * x * g9[4] - w * g9[5] + z * g9[6] + w * g9[7] - 2 * x * g9[8]);
+  dq[2] = 2 * (-2 * y * g9[0] + x * g9[1] + w * g9[2] + x * g9[3] + z * g9[5] - w * g9[6] + z * g9[7] - 2 * y * g9[8]);
+  dq[3] = 2 * (-2 * z * g9[0] - w * g9[1] + x * g9[2] + w * g9[3] - 2 * z * g9[4] + y * g9[5] + x * g9[6] + y * g9[7]);
+  const T dqq = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
+  const int64_t a = act_idx[i];
+  T* G = grad + a;
+  G[0] = dmu0; G[ld] = dmu1; G[2 * ld] = dmu2;
+  G[3 * ld] = gls[0]; G[4 * ld] = gls[1]; G[5 * ld] = gls[2];
+  G[6 * ld] = (dq[0] - dqq * w) * iq;
+  G[7 * ld] = (dq[1] - dqq * x) * iq;
+  G[8 * ld] = (dq[2] - dqq * y) * iq;
+  G[9 * ld] = (dq[3] - dqq * z) * iq;
+  G[10 * ld] = dlogit;
+#pragma unroll
+  for (int m = 0; m < 48; ++m) G[(int64_t)(11 + m) * ld] = gsh[m];
+}
+
+template <typename T>
+CamSet<T> make_camset(const tide_camera* cams, int n);
+
+}  // namespace tide
+
+using namespace tide;
+
+extern "C" size_t tide_render_bwd_ws_bytes(const tide_bins* bins, int32_t dtype) {
+  if (!bins) return 0;
+  const size_t es = dtype == TIDE_F64 ? 8 : 4;
+  return align_up((size_t)(bins->n_inst > 0 ? bins->n_inst : 1) * kG2 * es) +
+         align_up((size_t)kG2 * bins->n_cams * bins->n_pidx * es) + 256;
+}
+
+extern "C" tide_status tide_render_bwd(const tide_pool* pool, const tide_camera* cams, int32_t n_cams,
+                                       const tide_proj* proj, const tide_bins* bins, const tide_frame* fr,
+                                       const float* bg, const void* d_dimage, void* grad, int64_t grad_ld, void* ws,
+                                       size_t ws_bytes, void* stream) {
+  TIDE_CHECK_ARG(pool && cams && proj && bins && fr && bg && d_dimage && grad && ws, "null argument");
+  TIDE_CHECK_ARG(n_cams == proj->n_cams && n_cams == bins->n_cams, "camera counts differ");
+  TIDE_CHECK_ARG(proj->dtype == pool->dtype, "dtype mismatch");
+  TIDE_CHECK_ARG(grad_ld >= proj->n_pidx, "grad_ld (%lld) < n_pidx (%lld)", (long long)grad_ld,
+                 (long long)proj->n_pidx);
+  TIDE_CHECK_ARG(proj->n_pidx == (int64_t)pool->n_order * pool->block_rows, "proj does not match pool");
+  const size_t need = tide_render_bwd_ws_bytes(bins, proj->dtype);
+  if (ws_bytes < need) {
+    set_error("render_bwd workspace too small (%zu < %zu)", ws_bytes, need);
+    return TIDE_ECAPACITY;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const uint32_t grid = (uint32_t)(bins->n_cams * bins->tiles_x * bins->tiles_y);
+  const int64_t nrec = (int64_t)n_cams * proj->n_pidx;
+  Carver cv(ws);
+  if (proj->dtype == TIDE_F32) {
+    float* partial = cv.take<float>((size_t)(bins->n_inst > 0 ? bins->n_inst : 1) * kG2);
+    float* g2d = cv.take<float>((size_t)kG2 * nrec);
+    hipLaunchKernelGGL(k_render_bwd<float>, dim3(grid), dim3(64), 0, st, bins->ranges, bins->inst_e, bins->inst_rec,
+                       (const float*)proj->rec, bins->tiles_x, bins->tiles_y, fr->width, fr->height, bg[0], bg[1],
+                       bg[2], (const float*)fr->t_final, fr->last, (const float*)d_dimage, partial);
+    TIDE_LAUNCH_CHECK("k_render_bwd");
+    if (bins->n_vis > 0)
+      hipLaunchKernelGGL(k_reduce_pairs<float>, dim3((uint32_t)ceil_div(bins->n_vis, 256)), dim3(256), 0, st,
+                         bins->vis_rec, bins->inst_off, bins->n_vis, nrec, (const float*)partial, g2d);
+    TIDE_LAUNCH_CHECK("k_reduce_pairs");
+    const CamSet<float> cs = make_camset<float>(cams, n_cams);
+    if (proj->n_pidx > 0)
+      hipLaunchKernelGGL(k_adjoint<float>, dim3((uint32_t)ceil_div(proj->n_pidx, 128)), dim3(128), 0, st,
+                         (const float*)pool->params, pool->order, pool->block_rows, proj->n_pidx, cs,
+                         proj->tiles_touched, proj->active, proj->act_idx, (const float*)g2d, (float*)grad, grad_ld);
+    TIDE_LAUNCH_CHECK("k_adjoint");
+  } else {
+    double* partial = cv.take<double>((size_t)(bins->n_inst > 0 ? bins->n_inst : 1) * kG2);
+    double* g2d = cv.take<double>((size_t)kG2 * nrec);
+    hipLaunchKernelGGL(k_render_bwd<double>, dim3(grid), dim3(64), 0, st, bins->ranges, bins->inst_e,
+                       bins->inst_rec, (const double*)proj->rec, bins->tiles_x, bins->tiles_y, fr->width,
+                       fr->height, (double)bg[0], (double)bg[1], (double)bg[2], (const double*)fr->t_final,
+                       fr->last, (const double*)d_dimage, partial);
+    TIDE_LAUNCH_CHECK("k_render_bwd");
+    if (bins->n_vis > 0)
+      hipLaunchKernelGGL(k_reduce_pairs<double>, dim3((uint32_t)ceil_div(bins->n_vis, 256)), dim3(256), 0, st,
+                         bins->vis_rec, bins->inst_off, bins->n_vis, nrec, (const double*)partial, g2d);
+    TIDE_LAUNCH_CHECK("k_reduce_pairs");
+    const CamSet<double> cs = make_camset<double>(cams, n_cams);
+    if (proj->n_pidx > 0)
+      hipLaunchKernelGGL(k_adjoint<double>, dim3((uint32_t)ceil_div(proj->n_pidx, 128)), dim3(128), 0, st,
+                         (const double*)pool->params, pool->order, pool->block_rows, proj->n_pidx, cs,
+                         proj->tiles_touched, proj->active, proj->act_idx, (const double*)g2d, (double*)grad,
+                         grad_ld);
+    TIDE_LAUNCH_CHECK("k_adjoint");
+  }
+  return TIDE_OK;
+}

@@ -1,0 +1,537 @@
+// Forward half of the rasterizer: preprocessing (projection, culling, EWA
+// footprint, tile rectangle, SH colour), tile binning with the two-level
+// depth/tile radix sort, and front-to-back compositing.
+#include <cmath>
+#include <cstring>
+
+#include "prims.h"
+#include "raster.h"
+
+namespace tide {
+
+template <typename T>
+CamSet<T> make_camset(const tide_camera* cams, int n) {
+  CamSet<T> s;
+  std::memset(&s, 0, sizeof(s));
+  s.n = n;
+  for (int i = 0; i < n; ++i) {
+    const tide_camera& c = cams[i];
+    DevCam<T>& d = s.c[i];
+    for (int k = 0; k < 9; ++k) d.R[k] = (T)c.R[k];
+    for (int k = 0; k < 3; ++k) d.t[k] = (T)c.t[k];
+    d.fx = (T)c.fx; d.fy = (T)c.fy; d.cx = (T)c.cx; d.cy = (T)c.cy;
+    d.znear = (T)c.z_near; d.zfar = (T)c.z_far;
+    d.limx = (T)(1.3 * 0.5 * c.width / c.fx);
+    d.limy = (T)(1.3 * 0.5 * c.height / c.fy);
+    for (int k = 0; k < 3; ++k)
+      d.pos[k] = (T)(-(c.R[k] * c.t[0] + c.R[3 + k] * c.t[1] + c.R[6 + k] * c.t[2]));
+    d.W = c.width; d.H = c.height;
+    d.Tx = (c.width + kTile - 1) / kTile;
+    d.Ty = (c.height + kTile - 1) / kTile;
+  }
+  const double pi = M_PI;
+  s.sh.c0 = (T)(0.5 * std::sqrt(1.0 / pi));
+  s.sh.c1 = (T)std::sqrt(3.0 / (4.0 * pi));
+  s.sh.c2a = (T)(0.5 * std::sqrt(15.0 / pi));
+  s.sh.c2b = (T)(0.25 * std::sqrt(5.0 / pi));
+  s.sh.c2c = (T)(0.25 * std::sqrt(15.0 / pi));
+  s.sh.c3a = (T)(0.25 * std::sqrt(35.0 / (2.0 * pi)));
+  s.sh.c3b = (T)(0.5 * std::sqrt(105.0 / pi));
+  s.sh.c3c = (T)(0.25 * std::sqrt(21.0 / (2.0 * pi)));
+  s.sh.c3d = (T)(0.25 * std::sqrt(7.0 / pi));
+  s.sh.c3e = (T)(0.25 * std::sqrt(105.0 / pi));
+  return s;
+}
+template CamSet<float> make_camset<float>(const tide_camera*, int);
+template CamSet<double> make_camset<double>(const tide_camera*, int);
+
+// ------------------------------------------------------------- preprocess
+// One thread per processing index.  The mean (12 B) is read first and every
+// camera's depth test runs on it; the other 56 columns are read only if some
+// camera keeps the Gaussian.  Columns of a block are contiguous, so lanes
+// (consecutive rows) read coalesced.
+template <typename T>
+__global__ void __launch_bounds__(256) k_preprocess(const T* __restrict__ params, const int32_t* __restrict__ order,
+                                                    const int32_t* __restrict__ slot_rows, int32_t B,
+                                                    int64_t n_pidx, CamSet<T> cs, T* __restrict__ rec,
+                                                    float* __restrict__ depth, uint32_t* __restrict__ rect,
+                                                    uint32_t* __restrict__ tt, uint32_t* __restrict__ active) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_pidx) return;
+  const int64_t k = i / B;
+  const int32_t row = (int32_t)(i - k * B);
+  const int32_t slot = order[k];
+  const int ncam = cs.n;
+  uint32_t keep = 0;
+  T mu[3] = {0, 0, 0};
+  const T* P = params + (int64_t)slot * kD * B + row;
+  if (row < slot_rows[slot]) {
+    mu[0] = P[0]; mu[1] = P[B]; mu[2] = P[2 * (int64_t)B];
+#pragma unroll 1
+    for (int c = 0; c < ncam; ++c) {
+      const DevCam<T>& cm = cs.c[c];
+      const T pz = cm.R[6] * mu[0] + cm.R[7] * mu[1] + cm.R[8] * mu[2] + cm.t[2];
+      if (pz > cm.znear && pz <= cm.zfar) keep |= 1u << c;
+    }
+  }
+  uint32_t any = 0;
+  if (keep) {
+    // activations
+    const T s0 = Mth<T>::exp(P[3 * (int64_t)B]), s1 = Mth<T>::exp(P[4 * (int64_t)B]),
+            s2 = Mth<T>::exp(P[5 * (int64_t)B]);
+    T qw = P[6 * (int64_t)B], qx = P[7 * (int64_t)B], qy = P[8 * (int64_t)B], qz = P[9 * (int64_t)B];
+    const T qn = Mth<T>::sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+    const T iq = (T)1 / qn;
+    qw *= iq; qx *= iq; qy *= iq; qz *= iq;
+    const T op = (T)1 / ((T)1 + Mth<T>::exp(-P[10 * (int64_t)B]));
+    T sh[48];
+#pragma unroll
+    for (int m = 0; m < 48; ++m) sh[m] = P[(int64_t)(11 + m) * B];
+    // Sigma = M M^T, M = R(q) diag(s)
+    const T r00 = 1 - 2 * (qy * qy + qz * qz), r01 = 2 * (qx * qy - qw * qz), r02 = 2 * (qx * qz + qw * qy);
+    const T r10 = 2 * (qx * qy + qw * qz), r11 = 1 - 2 * (qx * qx + qz * qz), r12 = 2 * (qy * qz - qw * qx);
+    const T r20 = 2 * (qx * qz - qw * qy), r21 = 2 * (qy * qz + qw * qx), r22 = 1 - 2 * (qx * qx + qy * qy);
+    const T m00 = r00 * s0, m01 = r01 * s1, m02 = r02 * s2;
+    const T m10 = r10 * s0, m11 = r11 * s1, m12 = r12 * s2;
+    const T m20 = r20 * s0, m21 = r21 * s1, m22 = r22 * s2;
+    const T S00 = m00 * m00 + m01 * m01 + m02 * m02;
+    const T S01 = m00 * m10 + m01 * m11 + m02 * m12;
+    const T S02 = m00 * m20 + m01 * m21 + m02 * m22;
+    const T S11 = m10 * m10 + m11 * m11 + m12 * m12;
+    const T S12 = m10 * m20 + m11 * m21 + m12 * m22;
+    const T S22 = m20 * m20 + m21 * m21 + m22 * m22;
+#pragma unroll 1
+    for (int c = 0; c < ncam; ++c) {
+      const int64_t o = (int64_t)c * n_pidx + i;
+      uint32_t ntt = 0;
+      if (keep & (1u << c)) {
+        const DevCam<T>& cm = cs.c[c];
+        const T px = cm.R[0] * mu[0] + cm.R[1] * mu[1] + cm.R[2] * mu[2] + cm.t[0];
+        const T py = cm.R[3] * mu[0] + cm.R[4] * mu[1] + cm.R[5] * mu[2] + cm.t[1];
+        const T pz = cm.R[6] * mu[0] + cm.R[7] * mu[1] + cm.R[8] * mu[2] + cm.t[2];
+        const T iz = (T)1 / pz;
+        const T u = cm.fx * px * iz + cm.cx;
+        const T v = cm.fy * py * iz + cm.cy;
+        T xi = px * iz, eta = py * iz;
+        xi = xi < -cm.limx ? -cm.limx : (xi > cm.limx ? cm.limx : xi);
+        eta = eta < -cm.limy ? -cm.limy : (eta > cm.limy ? cm.limy : eta);
+        const T j00 = cm.fx * iz, j02 = -cm.fx * xi * iz, j11 = cm.fy * iz, j12 = -cm.fy * eta * iz;
+        // T = J W (2x3)
+        const T t00 = j00 * cm.R[0] + j02 * cm.R[6], t01 = j00 * cm.R[1] + j02 * cm.R[7],
+                t02 = j00 * cm.R[2] + j02 * cm.R[8];
+        const T t10 = j11 * cm.R[3] + j12 * cm.R[6], t11 = j11 * cm.R[4] + j12 * cm.R[7],
+                t12 = j11 * cm.R[5] + j12 * cm.R[8];
+        const T a0 = t00 * S00 + t01 * S01 + t02 * S02, a1 = t00 * S01 + t01 * S11 + t02 * S12,
+                a2 = t00 * S02 + t01 * S12 + t02 * S22;
+        const T b0 = t10 * S00 + t11 * S01 + t12 * S02, b1 = t10 * S01 + t11 * S11 + t12 * S12,
+                b2 = t10 * S02 + t11 * S12 + t12 * S22;
+        const T c00 = a0 * t00 + a1 * t01 + a2 * t02 + (T)0.3;
+        const T c01 = a0 * t10 + a1 * t11 + a2 * t12;
+        const T c11 = b0 * t10 + b1 * t11 + b2 * t12 + (T)0.3;
+        const T det = c00 * c11 - c01 * c01;
+        if (det > 0) {
+          const T idet = (T)1 / det;
+          const T mid = (T)0.5 * (c00 + c11);
+          T disc = mid * mid - det;
+          disc = disc > 0 ? disc : (T)0;
+          T rr = (T)3 * Mth<T>::sqrt(mid + Mth<T>::sqrt(disc));
+          rr = rr < (T)2097152 ? rr : (T)2097152;
+          const int r = (int)Mth<T>::ceil(rr);
+          int x0, y0, x1, y1;
+          if (tile_rect<T>(u, v, r, cm.Tx, cm.Ty, x0, y0, x1, y1)) {
+            ntt = (uint32_t)((x1 - x0) * (y1 - y0));
+            // view-dependent colour
+            T dx = mu[0] - cm.pos[0], dy = mu[1] - cm.pos[1], dz = mu[2] - cm.pos[2];
+            const T il = (T)1 / Mth<T>::sqrt(dx * dx + dy * dy + dz * dz);
+            dx *= il; dy *= il; dz *= il;
+            T Y[16];
+            sh_eval<T>(cs.sh, dx, dy, dz, Y);
+            T col[3] = {(T)0.5, (T)0.5, (T)0.5};
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+              col[0] += Y[m] * sh[3 * m];
+              col[1] += Y[m] * sh[3 * m + 1];
+              col[2] += Y[m] * sh[3 * m + 2];
+            }
+            T* R12 = rec + o * kRec;
+            R12[0] = u; R12[1] = v;
+            R12[2] = c11 * idet; R12[3] = -c01 * idet; R12[4] = c00 * idet;
+            R12[5] = op;
+            R12[6] = col[0] > 0 ? col[0] : (T)0;
+            R12[7] = col[1] > 0 ? col[1] : (T)0;
+            R12[8] = col[2] > 0 ? col[2] : (T)0;
+            R12[9] = pz; R12[10] = (T)r; R12[11] = 0;
+            depth[o] = (float)pz;
+            rect[2 * o] = (uint32_t)x0 | ((uint32_t)y0 << 16);
+            rect[2 * o + 1] = (uint32_t)x1 | ((uint32_t)y1 << 16);
+          }
+        }
+      }
+      tt[o] = ntt;
+      any |= ntt;
+    }
+  } else {
+    for (int c = 0; c < ncam; ++c) tt[(int64_t)c * n_pidx + i] = 0;
+  }
+  active[i] = any ? 1u : 0u;
+}
+
+size_t preprocess_ws_bytes(int64_t n_pidx) {
+  return align_up(scan_partial_count(n_pidx) * 8) + 256;
+}
+
+template <typename T>
+static tide_status preprocess_t(const tide_pool* pool, const tide_camera* cams, int n_cams, tide_proj* out,
+                                void* ws, hipStream_t st) {
+  const CamSet<T> cs = make_camset<T>(cams, n_cams);
+  const int64_t n = out->n_pidx;
+  if (n > 0) {
+    hipLaunchKernelGGL(k_preprocess<T>, dim3((uint32_t)ceil_div(n, 256)), dim3(256), 0, st,
+                       (const T*)pool->params, pool->order, pool->slot_rows, pool->block_rows, n, cs,
+                       (T*)out->rec, out->depth, out->rect, out->tiles_touched, out->active);
+    TIDE_LAUNCH_CHECK("k_preprocess");
+  }
+  Carver cv(ws);
+  unsigned long long* partial = cv.take<unsigned long long>(scan_partial_count(n));
+  unsigned long long* total = cv.take<unsigned long long>(1);
+  scan_exclusive(ArrayIn{out->active}, n, out->act_idx, partial, total, st);
+  TIDE_LAUNCH_CHECK("active scan");
+  // the count as u32 for the caller
+  TIDE_HIP(hipMemcpyAsync(out->n_active, total, 4, hipMemcpyDeviceToDevice, st));
+  return TIDE_OK;
+}
+
+static tide_status check_pool(const tide_pool* pool) {
+  TIDE_CHECK_ARG(pool, "pool is null");
+  TIDE_CHECK_ARG(pool->params && pool->order && pool->slot_rows && pool->slot_block, "pool has a null pointer");
+  TIDE_CHECK_ARG(pool->block_rows > 0 && pool->n_slots > 0 && pool->n_order >= 0 && pool->n_order <= pool->n_slots,
+                 "bad pool sizes (block_rows %d, n_slots %d, n_order %d)", pool->block_rows, pool->n_slots,
+                 pool->n_order);
+  TIDE_CHECK_ARG(pool->dtype == TIDE_F32 || pool->dtype == TIDE_F64, "bad dtype %d", pool->dtype);
+  TIDE_CHECK_ARG(aligned16(pool->params), "params must be 16-byte aligned");
+  return TIDE_OK;
+}
+
+static tide_status check_cams(const tide_camera* cams, int n_cams) {
+  TIDE_CHECK_ARG(cams, "cams is null");
+  TIDE_CHECK_ARG(n_cams >= 1 && n_cams <= TIDE_MAX_CAMS, "n_cams must be in [1, %d]", TIDE_MAX_CAMS);
+  for (int c = 0; c < n_cams; ++c) {
+    TIDE_CHECK_ARG(cams[c].width > 0 && cams[c].height > 0 && cams[c].width <= 65535 * 16 &&
+                       cams[c].height <= 65535 * 16,
+                   "camera %d has a bad image size", c);
+    TIDE_CHECK_ARG(cams[c].fx > 0 && cams[c].fy > 0, "camera %d has a non-positive focal length", c);
+    TIDE_CHECK_ARG(cams[c].z_near > 0 && cams[c].z_far > cams[c].z_near, "camera %d has bad near/far planes", c);
+  }
+  return TIDE_OK;
+}
+
+static tide_status check_proj(const tide_proj* p) {
+  TIDE_CHECK_ARG(p, "proj is null");
+  TIDE_CHECK_ARG(p->rec && p->depth && p->rect && p->tiles_touched && p->active && p->act_idx && p->n_active,
+                 "proj has a null pointer");
+  TIDE_CHECK_ARG(aligned16(p->rec), "proj.rec must be 16-byte aligned");
+  TIDE_CHECK_ARG(p->n_cams >= 1 && p->n_cams <= TIDE_MAX_CAMS, "proj.n_cams out of range");
+  TIDE_CHECK_ARG(p->n_pidx >= 0 && (int64_t)p->n_cams * p->n_pidx < (int64_t)UINT32_MAX,
+                 "n_cams * n_pidx must fit 32 bits");
+  TIDE_CHECK_ARG(p->dtype == TIDE_F32 || p->dtype == TIDE_F64, "bad dtype");
+  return TIDE_OK;
+}
+
+// ---------------------------------------------------------------- binning
+__global__ void k_compact_vis(const uint32_t* __restrict__ tt, const float* __restrict__ depth,
+                              const uint32_t* __restrict__ vis_off, int64_t n, uint32_t* __restrict__ key,
+                              uint32_t* __restrict__ val) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || tt[i] == 0) return;
+  const uint32_t o = vis_off[i];
+  key[o] = __float_as_uint(depth[i]);   // depth > 0: the bit pattern orders like the value
+  val[o] = (uint32_t)i;
+}
+
+// Instances of the s-th depth-ordered visible pair, tiles row-major.
+__global__ void k_emit(const uint32_t* __restrict__ vis_rec, const uint32_t* __restrict__ inst_off,
+                       const uint32_t* __restrict__ rect, int64_t n_vis, int64_t n_pidx, int32_t Tx, int32_t Ty,
+                       uint32_t* __restrict__ tkey, uint32_t* __restrict__ inst_rec) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_vis) return;
+  const uint32_t r = vis_rec[s];
+  const uint32_t c = (uint32_t)(r / (uint64_t)n_pidx);
+  const uint32_t a = rect[2 * (int64_t)r], b = rect[2 * (int64_t)r + 1];
+  const int x0 = a & 0xffff, y0 = a >> 16, x1 = b & 0xffff, y1 = b >> 16;
+  uint32_t e = inst_off[s];
+  const uint32_t tbase = c * (uint32_t)(Tx * Ty);
+  for (int ty = y0; ty < y1; ++ty)
+    for (int tx = x0; tx < x1; ++tx) {
+      tkey[e] = tbase + (uint32_t)(ty * Tx + tx);
+      inst_rec[e] = r;
+      ++e;
+    }
+}
+
+__global__ void k_set_u32(uint32_t* p, const unsigned long long* v) { *p = (uint32_t)*v; }
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_ranges(const uint32_t* __restrict__ key, int64_t n, uint32_t* __restrict__ ranges) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const uint32_t k = key[j];
+  if (j == 0 || key[j - 1] != k) ranges[2 * (int64_t)k] = (uint32_t)j;
+  if (j == n - 1 || key[j + 1] != k) ranges[2 * (int64_t)k + 1] = (uint32_t)(j + 1);
+}
+
+struct BinLayout {
+  uint32_t *vis_off, *ka, *va, *kb, *vb, *inst_off, *tka, *tva, *tkb, *tvb, *inst_rec, *ranges, *hist;
+  unsigned long long *partial, *totals;
+  size_t bytes;
+};
+
+static BinLayout bin_layout(void* ws, int n_cams, int64_t n_pidx, int64_t n_tiles, int64_t cap) {
+  const int64_t nv = (int64_t)n_cams * n_pidx;
+  Carver cv(ws);
+  BinLayout L;
+  L.vis_off = cv.take<uint32_t>(nv);
+  L.ka = cv.take<uint32_t>(nv);
+  L.va = cv.take<uint32_t>(nv);
+  L.kb = cv.take<uint32_t>(nv);
+  L.vb = cv.take<uint32_t>(nv);
+  L.inst_off = cv.take<uint32_t>(nv + 1);
+  L.tka = cv.take<uint32_t>(cap);
+  L.tva = cv.take<uint32_t>(cap);
+  L.tkb = cv.take<uint32_t>(cap);
+  L.tvb = cv.take<uint32_t>(cap);
+  L.inst_rec = cv.take<uint32_t>(cap);
+  L.ranges = cv.take<uint32_t>(2 * (size_t)n_cams * n_tiles);
+  const int64_t big = nv > cap ? nv : cap;
+  const size_t nh = radix_hist_count(big);
+  L.hist = cv.take<uint32_t>(nh);
+  const size_t np = scan_partial_count((int64_t)(nh > (size_t)big ? nh : (size_t)big));
+  L.partial = cv.take<unsigned long long>(np);
+  L.totals = cv.take<unsigned long long>(4);
+  L.bytes = cv.used;
+  return L;
+}
+
+// ------------------------------------------------------------- compositing
+// One wave64 per 16x16 tile; lane l owns the four pixels of column l % 16,
+// rows l / 16 + {0, 4, 8, 12}.  The tile's list is streamed through LDS in
+// batches of 64 records, read back as broadcasts.
+template <typename T>
+__global__ void __launch_bounds__(64) k_render_fwd(const uint32_t* __restrict__ ranges,
+                                                   const uint32_t* __restrict__ inst_e,
+                                                   const uint32_t* __restrict__ inst_rec, const T* __restrict__ rec,
+                                                   int32_t Tx, int32_t Ty, int32_t W, int32_t H, T bg0, T bg1,
+                                                   T bg2, T* __restrict__ image, T* __restrict__ tfin,
+                                                   uint32_t* __restrict__ last_out,
+                                                   unsigned long long* __restrict__ visits) {
+  const int nt = Tx * Ty;
+  const int g = blockIdx.x;
+  const int c = g / nt, t = g - c * nt;
+  const int tx = t % Tx, ty = t / Tx;
+  const int lane = threadIdx.x;
+  const int px = tx * kTile + (lane & 15);
+  const int py0 = ty * kTile + (lane >> 4);
+  const T fxp = (T)px + (T)0.5;
+  T fyp[4];
+  bool done[4];
+  T Tr[4], C0[4], C1[4], C2[4];
+  uint32_t lst[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    fyp[q] = (T)(py0 + 4 * q) + (T)0.5;
+    done[q] = !(px < W && py0 + 4 * q < H);
+    Tr[q] = 1; C0[q] = C1[q] = C2[q] = 0; lst[q] = 0;
+  }
+  unsigned long long nvis = 0;
+  const uint32_t start = ranges[2 * g], end = ranges[2 * g + 1];
+  __shared__ T s_u[64], s_v[64], s_A[64], s_B[64], s_C[64], s_o[64], s_r[64], s_g[64], s_b[64];
+  bool all_done = __ballot(!(done[0] && done[1] && done[2] && done[3])) == 0;
+  for (uint32_t b0 = start; b0 < end && !all_done; b0 += 64) {
+    const uint32_t j = b0 + lane;
+    if (j < end) {
+      const T* q = rec + (int64_t)inst_rec[inst_e[j]] * kRec;
+      s_u[lane] = q[0]; s_v[lane] = q[1];
+      s_A[lane] = (T)-0.5 * q[2]; s_B[lane] = -q[3]; s_C[lane] = (T)-0.5 * q[4];
+      s_o[lane] = q[5]; s_r[lane] = q[6]; s_g[lane] = q[7]; s_b[lane] = q[8];
+    }
+    __syncthreads();
+    const int nb = (int)(end - b0 < 64 ? end - b0 : 64);
+    for (int k = 0; k < nb; ++k) {
+      const T u = s_u[k], v = s_v[k], A = s_A[k], B = s_B[k], Cc = s_C[k], op = s_o[k];
+      const T cr = s_r[k], cg = s_g[k], cb = s_b[k];
+      const T dx = fxp - u;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (done[q]) continue;
+        ++nvis;
+        const T dy = fyp[q] - v;
+        T G, araw, alpha;
+        if (!entry_alpha<T>(A, B, Cc, op, dx, dy, G, araw, alpha)) continue;
+        const T tn = Tr[q] * ((T)1 - alpha);
+        if (tn < (T)1e-4) { done[q] = true; continue; }
+        const T w = alpha * Tr[q];
+        C0[q] += cr * w; C1[q] += cg * w; C2[q] += cb * w;
+        Tr[q] = tn;
+        lst[q] = b0 - start + (uint32_t)k + 1;
+      }
+      if (__ballot(!(done[0] && done[1] && done[2] && done[3])) == 0) { all_done = true; break; }
+    }
+    __syncthreads();
+  }
+  const int64_t HW = (int64_t)H * W;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int py = py0 + 4 * q;
+    if (px < W && py < H) {
+      const int64_t p = (int64_t)py * W + px;
+      image[((int64_t)c * 3 + 0) * HW + p] = C0[q] + Tr[q] * bg0;
+      image[((int64_t)c * 3 + 1) * HW + p] = C1[q] + Tr[q] * bg1;
+      image[((int64_t)c * 3 + 2) * HW + p] = C2[q] + Tr[q] * bg2;
+      tfin[(int64_t)c * HW + p] = Tr[q];
+      last_out[(int64_t)c * HW + p] = lst[q];
+    }
+  }
+  nvis = wave_sum(nvis);
+  if (lane == 0 && nvis) atomicAdd(&visits[c], nvis);
+}
+
+}  // namespace tide
+
+using namespace tide;
+
+extern "C" size_t tide_preprocess_ws_bytes(int64_t n_pidx) { return preprocess_ws_bytes(n_pidx); }
+
+extern "C" tide_status tide_preprocess(const tide_pool* pool, const tide_camera* cams, int32_t n_cams,
+                                       tide_proj* out, void* ws, size_t ws_bytes, void* stream) {
+  tide_status s;
+  if ((s = check_pool(pool)) != TIDE_OK) return s;
+  if ((s = check_cams(cams, n_cams)) != TIDE_OK) return s;
+  if ((s = check_proj(out)) != TIDE_OK) return s;
+  TIDE_CHECK_ARG(out->n_cams == n_cams, "proj.n_cams (%d) != n_cams (%d)", out->n_cams, n_cams);
+  TIDE_CHECK_ARG(out->dtype == pool->dtype, "proj and pool dtypes differ");
+  TIDE_CHECK_ARG(out->n_pidx == (int64_t)pool->n_order * pool->block_rows, "proj.n_pidx must be n_order * block_rows");
+  TIDE_CHECK_ARG(ws && ws_bytes >= preprocess_ws_bytes(out->n_pidx), "workspace too small (%zu < %zu)", ws_bytes,
+                 preprocess_ws_bytes(out->n_pidx));
+  hipStream_t st = (hipStream_t)stream;
+  return pool->dtype == TIDE_F32 ? preprocess_t<float>(pool, cams, n_cams, out, ws, st)
+                                 : preprocess_t<double>(pool, cams, n_cams, out, ws, st);
+}
+
+extern "C" size_t tide_bin_sort_ws_bytes(int32_t n_cams, int64_t n_pidx, int32_t tiles_x, int32_t tiles_y,
+                                         int64_t n_inst_cap) {
+  return bin_layout(nullptr, n_cams, n_pidx, (int64_t)tiles_x * tiles_y, n_inst_cap).bytes;
+}
+
+extern "C" tide_status tide_bin_sort(const tide_proj* proj, int32_t tiles_x, int32_t tiles_y, void* ws,
+                                     size_t ws_bytes, tide_bins* out, void* stream) {
+  tide_status s;
+  if ((s = check_proj(proj)) != TIDE_OK) return s;
+  TIDE_CHECK_ARG(out, "bins is null");
+  TIDE_CHECK_ARG(tiles_x > 0 && tiles_y > 0 && tiles_x < 65536 && tiles_y < 65536, "bad tile grid");
+  const int V = proj->n_cams;
+  const int64_t N = proj->n_pidx, nv = (int64_t)V * N, nt = (int64_t)tiles_x * tiles_y;
+  TIDE_CHECK_ARG((int64_t)V * nt < (1ll << 31), "too many tiles");
+  hipStream_t st = (hipStream_t)stream;
+  out->ws_required = 0;
+  // capacity this workspace gives for instances
+  const size_t fixed = bin_layout(nullptr, V, N, nt, 0).bytes;
+  TIDE_CHECK_ARG(ws, "workspace is null");
+  if (ws_bytes < fixed + 4096) {
+    out->ws_required = tide_bin_sort_ws_bytes(V, N, tiles_x, tiles_y, nv * 4 + 1024);
+    set_error("bin_sort workspace too small (%zu bytes; need at least %zu)", ws_bytes, out->ws_required);
+    return TIDE_ECAPACITY;
+  }
+  int64_t cap = (int64_t)((ws_bytes - fixed) / (6 * sizeof(uint32_t))) - 1024;
+  while (cap > 0 && bin_layout(nullptr, V, N, nt, cap).bytes > ws_bytes) cap -= (cap / 64 + 256);
+  if (cap < 0) cap = 0;
+  BinLayout L = bin_layout(ws, V, N, nt, cap);
+
+  // 1. visible pairs, compacted in (camera, pidx) order, keyed by depth bits
+  scan_exclusive(NonzeroIn{proj->tiles_touched}, nv, L.vis_off, L.partial, &L.totals[0], st);
+  if (nv > 0)
+    hipLaunchKernelGGL(k_compact_vis, dim3((uint32_t)ceil_div(nv, 256)), dim3(256), 0, st, proj->tiles_touched,
+                       proj->depth, L.vis_off, nv, L.ka, L.va);
+  TIDE_LAUNCH_CHECK("visibility compaction");
+  unsigned long long h_tot[2] = {0, 0};
+  TIDE_HIP(hipMemcpyAsync(&h_tot[0], &L.totals[0], 8, hipMemcpyDeviceToHost, st));
+  TIDE_HIP(hipStreamSynchronize(st));
+  const int64_t n_vis = (int64_t)h_tot[0];
+  // 2. stable sort of the visible pairs by depth
+  uint32_t *vk, *vrec;
+  radix_sort_pairs(L.ka, L.va, L.kb, L.vb, n_vis, 32, false, L.hist, L.partial, &L.totals[1], st, &vk, &vrec);
+  // 3. instance offsets in depth order
+  scan_exclusive(GatherIn{proj->tiles_touched, vrec}, n_vis, L.inst_off, L.partial, &L.totals[2], st);
+  hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, st, L.inst_off + n_vis, &L.totals[2]);
+  TIDE_LAUNCH_CHECK("instance scan");
+  TIDE_HIP(hipMemcpyAsync(&h_tot[1], &L.totals[2], 8, hipMemcpyDeviceToHost, st));
+  TIDE_HIP(hipStreamSynchronize(st));
+  const int64_t n_inst = (int64_t)h_tot[1];
+  if (n_inst >= (int64_t)UINT32_MAX) {
+    set_error("instance count %lld exceeds 32-bit indexing", (long long)n_inst);
+    return TIDE_EINVAL;
+  }
+  if (n_inst > cap) {
+    out->ws_required = tide_bin_sort_ws_bytes(V, N, tiles_x, tiles_y, n_inst + n_inst / 8 + 1024);
+    out->n_vis = n_vis;
+    out->n_inst = n_inst;
+    set_error("bin_sort needs %lld instances, workspace holds %lld", (long long)n_inst, (long long)cap);
+    return TIDE_ECAPACITY;
+  }
+  // 4. emit instances in depth order, keyed by global tile id
+  if (n_vis > 0)
+    hipLaunchKernelGGL(k_emit, dim3((uint32_t)ceil_div(n_vis, 256)), dim3(256), 0, st, vrec, L.inst_off, proj->rect,
+                       n_vis, N, tiles_x, tiles_y, L.tka, L.inst_rec);
+  TIDE_LAUNCH_CHECK("k_emit");
+  // 5. stable sort by tile; values are emission indices
+  int bits = 0;
+  while ((1ll << bits) < (int64_t)V * nt) ++bits;
+  bits = bits < 8 ? 8 : bits;
+  uint32_t *tk, *te;
+  radix_sort_pairs(L.tka, L.tva, L.tkb, L.tvb, n_inst, bits, true, L.hist, L.partial, &L.totals[3], st, &tk, &te);
+  // 6. per-tile ranges
+  const int64_t nr = 2 * (int64_t)V * nt;
+  hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)ceil_div(nr, 256)), dim3(256), 0, st, L.ranges, nr, 0u);
+  if (n_inst > 0)
+    hipLaunchKernelGGL(k_ranges, dim3((uint32_t)ceil_div(n_inst, 256)), dim3(256), 0, st, tk, n_inst, L.ranges);
+  TIDE_LAUNCH_CHECK("k_ranges");
+  out->vis_rec = vrec;
+  out->inst_off = L.inst_off;
+  out->inst_e = te;
+  out->inst_rec = L.inst_rec;
+  out->ranges = L.ranges;
+  out->n_vis = n_vis;
+  out->n_inst = n_inst;
+  out->n_cams = V;
+  out->tiles_x = tiles_x;
+  out->tiles_y = tiles_y;
+  out->n_pidx = N;
+  return TIDE_OK;
+}
+
+extern "C" tide_status tide_render_fwd(const tide_proj* proj, const tide_bins* bins, const float* bg,
+                                       tide_frame* fr, void* stream) {
+  tide_status s;
+  if ((s = check_proj(proj)) != TIDE_OK) return s;
+  TIDE_CHECK_ARG(bins && fr && bg, "null argument");
+  TIDE_CHECK_ARG(fr->image && fr->t_final && fr->last && fr->visits, "frame has a null pointer");
+  TIDE_CHECK_ARG(bins->n_cams == proj->n_cams && bins->n_pidx == proj->n_pidx, "bins do not match proj");
+  TIDE_CHECK_ARG(fr->width > 0 && fr->height > 0 && (fr->width + kTile - 1) / kTile == bins->tiles_x &&
+                     (fr->height + kTile - 1) / kTile == bins->tiles_y,
+                 "frame size does not match the tile grid");
+  hipStream_t st = (hipStream_t)stream;
+  const uint32_t grid = (uint32_t)(bins->n_cams * bins->tiles_x * bins->tiles_y);
+  if (proj->dtype == TIDE_F32)
+    hipLaunchKernelGGL(k_render_fwd<float>, dim3(grid), dim3(64), 0, st, bins->ranges, bins->inst_e, bins->inst_rec,
+                       (const float*)proj->rec, bins->tiles_x, bins->tiles_y, fr->width, fr->height, bg[0], bg[1],
+                       bg[2], (float*)fr->image, (float*)fr->t_final, fr->last, fr->visits);
+  else
+    hipLaunchKernelGGL(k_render_fwd<double>, dim3(grid), dim3(64), 0, st, bins->ranges, bins->inst_e,
+                       bins->inst_rec, (const double*)proj->rec, bins->tiles_x, bins->tiles_y, fr->width,
+                       fr->height, (double)bg[0], (double)bg[1], (double)bg[2], (double*)fr->image,
+                       (double*)fr->t_final, fr->last, fr->visits);
+  TIDE_LAUNCH_CHECK("k_render_fwd");
+  return TIDE_OK;
+}
