@@ -251,6 +251,19 @@ tide_status tide_adam_sparse(tide_pool* pool, const tide_proj* proj, const void*
                              int64_t grad_ld, const tide_adam_cfg* cfg, float* spheres,
                              uint8_t* dirty, int64_t n_blocks, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Timing hook for measurement.  Arms a pair of caller-created HIP events
+ * (hipEvent_t) for one kernel of the library; every later launch of that
+ * kernel records ev_start immediately before and ev_stop immediately after
+ * it, on the launch stream, until tide_timer_clear().  Kernel names:
+ * "preprocess", "compact_vis", "radix_scatter", "emit", "render_fwd",
+ * "loss_fwd", "loss_bwd", "render_bwd", "reduce_pairs", "adjoint", "adam".
+ * At most 16 names are armed at once; re-arming a name replaces its events.
+ * The events are not owned by the library.
+ * ---------------------------------------------------------------------- */
+tide_status tide_timer_arm(const char* kernel, void* ev_start, void* ev_stop);
+tide_status tide_timer_clear(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -59,7 +59,7 @@ def _declare(L):
     L.orc_tile_rect.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int, C.c_int, _i32]
     L.orc_bin.argtypes = [_d, _d, _d, _i32, _i32, C.c_int64, _d, C.c_int, _i64, C.c_int64, _i64]
     L.orc_bin.restype = C.c_int64
-    L.orc_composite.argtypes = [_i64, _i64, _d, C.c_int64, _d, C.c_int, _d, _d, _d, _i32, _i64, _d]
+    L.orc_composite.argtypes = [_i64, _i64, _d, C.c_int64, _d, C.c_int, _d, _d, _d, _i32, _i64, _d, _d]
     L.orc_render.argtypes = [_d, C.c_int64, _d, C.c_int, _d, _d, _d, _i32, _i64, _d, _d, _i32]
     L.orc_loss.argtypes = [_d, _d, C.c_int, C.c_int, C.c_int, _d, _d]
     L.orc_backward.argtypes = [_d, C.c_int64, _d, C.c_int, _d, _d, _d, _d]
@@ -119,12 +119,13 @@ def project(theta, cams):
     th = _f64(theta)
     cm = _f64(cams)
     V, N = cm.shape[0], th.shape[0]
-    pf = np.zeros((V, N, 14))
+    pf = np.zeros((V, N, 16))
     pi = np.zeros((V, N, 7), dtype=np.int32)
     mg = np.zeros((V, N))
     lib().orc_project(_p(th, _d), N, _p(cm, _d), V, _p(pf, _d), _p(pi, _i32), _p(mg, _d))
     return dict(u=pf[..., 0], v=pf[..., 1], depth=pf[..., 2], conic=pf[..., 3:6], opacity=pf[..., 6],
-                rgb=pf[..., 7:10], cov2d=pf[..., 10:13], rr=pf[..., 13], keep=pi[..., 0].astype(bool),
+                rgb=pf[..., 7:10], cov2d=pf[..., 10:13], rr=pf[..., 13], perr=pf[..., 14], derr=pf[..., 15],
+                keep=pi[..., 0].astype(bool),
                 radius=pi[..., 1], rect=pi[..., 2:6], tiles_touched=pi[..., 6], margin=mg)
 
 
@@ -159,11 +160,18 @@ def bin_sort(u, v, depth, radius, keep, cams):
     return gid[:m], ranges
 
 
-def composite(gid, ranges, rec, cams, bg=(0.0, 0.0, 0.0)):
-    """O7 over given lists.  rec[V, N, 9] = u, v, A, B, C, opacity, r, g, b."""
+def composite(gid, ranges, rec, cams, bg=(0.0, 0.0, 0.0), depth=None, perr=None, derr=None):
+    """O7 over given lists.  rec[V, N, 9] = u, v, A, B, C, opacity, r, g, b.
+    depth / perr / derr [V, N] only feed the near-tie margins; by default
+    the inputs are taken as exact (position uncertainty = rounding of u, v
+    in single precision, depth ties impossible)."""
     cm = _f64(cams)
     rec = _f64(rec)
     V, N = rec.shape[0], rec.shape[1]
+    unc = np.zeros((V, N, 3))
+    unc[..., 0] = 0.0 if depth is None else depth
+    unc[..., 1] = (np.abs(rec[..., 0]) + np.abs(rec[..., 1]) + 1.0) * 2.0 ** -22 if perr is None else perr
+    unc[..., 2] = 0.0 if derr is None else derr
     W, H = int(cm[0, 16]), int(cm[0, 17])
     gid = np.ascontiguousarray(gid, dtype=np.int64)
     ranges = np.ascontiguousarray(ranges, dtype=np.int64)
@@ -174,13 +182,14 @@ def composite(gid, ranges, rec, cams, bg=(0.0, 0.0, 0.0)):
     vis = np.zeros((V, H, W), dtype=np.int64)
     mg = np.zeros((V, H, W))
     lib().orc_composite(_p(gid, _i64), _p(ranges, _i64), _p(rec, _d), N, _p(cm, _d), V, _p(bgv, _d),
-                        _p(img, _d), _p(tf, _d), _p(last, _i32), _p(vis, _i64), _p(mg, _d))
+                        _p(img, _d), _p(tf, _d), _p(last, _i32), _p(vis, _i64), _p(mg, _d), _p(unc, _d))
     return dict(image=img, t_final=tf, last=last, visits=vis, pix_margin=mg)
 
 
 def render(theta, cams, bg=(0.0, 0.0, 0.0)):
     """Full FP64 forward.  Returns image [V,3,H,W], t_final, last, visits
-    (per pixel), keep [V,N], pair and pixel margins."""
+    (per pixel), keep [V,N], and pair / pixel near-tie ratios (margin over
+    its first-order single-precision uncertainty; below 1 is a near tie)."""
     th = _f64(theta)
     cm = _f64(cams)
     V, N = cm.shape[0], th.shape[0]

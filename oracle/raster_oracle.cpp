@@ -147,12 +147,22 @@ struct Fwd {
   double J[6], T[6];          // J (2x3), T = J W (2x3)
   double Sig[9], M[9], Rq[9];
   double s[3], qh[4], qn = 0;
-  double margin = 1e300;      // smallest relative margin of a discrete decision
+  double perr = 0, derr = 0;  // first-order FP32 uncertainty of (u, v) in px and of depth
+  double margin = 1e300;      // smallest decision margin / its FP32 uncertainty (< 1: near tie)
 };
 
 inline double rel_int_dist(double x) {  // distance of x to the nearest integer
   return std::fabs(x - std::nearbyint(x));
 }
+
+// Near-tie model.  A discrete decision taken in single precision can differ
+// from the double-precision one when its margin is within the rounding error
+// its inputs carry.  Every margin below is divided by a first-order estimate
+// of that error, so a ratio below 1 marks a near tie:
+//   position  perr = 2^-20 (|u| + |cx| + f (|mu| + |t|) / p_z)  pixels
+//   depth     derr = 2^-20 (|mu| + |t|)
+//   any other quantity x: 2^-20 |x| (relative).
+constexpr double kTieRel = 1.0 / 1048576.0;
 
 // Tile-coverage rectangle of O4 with exact integer-vs-real comparisons:
 // x0 = smallest tx with 16(tx+1) + r > u, x1 = 1 + largest tx with 16 tx - r <= u,
@@ -172,11 +182,9 @@ void tile_rect(double u, double v, int r, int Tx, int Ty, int rect[4]) {
 }
 
 double rect_margin(double u, double v, int r) {
-  // distance of u +- r, v +- r to the nearest tile boundary, relative
+  // distance (px) of u +- r, v +- r to the nearest tile boundary
   auto dm = [](double a) { return std::fabs(a / kTile - std::nearbyint(a / kTile)) * kTile; };
-  const double s = std::max(1.0, std::fabs(u) + std::fabs(v) + r);
-  double m = std::min(std::min(dm(u + r), dm(u - r)), std::min(dm(v + r), dm(v - r)));
-  return m / s;
+  return std::min(std::min(dm(u + r), dm(u - r)), std::min(dm(v + r), dm(v - r)));
 }
 
 void project_one(const double* th, const Cam& c, Fwd& f) {
@@ -188,8 +196,11 @@ void project_one(const double* th, const Cam& c, Fwd& f) {
     f.p[i] = c.R[3 * i] * mu[0] + c.R[3 * i + 1] * mu[1] + c.R[3 * i + 2] * mu[2] + c.t[i];
   const double pz = f.p[2];
   f.depth = pz;
-  f.margin = std::min(f.margin, std::fabs(pz - c.znear) / c.znear);
-  f.margin = std::min(f.margin, std::fabs(pz - c.zfar) / c.zfar);
+  const double mun = std::sqrt(mu[0] * mu[0] + mu[1] * mu[1] + mu[2] * mu[2]);
+  const double tn = std::sqrt(c.t[0] * c.t[0] + c.t[1] * c.t[1] + c.t[2] * c.t[2]);
+  f.derr = kTieRel * (mun + tn);
+  f.margin = std::min(f.margin, std::fabs(pz - c.znear) / f.derr);
+  f.margin = std::min(f.margin, std::fabs(pz - c.zfar) / f.derr);
   if (!(pz > c.znear) || pz > c.zfar) return;
 
   // activations
@@ -214,6 +225,8 @@ void project_one(const double* th, const Cam& c, Fwd& f) {
   // pinhole projection
   f.u = c.fx * f.p[0] / pz + c.cx;
   f.v = c.fy * f.p[1] / pz + c.cy;
+  f.perr = kTieRel * (std::fabs(f.u) + std::fabs(f.v) + std::fabs(c.cx) + std::fabs(c.cy) +
+                      std::max(c.fx, c.fy) * (mun + tn) / std::fabs(pz));
 
   // EWA: J evaluated at the clamped tangents
   const double limx = 1.3 * (0.5 * c.W) / c.fx, limy = 1.3 * (0.5 * c.H) / c.fy;
@@ -243,7 +256,7 @@ void project_one(const double* th, const Cam& c, Fwd& f) {
   f.s01 = 0.5 * (S2[1] + S2[2]);
   f.s11 = S2[3] + 0.3;
   f.det = f.s00 * f.s11 - f.s01 * f.s01;
-  f.margin = std::min(f.margin, std::fabs(f.det) / (f.s00 * f.s11));
+  f.margin = std::min(f.margin, std::fabs(f.det) / (f.s00 * f.s11) / kTieRel);
   if (!(f.det > 0)) return;
   f.A = f.s11 / f.det;
   f.B = -f.s01 / f.det;
@@ -255,9 +268,9 @@ void project_one(const double* th, const Cam& c, Fwd& f) {
   // radius cap of 2^21 px (a footprint that large covers any image; it keeps
   // 16 t +- r exactly representable in single precision on the GPU side)
   f.r = (int)std::ceil(std::min(rr, 2097152.0));
-  f.margin = std::min(f.margin, rel_int_dist(rr) / std::max(rr, 1.0));
+  f.margin = std::min(f.margin, rel_int_dist(rr) / (kTieRel * std::max(rr, 1.0)));
   tile_rect(f.u, f.v, f.r, c.tx(), c.ty(), f.rect);
-  f.margin = std::min(f.margin, rect_margin(f.u, f.v, f.r));
+  f.margin = std::min(f.margin, rect_margin(f.u, f.v, f.r) / f.perr);
   f.tt = (f.rect[2] - f.rect[0]) * (f.rect[3] - f.rect[1]);
   if (f.tt == 0) return;
 
@@ -304,7 +317,7 @@ void bin_camera(const Cam& c, int64_t n, const double* u, const double* v, const
 }
 
 // ------------------------------------------------------------- compositing
-struct Rec { double u, v, A, B, C, op, rgb[3]; };
+struct Rec { double u, v, A, B, C, op, rgb[3], depth, perr, derr; };
 
 // Composites one tile of camera c. Writes image/t_final/last/visits for the
 // pixels of the tile.  `list` holds the tile's gids in order.
@@ -317,18 +330,26 @@ void composite_tile(const Cam& c, int tx, int ty, const int64_t* list, int64_t l
       double T = 1.0, col[3] = {0, 0, 0}, mg = 1e300;
       int32_t lst = 0;
       int64_t vis = 0;
+      double eT = 0;  // uncertainty of ln T
       for (int64_t j = 0; j < len; ++j) {
         const Rec& g = rec[list[j]];
         ++vis;
+        if (j > 0 && g.derr + rec[list[j - 1]].derr > 0)  // depth order against the previous entry
+          mg = std::min(mg, std::fabs(g.depth - rec[list[j - 1]].depth) / (g.derr + rec[list[j - 1]].derr));
         const double dx = px + 0.5 - g.u, dy = py + 0.5 - g.v;
         const double power = -0.5 * (g.A * dx * dx + g.C * dy * dy) - g.B * dx * dy;
         if (power > 0) continue;
-        const double alpha = std::min(0.99, g.op * std::exp(power));
-        mg = std::min(mg, std::fabs(alpha - 1.0 / 255.0) * 255.0);
+        const double a_raw = g.op * std::exp(power);
+        const double alpha = std::min(0.99, a_raw);
+        const double gx = g.A * dx + g.B * dy, gy = g.B * dx + g.C * dy;
+        const double epow = std::sqrt(gx * gx + gy * gy) * g.perr + kTieRel * (std::fabs(power) + 1.0);
+        mg = std::min(mg, std::fabs(power + std::log(255.0 * g.op)) / epow);
         if (alpha < 1.0 / 255.0) continue;
+        const double ea = (a_raw < 0.99 ? alpha / (1 - alpha) * epow : 0.0) + kTieRel;
         const double Tn = T * (1 - alpha);
-        mg = std::min(mg, std::fabs(Tn - 1e-4) / 1e-4);
+        mg = std::min(mg, std::fabs(std::log(Tn / 1e-4)) / (eT + ea));
         if (Tn < 1e-4) break;
+        eT += ea;
         for (int ch = 0; ch < 3; ++ch) col[ch] += g.rgb[ch] * alpha * T;
         T = Tn;
         lst = (int32_t)(j + 1);
@@ -384,9 +405,10 @@ void orc_sh_basis_grad(const double* dir, double* dY) {
 }
 
 // Per (camera, Gaussian) projection, O2-O5.
-//   out_f[c][i][14]: u, v, depth, A, B, C, opacity, r, g, b, s00, s01, s11, lambda-radius(3 sqrt l1)
+//   out_f[c][i][16]: u, v, depth, A, B, C, opacity, r, g, b, s00, s01, s11, 3 sqrt(lambda_max),
+//                    position uncertainty (px), depth uncertainty
 //   out_i[c][i][7]:  keep, radius, x0, y0, x1, y1, tiles_touched
-//   margin[c][i]:    smallest relative margin over the pair's discrete decisions
+//   margin[c][i]:    smallest margin / uncertainty ratio of the pair's decisions (< 1: near tie)
 int orc_project(const double* theta, int64_t n, const double* cams, int n_cams, double* out_f,
                 int32_t* out_i, double* margin) {
   for (int ci = 0; ci < n_cams; ++ci) {
@@ -395,12 +417,14 @@ int orc_project(const double* theta, int64_t n, const double* cams, int n_cams, 
     for (int64_t i = 0; i < n; ++i) {
       Fwd f;
       project_one(theta + kD * i, c, f);
-      double* of = out_f + ((int64_t)ci * n + i) * 14;
+      double* of = out_f + ((int64_t)ci * n + i) * 16;
       int32_t* oi = out_i + ((int64_t)ci * n + i) * 7;
       of[0] = f.u; of[1] = f.v; of[2] = f.depth; of[3] = f.A; of[4] = f.B; of[5] = f.C;
       of[6] = f.op; of[7] = f.rgb[0]; of[8] = f.rgb[1]; of[9] = f.rgb[2];
       of[10] = f.s00; of[11] = f.s01; of[12] = f.s11;
       of[13] = f.rr;
+      of[14] = f.perr;
+      of[15] = f.derr;
       oi[0] = f.keep; oi[1] = f.r; oi[2] = f.rect[0]; oi[3] = f.rect[1]; oi[4] = f.rect[2];
       oi[5] = f.rect[3]; oi[6] = f.keep ? f.tt : 0;
       if (margin) margin[(int64_t)ci * n + i] = f.margin;
@@ -447,13 +471,15 @@ int64_t orc_bin(const double* u, const double* v, const double* depth, const int
 }
 
 // Compositing, O7, over given per-tile lists.  rec[c][i][9] = u, v, A, B, C,
-// opacity, r, g, b.  All cameras share W and H.  Outputs per camera:
-// image[c][3][H][W], t_final[c][H][W], last[c][H][W], visits[c][H][W]
-// (entries evaluated per pixel, including the one that stops it), and the
-// smallest relative margin of the pixel's alpha / transmittance decisions.
+// opacity, r, g, b; unc[c][i][3] = depth, position uncertainty (px), depth
+// uncertainty (used only for the near-tie margins).  All cameras share W
+// and H.  Outputs per camera: image[c][3][H][W], t_final[c][H][W],
+// last[c][H][W], visits[c][H][W] (entries evaluated per pixel, including the
+// one that stops it), and the smallest margin / uncertainty ratio of the
+// pixel's depth-order, alpha and transmittance decisions (< 1: near tie).
 int orc_composite(const int64_t* gid, const int64_t* ranges, const double* rec, int64_t n,
                   const double* cams, int n_cams, const double* bg, double* image, double* t_final,
-                  int32_t* last, int64_t* visits, double* pmargin) {
+                  int32_t* last, int64_t* visits, double* pmargin, const double* unc) {
   int64_t tile_base = 0;
   for (int ci = 0; ci < n_cams; ++ci) {
     const Cam c = load_cam(cams + 20 * ci);
@@ -462,7 +488,8 @@ int orc_composite(const int64_t* gid, const int64_t* ranges, const double* rec, 
     std::vector<Rec> R(n);
     for (int64_t i = 0; i < n; ++i) {
       const double* q = rec + ((int64_t)ci * n + i) * 9;
-      R[i] = Rec{q[0], q[1], q[2], q[3], q[4], q[5], {q[6], q[7], q[8]}};
+      const double* e = unc + ((int64_t)ci * n + i) * 3;   // depth, perr, derr
+      R[i] = Rec{q[0], q[1], q[2], q[3], q[4], q[5], {q[6], q[7], q[8]}, e[0], e[1], e[2]};
     }
 #pragma omp parallel for schedule(dynamic)
     for (int t = 0; t < Tx * Ty; ++t) {
@@ -481,15 +508,16 @@ int orc_composite(const int64_t* gid, const int64_t* ranges, const double* rec, 
 int orc_render(const double* theta, int64_t n, const double* cams, int n_cams, const double* bg,
                double* image, double* t_final, int32_t* last, int64_t* visits, double* pair_margin,
                double* pix_margin, int32_t* keep_out) {
-  std::vector<double> pf((size_t)n_cams * n * 14);
+  std::vector<double> pf((size_t)n_cams * n * 16);
   std::vector<int32_t> pi((size_t)n_cams * n * 7);
   orc_project(theta, n, cams, n_cams, pf.data(), pi.data(), pair_margin);
-  std::vector<double> u(n_cams * n), v(n_cams * n), d(n_cams * n), rec(n_cams * n * 9);
+  std::vector<double> u(n_cams * n), v(n_cams * n), d(n_cams * n), rec(n_cams * n * 9), unc(n_cams * n * 3);
   std::vector<int32_t> r(n_cams * n), k(n_cams * n);
   for (int64_t q = 0; q < n_cams * n; ++q) {
-    u[q] = pf[14 * q]; v[q] = pf[14 * q + 1]; d[q] = pf[14 * q + 2];
+    u[q] = pf[16 * q]; v[q] = pf[16 * q + 1]; d[q] = pf[16 * q + 2];
     r[q] = pi[7 * q + 1]; k[q] = pi[7 * q];
-    for (int j = 0; j < 9; ++j) rec[9 * q + j] = pf[14 * q + (j < 2 ? j : j + 1)];
+    for (int j = 0; j < 9; ++j) rec[9 * q + j] = pf[16 * q + (j < 2 ? j : j + 1)];
+    unc[3 * q] = d[q]; unc[3 * q + 1] = pf[16 * q + 14]; unc[3 * q + 2] = pf[16 * q + 15];
     if (keep_out) keep_out[q] = k[q];
   }
   int64_t tiles = 0;
@@ -503,7 +531,7 @@ int orc_render(const double* theta, int64_t n, const double* cams, int n_cams, c
   std::vector<int64_t> gid(std::max<int64_t>(m, 1));
   orc_bin(u.data(), v.data(), d.data(), r.data(), k.data(), n, cams, n_cams, gid.data(), m, ranges.data());
   orc_composite(gid.data(), ranges.data(), rec.data(), n, cams, n_cams, bg, image, t_final, last, visits,
-                pix_margin);
+                pix_margin, unc.data());
   return 0;
 }
 
@@ -583,7 +611,8 @@ int orc_backward(const double* theta, int64_t n, const double* cams, int n_cams,
     std::vector<Rec> R(n);
     for (int64_t i = 0; i < n; ++i) {
       u[i] = F[i].u; v[i] = F[i].v; d[i] = F[i].depth; r[i] = F[i].r; k[i] = F[i].keep;
-      R[i] = Rec{F[i].u, F[i].v, F[i].A, F[i].B, F[i].C, F[i].op, {F[i].rgb[0], F[i].rgb[1], F[i].rgb[2]}};
+      R[i] = Rec{F[i].u, F[i].v, F[i].A, F[i].B, F[i].C, F[i].op, {F[i].rgb[0], F[i].rgb[1], F[i].rgb[2]},
+                 F[i].depth, F[i].perr, F[i].derr};
     }
     std::vector<Inst> insts;
     bin_camera(c, n, u.data(), v.data(), d.data(), r.data(), k.data(), insts);

@@ -85,6 +85,8 @@ SIGNATURES = {
                                     _P(tide_frame), _P(C.c_float), _vp, _vp, C.c_int64, _vp, C.c_size_t, _vp]),
     "tide_adam_sparse": (C.c_int32, [_P(tide_pool), _P(tide_proj), _vp, C.c_int64, _P(tide_adam_cfg), _vp, _vp,
                                      C.c_int64, _vp]),
+    "tide_timer_arm": (C.c_int32, [C.c_char_p, _vp, _vp]),
+    "tide_timer_clear": (C.c_int32, []),
 }
 
 _lib = None

@@ -101,16 +101,16 @@ extern "C" tide_status tide_adam_sparse(tide_pool* pool, const tide_proj* proj, 
     AdamK<float> K;
     for (int j = 0; j < kD; ++j) K.lr[j] = cfg->lr[j];
     K.b1 = cfg->beta1; K.b2 = cfg->beta2; K.eps = cfg->eps; K.kappa = cfg->kappa;
-    hipLaunchKernelGGL(k_adam<float>, grid, dim3(256), 0, st, (float*)pool->params, (float*)pool->exp_avg,
+    TIDE_TIMED("adam", st, hipLaunchKernelGGL(k_adam<float>, grid, dim3(256), 0, st, (float*)pool->params, (float*)pool->exp_avg,
                        (float*)pool->exp_avg_sq, pool->step, pool->order, pool->slot_block, pool->block_rows, n,
-                       proj->active, proj->act_idx, (const float*)grad, grad_ld, K, spheres, dirty);
+                       proj->active, proj->act_idx, (const float*)grad, grad_ld, K, spheres, dirty));
   } else {
     AdamK<double> K;
     for (int j = 0; j < kD; ++j) K.lr[j] = cfg->lr[j];
     K.b1 = cfg->beta1; K.b2 = cfg->beta2; K.eps = cfg->eps; K.kappa = cfg->kappa;
-    hipLaunchKernelGGL(k_adam<double>, grid, dim3(256), 0, st, (double*)pool->params, (double*)pool->exp_avg,
+    TIDE_TIMED("adam", st, hipLaunchKernelGGL(k_adam<double>, grid, dim3(256), 0, st, (double*)pool->params, (double*)pool->exp_avg,
                        (double*)pool->exp_avg_sq, pool->step, pool->order, pool->slot_block, pool->block_rows, n,
-                       proj->active, proj->act_idx, (const double*)grad, grad_ld, K, spheres, dirty);
+                       proj->active, proj->act_idx, (const double*)grad, grad_ld, K, spheres, dirty));
   }
   TIDE_LAUNCH_CHECK("k_adam");
   return TIDE_OK;

@@ -15,6 +15,8 @@ namespace tide {
 // ------------------------------------------------------------ error state
 void set_error(const char* fmt, ...);
 tide_status hip_fail(hipError_t e, const char* what);
+// Records the events armed for `kernel` (tide_timer_arm) on `st`.
+void timer_mark(const char* kernel, hipStream_t st, bool begin);
 
 #define TIDE_CHECK_ARG(cond, ...)          \
   do {                                     \
@@ -28,6 +30,14 @@ tide_status hip_fail(hipError_t e, const char* what);
   do {                                                   \
     hipError_t e_ = (call);                              \
     if (e_ != hipSuccess) return ::tide::hip_fail(e_, #call); \
+  } while (0)
+
+// Launch wrapped by the timing hook: TIDE_TIMED("name", stream, launch...).
+#define TIDE_TIMED(name, st, ...)                \
+  do {                                           \
+    ::tide::timer_mark(name, st, true);          \
+    __VA_ARGS__;                                 \
+    ::tide::timer_mark(name, st, false);         \
   } while (0)
 
 #define TIDE_LAUNCH_CHECK(what)                               \

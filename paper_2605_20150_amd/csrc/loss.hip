@@ -194,19 +194,19 @@ extern "C" tide_status tide_loss(const void* image, const void* target, int32_t 
     float* dm = cv.take<float>(3 * (size_t)n_views * 3 * height * width);
     double* part = cv.take<double>(2 * nblk);
     const Win<float> w = make_window<float>();
-    hipLaunchKernelGGL(k_ssim_fwd<float>, grid, dim3(256), 0, st, (const float*)image, (const float*)target, height,
-                       width, w, dm, part);
-    hipLaunchKernelGGL(k_ssim_bwd<float>, grid, dim3(256), 0, st, (const float*)image, (const float*)target, dm,
-                       height, width, w, (float)(1.0 / n_all), (float*)d_dimage);
+    TIDE_TIMED("loss_fwd", st, hipLaunchKernelGGL(k_ssim_fwd<float>, grid, dim3(256), 0, st, (const float*)image, (const float*)target, height,
+                       width, w, dm, part));
+    TIDE_TIMED("loss_bwd", st, hipLaunchKernelGGL(k_ssim_bwd<float>, grid, dim3(256), 0, st, (const float*)image, (const float*)target, dm,
+                       height, width, w, (float)(1.0 / n_all), (float*)d_dimage));
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, part, nblk, 1.0 / n_all, d_loss);
   } else {
     double* dm = cv.take<double>(3 * (size_t)n_views * 3 * height * width);
     double* part = cv.take<double>(2 * nblk);
     const Win<double> w = make_window<double>();
-    hipLaunchKernelGGL(k_ssim_fwd<double>, grid, dim3(256), 0, st, (const double*)image, (const double*)target,
-                       height, width, w, dm, part);
-    hipLaunchKernelGGL(k_ssim_bwd<double>, grid, dim3(256), 0, st, (const double*)image, (const double*)target, dm,
-                       height, width, w, 1.0 / n_all, (double*)d_dimage);
+    TIDE_TIMED("loss_fwd", st, hipLaunchKernelGGL(k_ssim_fwd<double>, grid, dim3(256), 0, st, (const double*)image, (const double*)target,
+                       height, width, w, dm, part));
+    TIDE_TIMED("loss_bwd", st, hipLaunchKernelGGL(k_ssim_bwd<double>, grid, dim3(256), 0, st, (const double*)image, (const double*)target, dm,
+                       height, width, w, 1.0 / n_all, (double*)d_dimage));
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, part, nblk, 1.0 / n_all, d_loss);
   }
   TIDE_LAUNCH_CHECK("tide_loss");

@@ -115,8 +115,8 @@ void radix_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, in
     for (int shift = 0; shift < bits; shift += 8) {
       hipLaunchKernelGGL(k_radix_hist, dim3((uint32_t)nb), dim3(kSortThreads), 0, st, ki, n, shift, hist, nb);
       scan_exclusive(ArrayIn{hist}, 256 * nb, hist, partial, total, st);
-      hipLaunchKernelGGL(k_radix_scatter, dim3((uint32_t)nb), dim3(kSortThreads), 0, st, ki,
-                         ident ? nullptr : vi, n, shift, hist, nb, ko, vo);
+      TIDE_TIMED("radix_scatter", st, hipLaunchKernelGGL(k_radix_scatter, dim3((uint32_t)nb), dim3(kSortThreads), 0, st, ki,
+                         ident ? nullptr : vi, n, shift, hist, nb, ko, vo));
       ident = false;
       uint32_t* t = ki; ki = ko; ko = t;
       t = vi; vi = vo; vo = t;

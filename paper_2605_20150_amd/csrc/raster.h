@@ -11,6 +11,7 @@ constexpr int kRec = 12;  // u, v, A, B, C, opacity, r, g, b, depth, radius, 0
 
 template <typename T>
 struct DevCam {
+  double Rd[9], td[3], fxd, fyd, cxd, cyd;  // projection of the mean runs in double
   T R[9], t[3];
   T fx, fy, cx, cy;
   T znear, zfar;

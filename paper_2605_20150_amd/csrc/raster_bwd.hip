@@ -404,38 +404,38 @@ extern "C" tide_status tide_render_bwd(const tide_pool* pool, const tide_camera*
   if (proj->dtype == TIDE_F32) {
     float* partial = cv.take<float>((size_t)(bins->n_inst > 0 ? bins->n_inst : 1) * kG2);
     float* g2d = cv.take<float>((size_t)kG2 * nrec);
-    hipLaunchKernelGGL(k_render_bwd<float>, dim3(grid), dim3(64), 0, st, bins->ranges, bins->inst_e, bins->inst_rec,
+    TIDE_TIMED("render_bwd", st, hipLaunchKernelGGL(k_render_bwd<float>, dim3(grid), dim3(64), 0, st, bins->ranges, bins->inst_e, bins->inst_rec,
                        (const float*)proj->rec, bins->tiles_x, bins->tiles_y, fr->width, fr->height, bg[0], bg[1],
-                       bg[2], (const float*)fr->t_final, fr->last, (const float*)d_dimage, partial);
+                       bg[2], (const float*)fr->t_final, fr->last, (const float*)d_dimage, partial));
     TIDE_LAUNCH_CHECK("k_render_bwd");
     if (bins->n_vis > 0)
-      hipLaunchKernelGGL(k_reduce_pairs<float>, dim3((uint32_t)ceil_div(bins->n_vis, 256)), dim3(256), 0, st,
-                         bins->vis_rec, bins->inst_off, bins->n_vis, nrec, (const float*)partial, g2d);
+      TIDE_TIMED("reduce_pairs", st, hipLaunchKernelGGL(k_reduce_pairs<float>, dim3((uint32_t)ceil_div(bins->n_vis, 256)), dim3(256), 0, st,
+                         bins->vis_rec, bins->inst_off, bins->n_vis, nrec, (const float*)partial, g2d));
     TIDE_LAUNCH_CHECK("k_reduce_pairs");
     const CamSet<float> cs = make_camset<float>(cams, n_cams);
     if (proj->n_pidx > 0)
-      hipLaunchKernelGGL(k_adjoint<float>, dim3((uint32_t)ceil_div(proj->n_pidx, 128)), dim3(128), 0, st,
+      TIDE_TIMED("adjoint", st, hipLaunchKernelGGL(k_adjoint<float>, dim3((uint32_t)ceil_div(proj->n_pidx, 128)), dim3(128), 0, st,
                          (const float*)pool->params, pool->order, pool->block_rows, proj->n_pidx, cs,
-                         proj->tiles_touched, proj->active, proj->act_idx, (const float*)g2d, (float*)grad, grad_ld);
+                         proj->tiles_touched, proj->active, proj->act_idx, (const float*)g2d, (float*)grad, grad_ld));
     TIDE_LAUNCH_CHECK("k_adjoint");
   } else {
     double* partial = cv.take<double>((size_t)(bins->n_inst > 0 ? bins->n_inst : 1) * kG2);
     double* g2d = cv.take<double>((size_t)kG2 * nrec);
-    hipLaunchKernelGGL(k_render_bwd<double>, dim3(grid), dim3(64), 0, st, bins->ranges, bins->inst_e,
+    TIDE_TIMED("render_bwd", st, hipLaunchKernelGGL(k_render_bwd<double>, dim3(grid), dim3(64), 0, st, bins->ranges, bins->inst_e,
                        bins->inst_rec, (const double*)proj->rec, bins->tiles_x, bins->tiles_y, fr->width,
                        fr->height, (double)bg[0], (double)bg[1], (double)bg[2], (const double*)fr->t_final,
-                       fr->last, (const double*)d_dimage, partial);
+                       fr->last, (const double*)d_dimage, partial));
     TIDE_LAUNCH_CHECK("k_render_bwd");
     if (bins->n_vis > 0)
-      hipLaunchKernelGGL(k_reduce_pairs<double>, dim3((uint32_t)ceil_div(bins->n_vis, 256)), dim3(256), 0, st,
-                         bins->vis_rec, bins->inst_off, bins->n_vis, nrec, (const double*)partial, g2d);
+      TIDE_TIMED("reduce_pairs", st, hipLaunchKernelGGL(k_reduce_pairs<double>, dim3((uint32_t)ceil_div(bins->n_vis, 256)), dim3(256), 0, st,
+                         bins->vis_rec, bins->inst_off, bins->n_vis, nrec, (const double*)partial, g2d));
     TIDE_LAUNCH_CHECK("k_reduce_pairs");
     const CamSet<double> cs = make_camset<double>(cams, n_cams);
     if (proj->n_pidx > 0)
-      hipLaunchKernelGGL(k_adjoint<double>, dim3((uint32_t)ceil_div(proj->n_pidx, 128)), dim3(128), 0, st,
+      TIDE_TIMED("adjoint", st, hipLaunchKernelGGL(k_adjoint<double>, dim3((uint32_t)ceil_div(proj->n_pidx, 128)), dim3(128), 0, st,
                          (const double*)pool->params, pool->order, pool->block_rows, proj->n_pidx, cs,
                          proj->tiles_touched, proj->active, proj->act_idx, (const double*)g2d, (double*)grad,
-                         grad_ld);
+                         grad_ld));
     TIDE_LAUNCH_CHECK("k_adjoint");
   }
   return TIDE_OK;

@@ -19,6 +19,9 @@ CamSet<T> make_camset(const tide_camera* cams, int n) {
     DevCam<T>& d = s.c[i];
     for (int k = 0; k < 9; ++k) d.R[k] = (T)c.R[k];
     for (int k = 0; k < 3; ++k) d.t[k] = (T)c.t[k];
+    for (int k = 0; k < 9; ++k) d.Rd[k] = c.R[k];
+    for (int k = 0; k < 3; ++k) d.td[k] = c.t[k];
+    d.fxd = c.fx; d.fyd = c.fy; d.cxd = c.cx; d.cyd = c.cy;
     d.fx = (T)c.fx; d.fy = (T)c.fy; d.cx = (T)c.cx; d.cy = (T)c.cy;
     d.znear = (T)c.z_near; d.zfar = (T)c.z_far;
     d.limx = (T)(1.3 * 0.5 * c.width / c.fx);
@@ -49,7 +52,15 @@ template CamSet<double> make_camset<double>(const tide_camera*, int);
 // One thread per processing index.  The mean (12 B) is read first and every
 // camera's depth test runs on it; the other 56 columns are read only if some
 // camera keeps the Gaussian.  Columns of a block are contiguous, so lanes
-// (consecutive rows) read coalesced.
+// (consecutive rows) read coalesced.  The camera-space position and the
+// pixel position are computed in double: at aerial scales (|p| ~ 300 m,
+// f ~ 1700 px) single precision would put ~3e-4 px of error on u, v, which a
+// sub-pixel footprint turns into flipped alpha >= 1/255 decisions; rounding
+// the double result once leaves at most half an ulp of u.  This costs a few
+// FP64 operations per (Gaussian, camera) in a bandwidth-bound kernel.
+__device__ inline double cam_depth(const double* Rd, const double* td, double m0, double m1, double m2) {
+  return Rd[6] * m0 + Rd[7] * m1 + Rd[8] * m2 + td[2];
+}
 template <typename T>
 __global__ void __launch_bounds__(256) k_preprocess(const T* __restrict__ params, const int32_t* __restrict__ order,
                                                     const int32_t* __restrict__ slot_rows, int32_t B,
@@ -70,8 +81,8 @@ __global__ void __launch_bounds__(256) k_preprocess(const T* __restrict__ params
 #pragma unroll 1
     for (int c = 0; c < ncam; ++c) {
       const DevCam<T>& cm = cs.c[c];
-      const T pz = cm.R[6] * mu[0] + cm.R[7] * mu[1] + cm.R[8] * mu[2] + cm.t[2];
-      if (pz > cm.znear && pz <= cm.zfar) keep |= 1u << c;
+      const double pz = cam_depth(cm.Rd, cm.td, (double)mu[0], (double)mu[1], (double)mu[2]);
+      if (pz > (double)cm.znear && pz <= (double)cm.zfar) keep |= 1u << c;
     }
   }
   uint32_t any = 0;
@@ -106,12 +117,15 @@ __global__ void __launch_bounds__(256) k_preprocess(const T* __restrict__ params
       uint32_t ntt = 0;
       if (keep & (1u << c)) {
         const DevCam<T>& cm = cs.c[c];
-        const T px = cm.R[0] * mu[0] + cm.R[1] * mu[1] + cm.R[2] * mu[2] + cm.t[0];
-        const T py = cm.R[3] * mu[0] + cm.R[4] * mu[1] + cm.R[5] * mu[2] + cm.t[1];
-        const T pz = cm.R[6] * mu[0] + cm.R[7] * mu[1] + cm.R[8] * mu[2] + cm.t[2];
-        const T iz = (T)1 / pz;
-        const T u = cm.fx * px * iz + cm.cx;
-        const T v = cm.fy * py * iz + cm.cy;
+        const double m0 = mu[0], m1 = mu[1], m2 = mu[2];
+        const double pxd = cm.Rd[0] * m0 + cm.Rd[1] * m1 + cm.Rd[2] * m2 + cm.td[0];
+        const double pyd = cm.Rd[3] * m0 + cm.Rd[4] * m1 + cm.Rd[5] * m2 + cm.td[1];
+        const double pzd = cam_depth(cm.Rd, cm.td, m0, m1, m2);
+        const double izd = 1.0 / pzd;
+        const T u = (T)(cm.fxd * pxd * izd + cm.cxd);
+        const T v = (T)(cm.fyd * pyd * izd + cm.cyd);
+        const T px = (T)pxd, py = (T)pyd, pz = (T)pzd;
+        const T iz = (T)izd;
         T xi = px * iz, eta = py * iz;
         xi = xi < -cm.limx ? -cm.limx : (xi > cm.limx ? cm.limx : xi);
         eta = eta < -cm.limy ? -cm.limy : (eta > cm.limy ? cm.limy : eta);
@@ -161,7 +175,7 @@ __global__ void __launch_bounds__(256) k_preprocess(const T* __restrict__ params
             R12[7] = col[1] > 0 ? col[1] : (T)0;
             R12[8] = col[2] > 0 ? col[2] : (T)0;
             R12[9] = pz; R12[10] = (T)r; R12[11] = 0;
-            depth[o] = (float)pz;
+            depth[o] = (float)pzd;
             rect[2 * o] = (uint32_t)x0 | ((uint32_t)y0 << 16);
             rect[2 * o + 1] = (uint32_t)x1 | ((uint32_t)y1 << 16);
           }
@@ -186,9 +200,9 @@ static tide_status preprocess_t(const tide_pool* pool, const tide_camera* cams, 
   const CamSet<T> cs = make_camset<T>(cams, n_cams);
   const int64_t n = out->n_pidx;
   if (n > 0) {
-    hipLaunchKernelGGL(k_preprocess<T>, dim3((uint32_t)ceil_div(n, 256)), dim3(256), 0, st,
+    TIDE_TIMED("preprocess", st, hipLaunchKernelGGL(k_preprocess<T>, dim3((uint32_t)ceil_div(n, 256)), dim3(256), 0, st,
                        (const T*)pool->params, pool->order, pool->slot_rows, pool->block_rows, n, cs,
-                       (T*)out->rec, out->depth, out->rect, out->tiles_touched, out->active);
+                       (T*)out->rec, out->depth, out->rect, out->tiles_touched, out->active));
     TIDE_LAUNCH_CHECK("k_preprocess");
   }
   Carver cv(ws);
@@ -452,8 +466,8 @@ extern "C" tide_status tide_bin_sort(const tide_proj* proj, int32_t tiles_x, int
   // 1. visible pairs, compacted in (camera, pidx) order, keyed by depth bits
   scan_exclusive(NonzeroIn{proj->tiles_touched}, nv, L.vis_off, L.partial, &L.totals[0], st);
   if (nv > 0)
-    hipLaunchKernelGGL(k_compact_vis, dim3((uint32_t)ceil_div(nv, 256)), dim3(256), 0, st, proj->tiles_touched,
-                       proj->depth, L.vis_off, nv, L.ka, L.va);
+    TIDE_TIMED("compact_vis", st, hipLaunchKernelGGL(k_compact_vis, dim3((uint32_t)ceil_div(nv, 256)), dim3(256), 0, st, proj->tiles_touched,
+                       proj->depth, L.vis_off, nv, L.ka, L.va));
   TIDE_LAUNCH_CHECK("visibility compaction");
   unsigned long long h_tot[2] = {0, 0};
   TIDE_HIP(hipMemcpyAsync(&h_tot[0], &L.totals[0], 8, hipMemcpyDeviceToHost, st));
@@ -482,8 +496,8 @@ extern "C" tide_status tide_bin_sort(const tide_proj* proj, int32_t tiles_x, int
   }
   // 4. emit instances in depth order, keyed by global tile id
   if (n_vis > 0)
-    hipLaunchKernelGGL(k_emit, dim3((uint32_t)ceil_div(n_vis, 256)), dim3(256), 0, st, vrec, L.inst_off, proj->rect,
-                       n_vis, N, tiles_x, tiles_y, L.tka, L.inst_rec);
+    TIDE_TIMED("emit", st, hipLaunchKernelGGL(k_emit, dim3((uint32_t)ceil_div(n_vis, 256)), dim3(256), 0, st, vrec, L.inst_off, proj->rect,
+                       n_vis, N, tiles_x, tiles_y, L.tka, L.inst_rec));
   TIDE_LAUNCH_CHECK("k_emit");
   // 5. stable sort by tile; values are emission indices
   int bits = 0;
@@ -524,14 +538,14 @@ extern "C" tide_status tide_render_fwd(const tide_proj* proj, const tide_bins* b
   hipStream_t st = (hipStream_t)stream;
   const uint32_t grid = (uint32_t)(bins->n_cams * bins->tiles_x * bins->tiles_y);
   if (proj->dtype == TIDE_F32)
-    hipLaunchKernelGGL(k_render_fwd<float>, dim3(grid), dim3(64), 0, st, bins->ranges, bins->inst_e, bins->inst_rec,
+    TIDE_TIMED("render_fwd", st, hipLaunchKernelGGL(k_render_fwd<float>, dim3(grid), dim3(64), 0, st, bins->ranges, bins->inst_e, bins->inst_rec,
                        (const float*)proj->rec, bins->tiles_x, bins->tiles_y, fr->width, fr->height, bg[0], bg[1],
-                       bg[2], (float*)fr->image, (float*)fr->t_final, fr->last, fr->visits);
+                       bg[2], (float*)fr->image, (float*)fr->t_final, fr->last, fr->visits));
   else
-    hipLaunchKernelGGL(k_render_fwd<double>, dim3(grid), dim3(64), 0, st, bins->ranges, bins->inst_e,
+    TIDE_TIMED("render_fwd", st, hipLaunchKernelGGL(k_render_fwd<double>, dim3(grid), dim3(64), 0, st, bins->ranges, bins->inst_e,
                        bins->inst_rec, (const double*)proj->rec, bins->tiles_x, bins->tiles_y, fr->width,
                        fr->height, (double)bg[0], (double)bg[1], (double)bg[2], (double*)fr->image,
-                       (double*)fr->t_final, fr->last, fr->visits);
+                       (double*)fr->t_final, fr->last, fr->visits));
   TIDE_LAUNCH_CHECK("k_render_fwd");
   return TIDE_OK;
 }
