@@ -32,7 +32,7 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 FLOPS_PER_FWD_VISIT = 21      # offset 2, exponent 8, exp 1, alpha 1, transmittance 2, weight 1, colour 6
 FLOPS_PER_BWD_VISIT = 64      # the forward terms plus T recovery, colour/alpha/conic/mean adjoints
 KERNELS = ["preprocess", "compact_vis", "emit", "render_fwd", "loss_fwd", "loss_bwd", "render_bwd",
-           "reduce_pairs", "adjoint", "adam"]
+           "reduce_pairs", "reduce_big", "adjoint", "adam"]
 
 
 def parse():
@@ -58,8 +58,8 @@ def algorithmic_bytes(kernel, n_pidx, n_kept, n_vis, n_inst, n_active, pixels, V
         return n_vis * (4 + 8 + 36) + n_inst * 36
     if kernel == "adjoint":
         return n_active * (236 + 236 + 8) + n_vis * 36
-    if kernel == "adam":
-        return n_active * (7 * 236 + 12)
+    if kernel == "adam":   # the column pass: p, m, v read + written, g read
+        return n_active * (7 * 236)
     if kernel in ("loss_fwd",):
         return pixels * 3 * (4 + 4 + 12)
     if kernel in ("loss_bwd",):

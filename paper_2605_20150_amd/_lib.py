@@ -83,8 +83,9 @@ SIGNATURES = {
     "tide_render_bwd_ws_bytes": (C.c_size_t, [_P(tide_bins), C.c_int32]),
     "tide_render_bwd": (C.c_int32, [_P(tide_pool), _P(tide_camera), C.c_int32, _P(tide_proj), _P(tide_bins),
                                     _P(tide_frame), _P(C.c_float), _vp, _vp, C.c_int64, _vp, C.c_size_t, _vp]),
+    "tide_adam_ws_bytes": (C.c_size_t, [C.c_int64]),
     "tide_adam_sparse": (C.c_int32, [_P(tide_pool), _P(tide_proj), _vp, C.c_int64, _P(tide_adam_cfg), _vp, _vp,
-                                     C.c_int64, _vp]),
+                                     C.c_int64, _vp, C.c_size_t, _vp]),
     "tide_timer_arm": (C.c_int32, [C.c_char_p, _vp, _vp]),
     "tide_timer_clear": (C.c_int32, []),
 }

@@ -72,6 +72,7 @@ struct Mth<float> {
   __device__ static float exp(float x) { return __expf(x); }
   __device__ static float sqrt(float x) { return sqrtf(x); }
   __device__ static float rcp(float x) { return __frcp_rn(x); }
+  __device__ static float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
   __device__ static float ceil(float x) { return ceilf(x); }
   __device__ static float floor(float x) { return floorf(x); }
 };
@@ -81,6 +82,7 @@ struct Mth<double> {
   __device__ static double exp(double x) { return ::exp(x); }
   __device__ static double sqrt(double x) { return ::sqrt(x); }
   __device__ static double rcp(double x) { return 1.0 / x; }
+  __device__ static double rcp_fast(double x) { return 1.0 / x; }
   __device__ static double ceil(double x) { return ::ceil(x); }
   __device__ static double floor(double x) { return ::floor(x); }
 };

@@ -39,9 +39,19 @@ struct GatherIn {  // a[idx[i]]
   __device__ uint32_t operator()(int64_t i) const { return a[idx[i]]; }
 };
 
+// Element counts: n_max bounds the launch; when d_n is given the kernels
+// read the actual count from device memory (n = min(n_max, *d_n)), which
+// lets a pipeline size its grids without a host round trip.
+__device__ inline int64_t dev_count(int64_t n_max, const unsigned long long* d_n) {
+  if (!d_n) return n_max;
+  const int64_t n = (int64_t)*d_n;
+  return n < n_max ? n : n_max;
+}
+
 template <typename In>
-__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(In in, int64_t n,
+__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(In in, int64_t n_max, const unsigned long long* d_n,
                                                               unsigned long long* partial) {
+  const int64_t n = dev_count(n_max, d_n);
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   unsigned long long s = 0;
 #pragma unroll
@@ -63,9 +73,10 @@ __global__ void __launch_bounds__(1024) k_scan_partials(unsigned long long* part
                                                         unsigned long long* total);
 
 template <typename In>
-__global__ void __launch_bounds__(kScanThreads) k_scan_down(In in, int64_t n,
+__global__ void __launch_bounds__(kScanThreads) k_scan_down(In in, int64_t n_max, const unsigned long long* d_n,
                                                             const unsigned long long* partial,
                                                             uint32_t* out) {
+  const int64_t n = dev_count(n_max, d_n);
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   uint32_t v[kScanItems];
   uint32_t s = 0;
@@ -91,27 +102,28 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_down(In in, int64_t n,
 }
 
 // Exclusive scan of in(0..n) into out; total (u64, device) receives the sum.
-// partial needs ceil(n/4096) u64 entries.
+// partial needs ceil(n_max/4096) u64 entries; d_n as for dev_count.
 template <typename In>
 inline void scan_exclusive(In in, int64_t n, uint32_t* out, unsigned long long* partial,
-                           unsigned long long* total, hipStream_t st) {
+                           unsigned long long* total, hipStream_t st, const unsigned long long* d_n = nullptr) {
   const int64_t nb = ceil_div(n > 0 ? n : 1, kScanTile);
-  hipLaunchKernelGGL(k_scan_reduce<In>, dim3((uint32_t)nb), dim3(kScanThreads), 0, st, in, n, partial);
+  hipLaunchKernelGGL(k_scan_reduce<In>, dim3((uint32_t)nb), dim3(kScanThreads), 0, st, in, n, d_n, partial);
   hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, partial, nb, total);
-  hipLaunchKernelGGL(k_scan_down<In>, dim3((uint32_t)nb), dim3(kScanThreads), 0, st, in, n,
+  hipLaunchKernelGGL(k_scan_down<In>, dim3((uint32_t)nb), dim3(kScanThreads), 0, st, in, n, d_n,
                      (const unsigned long long*)partial, out);
 }
 
 inline size_t scan_partial_count(int64_t n) { return (size_t)ceil_div(n > 0 ? n : 1, kScanTile); }
 
 // ------------------------------------------------------------- radix sort
-__global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint32_t* keys, int64_t n, int shift,
+__global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint32_t* keys, int64_t n_max,
+                                                             const unsigned long long* d_n, int shift,
                                                              uint32_t* ghist, int64_t nb);
 __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint32_t* keys_in,
-                                                                const uint32_t* vals_in, int64_t n,
-                                                                int shift, const uint32_t* gofs,
-                                                                int64_t nb, uint32_t* keys_out,
-                                                                uint32_t* vals_out);
+                                                                const uint32_t* vals_in, int64_t n_max,
+                                                                const unsigned long long* d_n, int shift,
+                                                                const uint32_t* gofs, int64_t nb,
+                                                                uint32_t* keys_out, uint32_t* vals_out);
 
 inline size_t radix_hist_count(int64_t n) { return 256 * (size_t)ceil_div(n > 0 ? n : 1, kSortTile); }
 
@@ -124,6 +136,6 @@ inline size_t radix_hist_count(int64_t n) { return 256 * (size_t)ceil_div(n > 0 
 void radix_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int64_t n, int bits,
                       bool identity_vals, uint32_t* hist, unsigned long long* partial,
                       unsigned long long* total, hipStream_t st, uint32_t** keys_res,
-                      uint32_t** vals_res);
+                      uint32_t** vals_res, const unsigned long long* d_n = nullptr);
 
 }  // namespace tide

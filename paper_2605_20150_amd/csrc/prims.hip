@@ -31,8 +31,10 @@ __global__ void __launch_bounds__(1024) k_scan_partials(unsigned long long* part
   if (threadIdx.x == 0) *total = carry;
 }
 
-__global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint32_t* keys, int64_t n, int shift,
+__global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint32_t* keys, int64_t n_max,
+                                                             const unsigned long long* d_n, int shift,
                                                              uint32_t* ghist, int64_t nb) {
+  const int64_t n = dev_count(n_max, d_n);
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0;
   __syncthreads();
@@ -47,10 +49,12 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint32_t* key
 }
 
 __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint32_t* keys_in,
-                                                                const uint32_t* vals_in, int64_t n,
-                                                                int shift, const uint32_t* gofs,
-                                                                int64_t nb, uint32_t* keys_out,
-                                                                uint32_t* vals_out) {
+                                                                const uint32_t* vals_in, int64_t n_max,
+                                                                const unsigned long long* d_n, int shift,
+                                                                const uint32_t* gofs, int64_t nb,
+                                                                uint32_t* keys_out, uint32_t* vals_out) {
+  const int64_t n = dev_count(n_max, d_n);
+  if ((int64_t)blockIdx.x * kSortTile >= n) return;
   __shared__ uint32_t wcnt[kSortWaves][256];
   __shared__ uint32_t gbase[256];
   for (int k = threadIdx.x; k < kSortWaves * 256; k += kSortThreads) (&wcnt[0][0])[k] = 0;
@@ -107,16 +111,16 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint32_t* 
 void radix_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int64_t n, int bits,
                       bool identity_vals, uint32_t* hist, unsigned long long* partial,
                       unsigned long long* total, hipStream_t st, uint32_t** keys_res,
-                      uint32_t** vals_res) {
+                      uint32_t** vals_res, const unsigned long long* d_n) {
   uint32_t *ki = ka, *vi = va, *ko = kb, *vo = vb;
   bool ident = identity_vals;
   const int64_t nb = ceil_div(n > 0 ? n : 1, kSortTile);
   if (n > 0) {
     for (int shift = 0; shift < bits; shift += 8) {
-      hipLaunchKernelGGL(k_radix_hist, dim3((uint32_t)nb), dim3(kSortThreads), 0, st, ki, n, shift, hist, nb);
+      hipLaunchKernelGGL(k_radix_hist, dim3((uint32_t)nb), dim3(kSortThreads), 0, st, ki, n, d_n, shift, hist, nb);
       scan_exclusive(ArrayIn{hist}, 256 * nb, hist, partial, total, st);
       TIDE_TIMED("radix_scatter", st, hipLaunchKernelGGL(k_radix_scatter, dim3((uint32_t)nb), dim3(kSortThreads), 0, st, ki,
-                         ident ? nullptr : vi, n, shift, hist, nb, ko, vo));
+                         ident ? nullptr : vi, n, d_n, shift, hist, nb, ko, vo));
       ident = false;
       uint32_t* t = ki; ki = ko; ko = t;
       t = vi; vi = vo; vo = t;

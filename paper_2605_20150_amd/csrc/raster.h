@@ -87,19 +87,69 @@ __device__ inline void sh_eval(const ShK<T>& k, T x, T y, T z, T Y[16]) {
   Y[15] = -k.c3a * x * (xx - 3 * yy);
 }
 
+// Exponent scale of the compositing kernels: FP32 folds log2(e) into the
+// conic and evaluates exp2 with the hardware v_exp_f32; FP64 keeps exp.
+template <typename T>
+struct Ex;
+template <>
+struct Ex<float> {
+  static constexpr double k = 1.4426950408889634;  // log2(e)
+  __device__ static float eval(float x) { return __builtin_amdgcn_exp2f(x); }
+};
+template <>
+struct Ex<double> {
+  static constexpr double k = 1.0;
+  __device__ static double eval(double x) { return ::exp(x); }
+};
+
 // Opacity-weighted Gaussian of one list entry at one pixel, shared by the
 // forward and backward kernels so that both take identical skip decisions.
-// Ah = -A/2, Bh = -B, Ch = -C/2 (pre-scaled conic).  Returns false when the
-// entry is skipped (power > 0 or alpha < 1/255); otherwise G = exp(power),
-// araw = opacity * G and alpha = min(0.99, araw).
+// The per-entry terms are prepared once per lane column: with the scaled
+// conic Ah = -A k/2, Bh = -B k, Ch = -C k/2 (k = Ex<T>::k) and dx the pixel
+// offset, adx2 = Ah dx dx and bdx = Bh dx; then power = adx2 + bdx dy +
+// Ch dy dy.  ok is false when the entry is skipped (power > 0 or
+// alpha < 1/255); G = exp(power / k), araw = opacity G, alpha = min(0.99, araw).
 template <typename T>
-__device__ __forceinline__ bool entry_alpha(T Ah, T Bh, T Ch, T op, T dx, T dy, T& G, T& araw, T& alpha) {
-  const T power = Ah * dx * dx + Ch * dy * dy + Bh * dx * dy;
-  if (power > 0) return false;
-  G = Mth<T>::exp(power);
+__device__ __forceinline__ bool entry_alpha(T adx2, T bdx, T Ch, T op, T dy, T& G, T& araw, T& alpha) {
+  const T power = adx2 + dy * (bdx + Ch * dy);
+  G = Ex<T>::eval(power);
   araw = op * G;
   alpha = araw < (T)0.99 ? araw : (T)0.99;
-  return !(alpha < (T)(1.0 / 255.0));
+  return power <= (T)0 && alpha >= (T)(1.0 / 255.0);
+}
+
+// Wave64 sum with DPP row shifts and row broadcasts; the total lands in
+// lane 63 (other lanes hold partial sums).
+template <int CTRL, int ROWS, bool BC>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, BC));
+}
+__device__ __forceinline__ float wave_sum_to_63(float x) {
+  x += dpp_f32<0x111, 0xF, true>(x);   // row_shr:1
+  x += dpp_f32<0x112, 0xF, true>(x);   // row_shr:2
+  x += dpp_f32<0x114, 0xF, true>(x);   // row_shr:4
+  x += dpp_f32<0x118, 0xF, true>(x);   // row_shr:8  -> lane 15 of each row holds its row sum
+  x += dpp_f32<0x142, 0xA, false>(x);  // row_bcast:15 into rows 1 and 3
+  x += dpp_f32<0x143, 0xC, false>(x);  // row_bcast:31 into rows 2 and 3
+  return x;
+}
+__device__ __forceinline__ double wave_sum_to_63(double x) { return wave_sum(x); }
+
+// Sum over each row of 16 lanes; lane 16 r + 15 holds row r's total.
+__device__ __forceinline__ float row_sum_to_15(float x) {
+  x += dpp_f32<0x111, 0xF, true>(x);
+  x += dpp_f32<0x112, 0xF, true>(x);
+  x += dpp_f32<0x114, 0xF, true>(x);
+  x += dpp_f32<0x118, 0xF, true>(x);
+  return x;
+}
+__device__ __forceinline__ double row_sum_to_15(double x) {
+#pragma unroll
+  for (int off = 1; off < 16; off <<= 1) {
+    const double y = __shfl_up(x, off, 16);
+    if ((__lane_id() & 15) >= off) x += y;
+  }
+  return x;
 }
 
 }  // namespace tide

@@ -13,9 +13,11 @@ constexpr int kG2 = 9;  // du, dv, dA, dB, dC, dopacity, dr, dg, db
 // Same lane/pixel layout as the forward.  Each pixel walks back from its
 // last contributor, recovering T_i = T_{i+1} / (1 - alpha_i) and the
 // normalised colour behind the entry (r_{i-1} = alpha_i c_i + (1-alpha_i) r_i,
-// starting from the background).  The four pixels of a lane are summed in
-// registers and the wave is reduced once per entry; entries that no pixel of
-// the tile reaches get zero partials.
+// starting from the background).  The per-pixel update is branch-free; the
+// four pixels of a lane are summed in registers, each row of 16 lanes is
+// reduced with DPP and the four row sums are parked in LDS; once a batch of
+// 64 entries is done, lane k adds entry k's four row sums (fixed order) and
+// stores its partial.  Entries no pixel reaches get zero partials.
 template <typename T>
 __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ ranges,
                                                    const uint32_t* __restrict__ inst_e,
@@ -53,80 +55,102 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
     }
     maxl = lst[q] > maxl ? lst[q] : maxl;
   }
-  // wave max of the last contributors
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
     const uint32_t o = __shfl_xor(maxl, off, kWave);
     maxl = o > maxl ? o : maxl;
   }
   const uint32_t start = ranges[2 * g], end = ranges[2 * g + 1];
-  // entries beyond every pixel's last contributor receive nothing
   for (uint32_t j = start + maxl + lane; j < end; j += 64) {
     T* P = partial + (int64_t)inst_e[j] * kG2;
 #pragma unroll
     for (int m = 0; m < kG2; ++m) P[m] = 0;
   }
-  __shared__ T s_u[64], s_v[64], s_A[64], s_B[64], s_C[64], s_o[64], s_r[64], s_g[64], s_b[64];
-  __shared__ uint32_t s_e[64];
+  __shared__ T s_u[64], s_v[64], s_Ah[64], s_Bh[64], s_Ch[64], s_A[64], s_B[64], s_C[64], s_o[64], s_r[64],
+      s_g[64], s_b[64];
+  __shared__ T s_part[64][4][kG2];
+  __shared__ uint32_t s_hit[64];
+  const T ks = (T)Ex<T>::k;
+  const int row = lane >> 4;
   for (int32_t hi = (int32_t)maxl; hi > 0; hi -= 64) {
     const int32_t lo = hi - 64 > 0 ? hi - 64 : 0;
     const int32_t n = hi - lo;
+    uint32_t my_e = 0;
     if (lane < n) {
-      const uint32_t e = inst_e[start + lo + lane];
-      const T* q = rec + (int64_t)inst_rec[e] * kRec;
-      s_e[lane] = e;
+      my_e = inst_e[start + lo + lane];
+      const T* q = rec + (int64_t)inst_rec[my_e] * kRec;
       s_u[lane] = q[0]; s_v[lane] = q[1];
-      s_A[lane] = (T)-0.5 * q[2]; s_B[lane] = -q[3]; s_C[lane] = (T)-0.5 * q[4];
+      s_A[lane] = q[2]; s_B[lane] = q[3]; s_C[lane] = q[4];
+      s_Ah[lane] = (T)-0.5 * ks * q[2]; s_Bh[lane] = -ks * q[3]; s_Ch[lane] = (T)-0.5 * ks * q[4];
       s_o[lane] = q[5]; s_r[lane] = q[6]; s_g[lane] = q[7]; s_b[lane] = q[8];
     }
     __syncthreads();
     for (int k = n - 1; k >= 0; --k) {
       const uint32_t pos = (uint32_t)(lo + k);
-      const T u = s_u[k], v = s_v[k], Ah = s_A[k], Bh = s_B[k], Ch = s_C[k], op = s_o[k];
+      const T v = s_v[k], Ch = s_Ch[k], op = s_o[k];
+      const T B = s_B[k], C = s_C[k];
       const T cr = s_r[k], cg = s_g[k], cb = s_b[k];
-      const T dx = fxp - u;
-      T a_u = 0, a_v = 0, a_A = 0, a_B = 0, a_C = 0, a_o = 0, a_r = 0, a_g = 0, a_b = 0;
+      const T dx = fxp - s_u[k];
+      const T adx2 = s_Ah[k] * dx * dx, bdx = s_Bh[k] * dx;
+      const T Bdx = B * dx, dx2 = dx * dx;
+      // a lane's four pixels share dx, so the conic and mean gradients are
+      // accumulated as moments of dp over dy and finished once per lane:
+      // d/dA = dx^2 S0, d/dB = dx S1, d/dC = S2 (times -1/2, -1, -1/2 below),
+      // d/du = A dx S0 + B S1, d/dv = B dx S0 + C S1.
+      T S0 = 0, S1 = 0, S2 = 0, a_o = 0, a_r = 0, a_g = 0, a_b = 0;
       bool hit = false;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        if (pos >= lst[q]) continue;
         const T dy = fyp[q] - v;
         T G, araw, alpha;
-        if (!entry_alpha<T>(Ah, Bh, Ch, op, dx, dy, G, araw, alpha)) continue;
-        hit = true;
-        Tr[q] = Tr[q] / ((T)1 - alpha);
-        const T w = alpha * Tr[q];
+        const bool pass = entry_alpha<T>(adx2, bdx, Ch, op, dy, G, araw, alpha);
+        const bool ok = pass && pos < lst[q];
+        const bool okg = ok && araw < (T)0.99;   // alpha clamped at 0.99: no input dependence
+        hit = hit || ok;
+        const T a_ok = ok ? alpha : (T)0;
+        const T G_ok = okg ? G : (T)0;
+        const T r_ok = okg ? araw : (T)0;
+        const T Tn = ok ? Tr[q] * Mth<T>::rcp_fast((T)1 - alpha) : Tr[q];
+        Tr[q] = Tn;
+        const T w = a_ok * Tn;
         a_r += w * g0[q]; a_g += w * g1[q]; a_b += w * g2[q];
-        const T dal = Tr[q] * ((cr - rb0[q]) * g0[q] + (cg - rb1[q]) * g1[q] + (cb - rb2[q]) * g2[q]);
-        const T om = (T)1 - alpha;
-        rb0[q] = alpha * cr + om * rb0[q];
-        rb1[q] = alpha * cg + om * rb1[q];
-        rb2[q] = alpha * cb + om * rb2[q];
-        if (araw < (T)0.99) {
-          a_o += dal * G;
-          const T dp = dal * araw;
-          // A = -2 Ah, B = -Bh, C = -2 Ch
-          a_u += dp * ((T)-2 * Ah * dx - Bh * dy);
-          a_v += dp * (-Bh * dx + (T)-2 * Ch * dy);
-          a_A += dp * ((T)-0.5 * dx * dx);
-          a_B += dp * (-dx * dy);
-          a_C += dp * ((T)-0.5 * dy * dy);
-        }
+        const T d0 = cr - rb0[q], d1 = cg - rb1[q], d2 = cb - rb2[q];
+        const T dal = Tn * (d0 * g0[q] + d1 * g1[q] + d2 * g2[q]);
+        rb0[q] += a_ok * d0; rb1[q] += a_ok * d1; rb2[q] += a_ok * d2;
+        a_o += dal * G_ok;
+        const T dp = dal * r_ok;
+        const T dpdy = dp * dy;
+        S0 += dp; S1 += dpdy; S2 += dpdy * dy;
       }
-      T* P = partial + (int64_t)s_e[k] * kG2;
-      if (__ballot(hit) == 0) {
-        if (lane == 0) {
+      T a_u = s_A[k] * dx * S0 + B * S1;
+      T a_v = Bdx * S0 + C * S1;
+      T a_A = dx2 * S0, a_B = dx * S1, a_C = S2;
+      const bool any_hit = __ballot(hit) != 0;
+      if (lane == 0) s_hit[k] = any_hit ? 1u : 0u;
+      if (!any_hit) continue;
+      a_u = row_sum_to_15(a_u); a_v = row_sum_to_15(a_v); a_A = row_sum_to_15(a_A);
+      a_B = row_sum_to_15(a_B); a_C = row_sum_to_15(a_C); a_o = row_sum_to_15(a_o);
+      a_r = row_sum_to_15(a_r); a_g = row_sum_to_15(a_g); a_b = row_sum_to_15(a_b);
+      if ((lane & 15) == 15) {
+        T* S = s_part[k][row];
+        S[0] = a_u; S[1] = a_v; S[2] = a_A; S[3] = a_B; S[4] = a_C;
+        S[5] = a_o; S[6] = a_r; S[7] = a_g; S[8] = a_b;
+      }
+    }
+    __syncthreads();
+    if (lane < n) {
+      T* P = partial + (int64_t)my_e * kG2;
+      if (s_hit[lane]) {
+        T r[kG2];
 #pragma unroll
-          for (int m = 0; m < kG2; ++m) P[m] = 0;
-        }
-        continue;
-      }
-      a_u = wave_sum(a_u); a_v = wave_sum(a_v); a_A = wave_sum(a_A); a_B = wave_sum(a_B);
-      a_C = wave_sum(a_C); a_o = wave_sum(a_o); a_r = wave_sum(a_r); a_g = wave_sum(a_g);
-      a_b = wave_sum(a_b);
-      if (lane == 0) {
-        P[0] = a_u; P[1] = a_v; P[2] = a_A; P[3] = a_B; P[4] = a_C;
-        P[5] = a_o; P[6] = a_r; P[7] = a_g; P[8] = a_b;
+        for (int m = 0; m < kG2; ++m)
+          r[m] = ((s_part[lane][0][m] + s_part[lane][1][m]) + s_part[lane][2][m]) + s_part[lane][3][m];
+        // dpower/dA = -dx^2/2, dpower/dB = -dx dy, dpower/dC = -dy^2/2
+        P[0] = r[0]; P[1] = r[1]; P[2] = (T)-0.5 * r[2]; P[3] = -r[3]; P[4] = (T)-0.5 * r[4];
+        P[5] = r[5]; P[6] = r[6]; P[7] = r[7]; P[8] = r[8];
+      } else {
+#pragma unroll
+        for (int m = 0; m < kG2; ++m) P[m] = 0;
       }
     }
     __syncthreads();
@@ -136,13 +160,23 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
 // ---------------------------------------------- per-pair reduction (fixed order)
 // Thread s sums the contiguous partials of the s-th depth-ordered visible
 // pair (its tiles in row-major order) and stores them SoA by record index.
+// Pairs with more than kBigPair instances (large footprints) would stall
+// their wave, so they are queued and summed by k_reduce_big, one wave per
+// pair with coalesced loads and a fixed reduction tree.
+constexpr uint32_t kBigPair = 24;
+
 template <typename T>
 __global__ void k_reduce_pairs(const uint32_t* __restrict__ vis_rec, const uint32_t* __restrict__ inst_off,
-                               int64_t n_vis, int64_t n_rec, const T* __restrict__ partial, T* __restrict__ g2d) {
+                               int64_t n_vis, int64_t n_rec, const T* __restrict__ partial, T* __restrict__ g2d,
+                               uint32_t* __restrict__ big_list, uint32_t* __restrict__ big_count) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n_vis) return;
-  const uint32_t r = vis_rec[s];
   const uint32_t e0 = inst_off[s], e1 = inst_off[s + 1];
+  if (e1 - e0 > kBigPair) {
+    big_list[atomicAdd(big_count, 1u)] = (uint32_t)s;
+    return;
+  }
+  const uint32_t r = vis_rec[s];
   T acc[kG2];
 #pragma unroll
   for (int m = 0; m < kG2; ++m) acc[m] = 0;
@@ -154,6 +188,39 @@ __global__ void k_reduce_pairs(const uint32_t* __restrict__ vis_rec, const uint3
 #pragma unroll
   for (int m = 0; m < kG2; ++m) g2d[(int64_t)m * n_rec + r] = acc[m];
 }
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_reduce_big(const uint32_t* __restrict__ vis_rec,
+                                                    const uint32_t* __restrict__ inst_off, int64_t n_rec,
+                                                    const T* __restrict__ partial, T* __restrict__ g2d,
+                                                    const uint32_t* __restrict__ big_list,
+                                                    const uint32_t* __restrict__ big_count) {
+  const uint32_t nbig = *big_count;
+  const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const uint32_t nw = gridDim.x * blockDim.x / kWave;
+  const int lane = __lane_id();
+  for (uint32_t w = wid; w < nbig; w += nw) {
+    const uint32_t s = big_list[w];
+    const uint32_t e0 = inst_off[s], e1 = inst_off[s + 1];
+    T acc[kG2];
+#pragma unroll
+    for (int m = 0; m < kG2; ++m) acc[m] = 0;
+    for (uint32_t e = e0 + lane; e < e1; e += kWave) {
+      const T* P = partial + (int64_t)e * kG2;
+#pragma unroll
+      for (int m = 0; m < kG2; ++m) acc[m] += P[m];
+    }
+#pragma unroll
+    for (int m = 0; m < kG2; ++m) acc[m] = wave_sum(acc[m]);
+    if (lane == 0) {
+      const uint32_t r = vis_rec[s];
+#pragma unroll
+      for (int m = 0; m < kG2; ++m) g2d[(int64_t)m * n_rec + r] = acc[m];
+    }
+  }
+}
+
+__global__ void k_zero_u32(uint32_t* p) { *p = 0u; }
 
 // --------------------------------------------------- preprocess adjoint
 // Thread per processing index; only active rows work.  Recomputes the
@@ -379,7 +446,8 @@ extern "C" size_t tide_render_bwd_ws_bytes(const tide_bins* bins, int32_t dtype)
   if (!bins) return 0;
   const size_t es = dtype == TIDE_F64 ? 8 : 4;
   return align_up((size_t)(bins->n_inst > 0 ? bins->n_inst : 1) * kG2 * es) +
-         align_up((size_t)kG2 * bins->n_cams * bins->n_pidx * es) + 256;
+         align_up((size_t)kG2 * bins->n_cams * bins->n_pidx * es) +
+         align_up((size_t)(bins->n_vis > 0 ? bins->n_vis : 1) * 4) + align_up(4) + 256;
 }
 
 extern "C" tide_status tide_render_bwd(const tide_pool* pool, const tide_camera* cams, int32_t n_cams,
@@ -404,13 +472,19 @@ extern "C" tide_status tide_render_bwd(const tide_pool* pool, const tide_camera*
   if (proj->dtype == TIDE_F32) {
     float* partial = cv.take<float>((size_t)(bins->n_inst > 0 ? bins->n_inst : 1) * kG2);
     float* g2d = cv.take<float>((size_t)kG2 * nrec);
+    uint32_t* big_list = cv.take<uint32_t>((size_t)(bins->n_vis > 0 ? bins->n_vis : 1));
+    uint32_t* big_count = cv.take<uint32_t>(1);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, big_count);
     TIDE_TIMED("render_bwd", st, hipLaunchKernelGGL(k_render_bwd<float>, dim3(grid), dim3(64), 0, st, bins->ranges, bins->inst_e, bins->inst_rec,
                        (const float*)proj->rec, bins->tiles_x, bins->tiles_y, fr->width, fr->height, bg[0], bg[1],
                        bg[2], (const float*)fr->t_final, fr->last, (const float*)d_dimage, partial));
     TIDE_LAUNCH_CHECK("k_render_bwd");
     if (bins->n_vis > 0)
       TIDE_TIMED("reduce_pairs", st, hipLaunchKernelGGL(k_reduce_pairs<float>, dim3((uint32_t)ceil_div(bins->n_vis, 256)), dim3(256), 0, st,
-                         bins->vis_rec, bins->inst_off, bins->n_vis, nrec, (const float*)partial, g2d));
+                         bins->vis_rec, bins->inst_off, bins->n_vis, nrec, (const float*)partial, g2d, big_list, big_count));
+    TIDE_TIMED("reduce_big", st, hipLaunchKernelGGL(k_reduce_big<float>, dim3(512), dim3(256), 0, st, bins->vis_rec,
+                                                   bins->inst_off, nrec, (const float*)partial, g2d, big_list,
+                                                   big_count));
     TIDE_LAUNCH_CHECK("k_reduce_pairs");
     const CamSet<float> cs = make_camset<float>(cams, n_cams);
     if (proj->n_pidx > 0)
@@ -421,6 +495,9 @@ extern "C" tide_status tide_render_bwd(const tide_pool* pool, const tide_camera*
   } else {
     double* partial = cv.take<double>((size_t)(bins->n_inst > 0 ? bins->n_inst : 1) * kG2);
     double* g2d = cv.take<double>((size_t)kG2 * nrec);
+    uint32_t* big_list = cv.take<uint32_t>((size_t)(bins->n_vis > 0 ? bins->n_vis : 1));
+    uint32_t* big_count = cv.take<uint32_t>(1);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, big_count);
     TIDE_TIMED("render_bwd", st, hipLaunchKernelGGL(k_render_bwd<double>, dim3(grid), dim3(64), 0, st, bins->ranges, bins->inst_e,
                        bins->inst_rec, (const double*)proj->rec, bins->tiles_x, bins->tiles_y, fr->width,
                        fr->height, (double)bg[0], (double)bg[1], (double)bg[2], (const double*)fr->t_final,
@@ -428,7 +505,10 @@ extern "C" tide_status tide_render_bwd(const tide_pool* pool, const tide_camera*
     TIDE_LAUNCH_CHECK("k_render_bwd");
     if (bins->n_vis > 0)
       TIDE_TIMED("reduce_pairs", st, hipLaunchKernelGGL(k_reduce_pairs<double>, dim3((uint32_t)ceil_div(bins->n_vis, 256)), dim3(256), 0, st,
-                         bins->vis_rec, bins->inst_off, bins->n_vis, nrec, (const double*)partial, g2d));
+                         bins->vis_rec, bins->inst_off, bins->n_vis, nrec, (const double*)partial, g2d, big_list, big_count));
+    TIDE_TIMED("reduce_big", st, hipLaunchKernelGGL(k_reduce_big<double>, dim3(512), dim3(256), 0, st, bins->vis_rec,
+                                                   bins->inst_off, nrec, (const double*)partial, g2d, big_list,
+                                                   big_count));
     TIDE_LAUNCH_CHECK("k_reduce_pairs");
     const CamSet<double> cs = make_camset<double>(cams, n_cams);
     if (proj->n_pidx > 0)

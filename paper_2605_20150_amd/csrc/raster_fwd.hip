@@ -262,12 +262,21 @@ __global__ void k_compact_vis(const uint32_t* __restrict__ tt, const float* __re
   val[o] = (uint32_t)i;
 }
 
-// Instances of the s-th depth-ordered visible pair, tiles row-major.
+// Instances of the s-th depth-ordered visible pair, tiles row-major.  A pair
+// covering more than kBigRect tiles is queued for k_emit_big, where a whole
+// wave writes its instances.
+constexpr uint32_t kBigRect = 32;
+
 __global__ void k_emit(const uint32_t* __restrict__ vis_rec, const uint32_t* __restrict__ inst_off,
                        const uint32_t* __restrict__ rect, int64_t n_vis, int64_t n_pidx, int32_t Tx, int32_t Ty,
-                       uint32_t* __restrict__ tkey, uint32_t* __restrict__ inst_rec) {
+                       uint32_t* __restrict__ tkey, uint32_t* __restrict__ inst_rec, uint32_t* __restrict__ big,
+                       uint32_t* __restrict__ big_count) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n_vis) return;
+  if (inst_off[s + 1] - inst_off[s] > kBigRect) {
+    big[atomicAdd(big_count, 1u)] = (uint32_t)s;
+    return;
+  }
   const uint32_t r = vis_rec[s];
   const uint32_t c = (uint32_t)(r / (uint64_t)n_pidx);
   const uint32_t a = rect[2 * (int64_t)r], b = rect[2 * (int64_t)r + 1];
@@ -282,7 +291,36 @@ __global__ void k_emit(const uint32_t* __restrict__ vis_rec, const uint32_t* __r
     }
 }
 
-__global__ void k_set_u32(uint32_t* p, const unsigned long long* v) { *p = (uint32_t)*v; }
+__global__ void __launch_bounds__(256) k_emit_big(const uint32_t* __restrict__ vis_rec,
+                                                  const uint32_t* __restrict__ inst_off,
+                                                  const uint32_t* __restrict__ rect, int64_t n_pidx, int32_t Tx,
+                                                  int32_t Ty, uint32_t* __restrict__ tkey,
+                                                  uint32_t* __restrict__ inst_rec, const uint32_t* __restrict__ big,
+                                                  const uint32_t* __restrict__ big_count) {
+  const uint32_t nbig = *big_count;
+  const uint32_t nw = gridDim.x * blockDim.x / kWave;
+  const int lane = __lane_id();
+  for (uint32_t w = (blockIdx.x * blockDim.x + threadIdx.x) / kWave; w < nbig; w += nw) {
+    const uint32_t s = big[w];
+    const uint32_t r = vis_rec[s];
+    const uint32_t c = (uint32_t)(r / (uint64_t)n_pidx);
+    const uint32_t a = rect[2 * (int64_t)r], b = rect[2 * (int64_t)r + 1];
+    const int x0 = a & 0xffff, y0 = a >> 16, x1 = b & 0xffff;
+    const uint32_t rw = (uint32_t)(x1 - x0);
+    const uint32_t e0 = inst_off[s], cnt = inst_off[s + 1] - e0;
+    const uint32_t tbase = c * (uint32_t)(Tx * Ty);
+    for (uint32_t k = lane; k < cnt; k += kWave) {
+      const uint32_t ty = (uint32_t)y0 + k / rw, tx = (uint32_t)x0 + k % rw;
+      tkey[e0 + k] = tbase + ty * (uint32_t)Tx + tx;
+      inst_rec[e0 + k] = r;
+    }
+  }
+}
+
+// inst_off[n_vis] = n_inst, with both counts read on the device.
+__global__ void k_set_end(uint32_t* inst_off, const unsigned long long* n_vis, const unsigned long long* n_inst) {
+  inst_off[*n_vis] = (uint32_t)*n_inst;
+}
 
 __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -299,6 +337,7 @@ __global__ void k_ranges(const uint32_t* __restrict__ key, int64_t n, uint32_t* 
 
 struct BinLayout {
   uint32_t *vis_off, *ka, *va, *kb, *vb, *inst_off, *tka, *tva, *tkb, *tvb, *inst_rec, *ranges, *hist;
+  uint32_t *emit_big, *emit_cnt;
   unsigned long long *partial, *totals;
   size_t bytes;
 };
@@ -319,6 +358,8 @@ static BinLayout bin_layout(void* ws, int n_cams, int64_t n_pidx, int64_t n_tile
   L.tvb = cv.take<uint32_t>(cap);
   L.inst_rec = cv.take<uint32_t>(cap);
   L.ranges = cv.take<uint32_t>(2 * (size_t)n_cams * n_tiles);
+  L.emit_big = cv.take<uint32_t>(nv > 0 ? nv : 1);
+  L.emit_cnt = cv.take<uint32_t>(1);
   const int64_t big = nv > cap ? nv : cap;
   const size_t nh = radix_hist_count(big);
   L.hist = cv.take<uint32_t>(nh);
@@ -332,7 +373,10 @@ static BinLayout bin_layout(void* ws, int n_cams, int64_t n_pidx, int64_t n_tile
 // ------------------------------------------------------------- compositing
 // One wave64 per 16x16 tile; lane l owns the four pixels of column l % 16,
 // rows l / 16 + {0, 4, 8, 12}.  The tile's list is streamed through LDS in
-// batches of 64 records, read back as broadcasts.
+// batches of 64 records and read back as broadcasts.  The per-pixel update is
+// branch-free (selects on the skip / stop / contribute predicates), and the
+// terms that depend only on the lane's column are formed once per entry and
+// shared by its four pixels.
 template <typename T>
 __global__ void __launch_bounds__(64) k_render_fwd(const uint32_t* __restrict__ ranges,
                                                    const uint32_t* __restrict__ inst_e,
@@ -349,49 +393,56 @@ __global__ void __launch_bounds__(64) k_render_fwd(const uint32_t* __restrict__ 
   const int px = tx * kTile + (lane & 15);
   const int py0 = ty * kTile + (lane >> 4);
   const T fxp = (T)px + (T)0.5;
-  T fyp[4];
-  bool done[4];
-  T Tr[4], C0[4], C1[4], C2[4];
+  // A pixel is live while Tr > 0; stopping stores -T (the final T, negated),
+  // and pixels outside the image start stopped.
+  T fyp[4], Tr[4], C0[4], C1[4], C2[4];
   uint32_t lst[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     fyp[q] = (T)(py0 + 4 * q) + (T)0.5;
-    done[q] = !(px < W && py0 + 4 * q < H);
-    Tr[q] = 1; C0[q] = C1[q] = C2[q] = 0; lst[q] = 0;
+    Tr[q] = (px < W && py0 + 4 * q < H) ? (T)1 : (T)-1;
+    C0[q] = C1[q] = C2[q] = 0;
+    lst[q] = 0;
   }
-  unsigned long long nvis = 0;
+  unsigned long long nvis = 0;   // wave-uniform: live pixels summed over entries
   const uint32_t start = ranges[2 * g], end = ranges[2 * g + 1];
   __shared__ T s_u[64], s_v[64], s_A[64], s_B[64], s_C[64], s_o[64], s_r[64], s_g[64], s_b[64];
-  bool all_done = __ballot(!(done[0] && done[1] && done[2] && done[3])) == 0;
-  for (uint32_t b0 = start; b0 < end && !all_done; b0 += 64) {
+  const T ks = (T)Ex<T>::k;
+  bool any = __ballot(Tr[0] > 0 || Tr[1] > 0 || Tr[2] > 0 || Tr[3] > 0) != 0;
+  for (uint32_t b0 = start; b0 < end && any; b0 += 64) {
     const uint32_t j = b0 + lane;
     if (j < end) {
       const T* q = rec + (int64_t)inst_rec[inst_e[j]] * kRec;
       s_u[lane] = q[0]; s_v[lane] = q[1];
-      s_A[lane] = (T)-0.5 * q[2]; s_B[lane] = -q[3]; s_C[lane] = (T)-0.5 * q[4];
+      s_A[lane] = (T)-0.5 * ks * q[2]; s_B[lane] = -ks * q[3]; s_C[lane] = (T)-0.5 * ks * q[4];
       s_o[lane] = q[5]; s_r[lane] = q[6]; s_g[lane] = q[7]; s_b[lane] = q[8];
     }
     __syncthreads();
     const int nb = (int)(end - b0 < 64 ? end - b0 : 64);
     for (int k = 0; k < nb; ++k) {
-      const T u = s_u[k], v = s_v[k], A = s_A[k], B = s_B[k], Cc = s_C[k], op = s_o[k];
+      const T v = s_v[k], Ch = s_C[k], op = s_o[k];
       const T cr = s_r[k], cg = s_g[k], cb = s_b[k];
-      const T dx = fxp - u;
+      const T dx = fxp - s_u[k];
+      const T adx2 = s_A[k] * dx * dx, bdx = s_B[k] * dx;
+      const uint32_t idx = b0 - start + (uint32_t)k + 1;
+      bool live_any = false;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        if (done[q]) continue;
-        ++nvis;
-        const T dy = fyp[q] - v;
         T G, araw, alpha;
-        if (!entry_alpha<T>(A, B, Cc, op, dx, dy, G, araw, alpha)) continue;
+        const bool pass = entry_alpha<T>(adx2, bdx, Ch, op, fyp[q] - v, G, araw, alpha);
+        const bool live = Tr[q] > 0;
+        nvis += (unsigned long long)__popcll(__ballot(live));
         const T tn = Tr[q] * ((T)1 - alpha);
-        if (tn < (T)1e-4) { done[q] = true; continue; }
-        const T w = alpha * Tr[q];
+        const bool ok = pass && live;
+        const bool stop = ok && tn < (T)1e-4;
+        const bool take = ok && !stop;
+        const T w = take ? alpha * Tr[q] : (T)0;
         C0[q] += cr * w; C1[q] += cg * w; C2[q] += cb * w;
-        Tr[q] = tn;
-        lst[q] = b0 - start + (uint32_t)k + 1;
+        Tr[q] = take ? tn : (stop ? -Tr[q] : Tr[q]);
+        lst[q] = take ? idx : lst[q];
+        live_any = live_any || (live && !stop);
       }
-      if (__ballot(!(done[0] && done[1] && done[2] && done[3])) == 0) { all_done = true; break; }
+      if (__ballot(live_any) == 0) { any = false; break; }
     }
     __syncthreads();
   }
@@ -401,14 +452,14 @@ __global__ void __launch_bounds__(64) k_render_fwd(const uint32_t* __restrict__ 
     const int py = py0 + 4 * q;
     if (px < W && py < H) {
       const int64_t p = (int64_t)py * W + px;
-      image[((int64_t)c * 3 + 0) * HW + p] = C0[q] + Tr[q] * bg0;
-      image[((int64_t)c * 3 + 1) * HW + p] = C1[q] + Tr[q] * bg1;
-      image[((int64_t)c * 3 + 2) * HW + p] = C2[q] + Tr[q] * bg2;
-      tfin[(int64_t)c * HW + p] = Tr[q];
+      const T tf = Tr[q] < 0 ? -Tr[q] : Tr[q];
+      image[((int64_t)c * 3 + 0) * HW + p] = C0[q] + tf * bg0;
+      image[((int64_t)c * 3 + 1) * HW + p] = C1[q] + tf * bg1;
+      image[((int64_t)c * 3 + 2) * HW + p] = C2[q] + tf * bg2;
+      tfin[(int64_t)c * HW + p] = tf;
       last_out[(int64_t)c * HW + p] = lst[q];
     }
   }
-  nvis = wave_sum(nvis);
   if (lane == 0 && nvis) atomicAdd(&visits[c], nvis);
 }
 
@@ -469,20 +520,20 @@ extern "C" tide_status tide_bin_sort(const tide_proj* proj, int32_t tiles_x, int
     TIDE_TIMED("compact_vis", st, hipLaunchKernelGGL(k_compact_vis, dim3((uint32_t)ceil_div(nv, 256)), dim3(256), 0, st, proj->tiles_touched,
                        proj->depth, L.vis_off, nv, L.ka, L.va));
   TIDE_LAUNCH_CHECK("visibility compaction");
-  unsigned long long h_tot[2] = {0, 0};
-  TIDE_HIP(hipMemcpyAsync(&h_tot[0], &L.totals[0], 8, hipMemcpyDeviceToHost, st));
+  // 2. stable sort of the visible pairs by depth; grids are sized by the
+  //    upper bound and the kernels read the visible count from the device
+  uint32_t *vk, *vrec;
+  radix_sort_pairs(L.ka, L.va, L.kb, L.vb, nv, 32, false, L.hist, L.partial, &L.totals[1], st, &vk, &vrec,
+                   &L.totals[0]);
+  // 3. instance offsets in depth order, and the one host read of the counts
+  scan_exclusive(GatherIn{proj->tiles_touched, vrec}, nv, L.inst_off, L.partial, &L.totals[2], st, &L.totals[0]);
+  hipLaunchKernelGGL(k_set_end, dim3(1), dim3(1), 0, st, L.inst_off, &L.totals[0], &L.totals[2]);
+  TIDE_LAUNCH_CHECK("instance scan");
+  unsigned long long h_tot[3] = {0, 0, 0};
+  TIDE_HIP(hipMemcpyAsync(h_tot, L.totals, 24, hipMemcpyDeviceToHost, st));
   TIDE_HIP(hipStreamSynchronize(st));
   const int64_t n_vis = (int64_t)h_tot[0];
-  // 2. stable sort of the visible pairs by depth
-  uint32_t *vk, *vrec;
-  radix_sort_pairs(L.ka, L.va, L.kb, L.vb, n_vis, 32, false, L.hist, L.partial, &L.totals[1], st, &vk, &vrec);
-  // 3. instance offsets in depth order
-  scan_exclusive(GatherIn{proj->tiles_touched, vrec}, n_vis, L.inst_off, L.partial, &L.totals[2], st);
-  hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, st, L.inst_off + n_vis, &L.totals[2]);
-  TIDE_LAUNCH_CHECK("instance scan");
-  TIDE_HIP(hipMemcpyAsync(&h_tot[1], &L.totals[2], 8, hipMemcpyDeviceToHost, st));
-  TIDE_HIP(hipStreamSynchronize(st));
-  const int64_t n_inst = (int64_t)h_tot[1];
+  const int64_t n_inst = (int64_t)h_tot[2];
   if (n_inst >= (int64_t)UINT32_MAX) {
     set_error("instance count %lld exceeds 32-bit indexing", (long long)n_inst);
     return TIDE_EINVAL;
@@ -495,9 +546,14 @@ extern "C" tide_status tide_bin_sort(const tide_proj* proj, int32_t tiles_x, int
     return TIDE_ECAPACITY;
   }
   // 4. emit instances in depth order, keyed by global tile id
-  if (n_vis > 0)
-    TIDE_TIMED("emit", st, hipLaunchKernelGGL(k_emit, dim3((uint32_t)ceil_div(n_vis, 256)), dim3(256), 0, st, vrec, L.inst_off, proj->rect,
-                       n_vis, N, tiles_x, tiles_y, L.tka, L.inst_rec));
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, L.emit_cnt, 1, 0u);
+  if (n_vis > 0) {
+    TIDE_TIMED("emit", st, hipLaunchKernelGGL(k_emit, dim3((uint32_t)ceil_div(n_vis, 256)), dim3(256), 0, st, vrec,
+                                              L.inst_off, proj->rect, n_vis, N, tiles_x, tiles_y, L.tka, L.inst_rec,
+                                              L.emit_big, L.emit_cnt));
+    hipLaunchKernelGGL(k_emit_big, dim3(256), dim3(256), 0, st, vrec, L.inst_off, proj->rect, N, tiles_x, tiles_y,
+                       L.tka, L.inst_rec, L.emit_big, L.emit_cnt);
+  }
   TIDE_LAUNCH_CHECK("k_emit");
   // 5. stable sort by tile; values are emission indices
   int bits = 0;

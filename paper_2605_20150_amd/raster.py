@@ -281,10 +281,12 @@ class Rasterizer:
     def adam(self, pool: Pool, proj: Proj, grad: torch.Tensor, cfg: L.tide_adam_cfg, spheres=None, dirty=None):
         pc, qc = pool.c(), proj.c()
         nb = int(spheres.shape[0]) if spheres is not None else (int(dirty.shape[0]) if dirty is not None else 0)
+        wsb = self.lib.tide_adam_ws_bytes(proj.n_pidx)
+        ws = self.buf.get("adam_ws", wsb)
         L.check(self.lib.tide_adam_sparse(C.byref(pc), C.byref(qc), C.c_void_p(grad.data_ptr()), grad.shape[1],
                                           C.byref(cfg), C.c_void_p(spheres.data_ptr() if spheres is not None else 0),
                                           C.c_void_p(dirty.data_ptr() if dirty is not None else 0), nb,
-                                          C.c_void_p(_stream())))
+                                          C.c_void_p(ws.data_ptr()), ws.numel(), C.c_void_p(_stream())))
 
 
 def dense_grad(proj: Proj, grad: torch.Tensor, n: int) -> torch.Tensor:

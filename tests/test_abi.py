@@ -52,4 +52,4 @@ def test_null_arguments_rejected_before_launch():
     assert lib.tide_preprocess(C.byref(pool), cam, 1, None, None, 0, None) == L.TIDE_EINVAL
     assert lib.tide_loss(None, None, 1, 8, 8, 0, None, None, None, 0, None) == L.TIDE_EINVAL
     cfg = L.tide_adam_cfg()
-    assert lib.tide_adam_sparse(None, None, None, 0, C.byref(cfg), None, None, 0, None) == L.TIDE_EINVAL
+    assert lib.tide_adam_sparse(None, None, None, 0, C.byref(cfg), None, None, 0, None, 0, None) == L.TIDE_EINVAL
