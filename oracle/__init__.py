@@ -72,13 +72,13 @@ def _declare(L):
 
 
 def _declare_tier(L):
-    L.orc_cull_blocks.argtypes = [_d, C.c_int64, _d, C.c_int, _d, _u8]
-    L.orc_block_spheres.argtypes = [_d, C.c_int64, C.c_int64, C.c_double, _d]
-    L.orc_alg1.argtypes = [_i32, C.c_int, _i32, C.c_int, _i32, _i32, C.c_int, _d, C.c_int64,
-                           C.c_double, C.c_double, C.c_int, _i32, _i32]
-    L.orc_alg1.restype = C.c_int
     L.orc_kappa.argtypes = [_d, C.c_int]
     L.orc_kappa.restype = C.c_double
+    L.orc_block_spheres.argtypes = [_d, C.c_int64, C.c_int64, C.c_double, _d]
+    L.orc_cull_blocks.argtypes = [_d, C.c_int64, _d, C.c_int, _u8]
+    L.orc_alg1.argtypes = [_i32, C.c_int, _i32, C.c_int, _i32, _i32, C.c_int, _d, C.c_int64, C.c_double,
+                           C.c_double, C.c_int, _i32, _i32]
+    L.orc_alg1.restype = C.c_int
 
 
 def _declare_mlp(L):
@@ -249,3 +249,46 @@ def adam(theta, m, v, step, grad, active, lr=LR59, b1=0.9, b2=0.999, eps=1e-15):
     lib().orc_adam(_p(th, _d), _p(m, _d), _p(v, _d), _p(st, _i64), _p(g, _d), _p(act, _u8),
                    th.shape[0], _p(lr, _d), b1, b2, eps)
     return th, m, v, st
+
+
+# --------------------------------------------------------------------------
+# block tier (Level-1 culling, Alg. 1)
+# --------------------------------------------------------------------------
+
+def kappa(cams) -> float:
+    cm = _f64(cams)
+    return lib().orc_kappa(_p(cm, _d), cm.shape[0])
+
+
+def block_spheres(theta, block_rows, kap):
+    th = _f64(theta)
+    K = (th.shape[0] + block_rows - 1) // block_rows
+    sp = np.zeros((K, 4))
+    lib().orc_block_spheres(_p(th, _d), th.shape[0], block_rows, float(kap), _p(sp, _d))
+    return sp
+
+
+def cull_blocks(spheres, cams):
+    """vis[c, k]: block k survives camera c's six-plane sphere test."""
+    sp = _f64(spheres)
+    cm = _f64(cams)
+    vis = np.zeros((cm.shape[0], sp.shape[0]), dtype=np.uint8)
+    lib().orc_cull_blocks(_p(sp, _d), sp.shape[0], _p(cm, _d), cm.shape[0], _p(vis, _u8))
+    return vis.astype(bool)
+
+
+def alg1(R, Kcur, Knext_per_cam, age, lam, gamma, C):
+    """One step of Alg. 1.  Returns (R_next sorted, S_plus, S_minus, age', pick order)."""
+    R = np.ascontiguousarray(sorted(set(int(x) for x in R)), dtype=np.int32)
+    Kc = np.ascontiguousarray(sorted(set(int(x) for x in Kcur)), dtype=np.int32)
+    lists = [sorted(set(int(x) for x in k)) for k in Knext_per_cam]
+    flat = np.ascontiguousarray([x for l in lists for x in l] or [0], dtype=np.int32)
+    counts = np.ascontiguousarray([len(l) for l in lists] or [0], dtype=np.int32)
+    ag = _f64(age).copy()
+    outR = np.zeros(max(C, 1), dtype=np.int32)
+    rank = np.zeros(max(C, 1), dtype=np.int32)
+    n = lib().orc_alg1(_p(R, _i32), len(R), _p(Kc, _i32), len(Kc), _p(flat, _i32), _p(counts, _i32), len(lists),
+                       _p(ag, _d), len(ag), float(lam), float(gamma), int(C), _p(outR, _i32), _p(rank, _i32))
+    Rn = outR[:n].copy()
+    sR, sN = set(R.tolist()), set(Rn.tolist())
+    return Rn, sorted(sN - sR), sorted(sR - sN), ag, rank[:n].copy()
