@@ -256,6 +256,130 @@ tide_status tide_adam_sparse(tide_pool* pool, const tide_proj* proj, const void*
                              void* stream);
 
 /* ------------------------------------------------------------------------
+ * Out-of-core block tier (Sec. 3.3 to 3.5; Alg. 1).  A host object owns the
+ * SSD log store (an immutable base segment plus append-only patch segments
+ * and Index[k] = (file_id, offset, size, version), Sec. 3.4), a host LRU
+ * block cache with dirty bits (pinned memory), I/O threads, and the GPU slot
+ * table of the caller's tide_pool.  Device memory stays the caller's: the
+ * pool arrays, the pool's slot_block / slot_rows / order arrays (written by
+ * the tier) and the bounding spheres.
+ *
+ * A block record is the block's parameters, Adam moments and steps in the
+ * pool's slot layout: params[59][B], m[59][B], v[59][B] (f32), step[B] (u32).
+ *
+ * Per iteration t (the paper's stages 1 to 4):
+ *   tide_residency_sync_bounds   wait for the last iteration's sphere / dirty
+ *                                read-back (bounds only grow, Sec. 3.3)
+ *   tide_cull_blocks             K_t per camera (Level 1, Eq. Kt_def)
+ *   tide_ensure_resident         make every block of K_t resident; blocks not
+ *                                yet transferred are fetched synchronously
+ *                                (the time spent waiting is the stall)
+ *   ... compute of iteration t on the compute stream ...
+ *   tide_cull_blocks             K_{t+1} per camera of the next batch
+ *   tide_stream_delta            Alg. 1: R_{t+1}, S+, S-; enqueues the
+ *                                transfers on the side stream behind the
+ *                                compute of iteration t
+ *   tide_residency_end_iteration records the compute event and reads the
+ *                                refreshed spheres and dirty flags back
+ * ---------------------------------------------------------------------- */
+typedef struct tide_residency tide_residency;
+
+#define TIDE_TIER_HOST_POOL 1   /* pool / spheres / dirty are host memory (CPU-only runs) */
+#define TIDE_TIER_ODIRECT 2     /* O_DIRECT reads and writes of the segment files */
+
+typedef struct {
+  const char* dir;            /* directory of the segment files (created if missing) */
+  int64_t n_rows;             /* N, rows of the whole table */
+  int32_t block_rows;         /* B */
+  int32_t capacity;           /* C: blocks Alg. 1 may keep resident (<= pool n_slots) */
+  int64_t host_cache_blocks;  /* host LRU capacity in blocks */
+  int32_t io_threads;         /* SSD worker threads (>= 1) */
+  int32_t flags;              /* TIDE_TIER_* */
+  double lambda_;             /* s(k) = lambda 1[k in K_{t+1}] + (1 - lambda) Recency(k) */
+  double gamma;               /* Recency(k) = gamma^age */
+  double kappa;               /* footprint stretch bound used by the bounds */
+} tide_store_cfg;
+
+typedef struct {
+  int64_t iterations;
+  int64_t blocks_in, blocks_out;          /* S+ and S- totals */
+  int64_t readmissions;                   /* S+ blocks that had been resident before */
+  int64_t h2d_bytes, d2h_bytes;           /* PCIe traffic of block records */
+  int64_t ssd_read_bytes, ssd_write_bytes;
+  int64_t host_hits, host_misses;         /* host cache lookups for S+ and sync fetches */
+  int64_t sync_fetches;                   /* blocks of K_t that were not on the GPU in time */
+  double stall_seconds;                   /* host time blocked in tide_ensure_resident */
+  int64_t resident;                       /* |R_t| */
+  int64_t prefetch_issued, prefetch_used; /* hinted blocks read ahead / later admitted */
+} tide_tier_stats;
+
+/* Creates the tier over pool (n_slots >= cfg->capacity; block_rows = B).
+ * No file is touched: a new store is laid out with tide_store_put_block /
+ * tide_store_finalize, an existing one is loaded with tide_store_open.
+ * d_spheres: f32 [K][4] (cx, cy, cz, r) and d_dirty: u8 [K], K = ceil(N/B),
+ * both device memory (host memory with TIDE_TIER_HOST_POOL); the tier keeps
+ * host copies.  Nothing is resident after creation. */
+tide_status tide_residency_create(const tide_store_cfg* cfg, tide_pool* pool, float* d_spheres,
+                                  uint8_t* d_dirty, tide_residency** out);
+tide_status tide_residency_destroy(tide_residency* res);
+
+/* Layout build (Sec. 3.3, 4.1): writes block k's record to the base segment
+ * with zero moments and steps.  params: host f32 [59][rows of block k].
+ * Computes the block's sphere: c_k = mean of the member means (fixed),
+ * r_k = max |mu_i - c_k| + 3 kappa max exp(log-scale_i). */
+tide_status tide_store_put_block(tide_residency* res, int64_t block, const float* params);
+/* Ends the layout build: persists Index and uploads the spheres. */
+tide_status tide_store_finalize(tide_residency* res);
+/* Reopens an existing store (after tide_residency_create on the same dir):
+ * loads the persisted Index and the sphere file. */
+tide_status tide_store_open(tide_residency* res);
+
+/* Level 1: K^(c) for each camera.  out_ids receives the ascending block ids
+ * of camera 0, then camera 1, ...; counts[c] their numbers.  cap = capacity
+ * of out_ids; TIDE_ECAPACITY if it is too small. Uses the host spheres. */
+tide_status tide_cull_blocks(const tide_residency* res, const tide_camera* cams, int32_t n_cams,
+                             int32_t* out_ids, int32_t* counts, int64_t cap);
+
+/* Makes every block of K (ascending ids) resident and writes the pool's
+ * order array (slots of K in ascending block id) and n_order; the compute
+ * stream waits for the transfers.  Host-blocking time is added to
+ * stall_seconds (and returned in *stall_s if non-null). */
+tide_status tide_ensure_resident(tide_residency* res, const int32_t* K, int32_t n, void* compute_stream,
+                                 double* stall_s);
+
+/* Alg. 1 with the per-camera next sets; enqueues S- device-to-host copies
+ * behind the compute event of the current iteration, and S+ host-to-device
+ * copies (SSD reads on the I/O threads first).  out_plus / out_minus
+ * (capacity cap each, may be null) receive S+ and S-. */
+tide_status tide_stream_delta(tide_residency* res, const int32_t* knext_ids, const int32_t* knext_counts,
+                              int32_t n_cams, void* side_stream, int32_t* out_plus, int32_t* n_plus,
+                              int32_t* out_minus, int32_t* n_minus, int64_t cap);
+
+/* Records the end of iteration t's compute on compute_stream and enqueues
+ * the read-back of spheres and dirty flags. */
+tide_status tide_residency_end_iteration(tide_residency* res, void* compute_stream);
+/* Waits for that read-back; the next culling uses the refreshed bounds. */
+tide_status tide_residency_sync_bounds(tide_residency* res);
+
+/* Prefetch hint: read these blocks from the SSD into the host cache ahead
+ * of need (horizon = iterations ahead, for statistics). */
+tide_status tide_prefetch_hint(tide_residency* res, const int32_t* blocks, int32_t n, int32_t horizon);
+
+/* Consistency barrier (Sec. 3.4): device-to-host of every dirty resident
+ * block, flush of every dirty host entry to a patch segment, fsync, then the
+ * Index is persisted atomically. Blocks until done. */
+tide_status tide_checkpoint(tide_residency* res);
+
+/* Reads block k's newest record (host, rec_bytes) through Index: from the
+ * GPU if resident (blocking copy), else the host cache, else the SSD. */
+size_t tide_block_record_bytes(int32_t block_rows);
+tide_status tide_read_block(tide_residency* res, int64_t block, void* dst);
+
+tide_status tide_tier_get_stats(const tide_residency* res, tide_tier_stats* out);
+/* Host copy of the spheres (f32 [K][4]) as the tier currently sees them. */
+tide_status tide_tier_spheres(const tide_residency* res, float* out, int64_t n_blocks);
+
+/* ------------------------------------------------------------------------
  * Timing hook for measurement.  Arms a pair of caller-created HIP events
  * (hipEvent_t) for one kernel of the library; every later launch of that
  * kernel records ev_start immediately before and ev_stop immediately after

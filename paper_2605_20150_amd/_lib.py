@@ -66,8 +66,29 @@ class tide_adam_cfg(C.Structure):
                 ("kappa", C.c_float)]
 
 
+class tide_store_cfg(C.Structure):
+    _fields_ = [("dir", C.c_char_p), ("n_rows", C.c_int64), ("block_rows", C.c_int32), ("capacity", C.c_int32),
+                ("host_cache_blocks", C.c_int64), ("io_threads", C.c_int32), ("flags", C.c_int32),
+                ("lambda_", C.c_double), ("gamma", C.c_double), ("kappa", C.c_double)]
+
+
+class tide_tier_stats(C.Structure):
+    _fields_ = [("iterations", C.c_int64), ("blocks_in", C.c_int64), ("blocks_out", C.c_int64),
+                ("readmissions", C.c_int64), ("h2d_bytes", C.c_int64), ("d2h_bytes", C.c_int64),
+                ("ssd_read_bytes", C.c_int64), ("ssd_write_bytes", C.c_int64), ("host_hits", C.c_int64),
+                ("host_misses", C.c_int64), ("sync_fetches", C.c_int64), ("stall_seconds", C.c_double),
+                ("resident", C.c_int64), ("prefetch_issued", C.c_int64), ("prefetch_used", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+TIDE_TIER_HOST_POOL = 1
+TIDE_TIER_ODIRECT = 2
+
 _P = C.POINTER
 _vp = C.c_void_p
+_pi32 = C.POINTER(C.c_int32)
 
 # name -> (restype, argtypes); every symbol include/tide.h declares
 SIGNATURES = {
@@ -87,6 +108,22 @@ SIGNATURES = {
     "tide_adam_sparse": (C.c_int32, [_P(tide_pool), _P(tide_proj), _vp, C.c_int64, _P(tide_adam_cfg), _vp, _vp,
                                      C.c_int64, _vp, C.c_size_t, _vp]),
     "tide_timer_arm": (C.c_int32, [C.c_char_p, _vp, _vp]),
+    "tide_residency_create": (C.c_int32, [_P(tide_store_cfg), _P(tide_pool), _vp, _vp, _P(_vp)]),
+    "tide_residency_destroy": (C.c_int32, [_vp]),
+    "tide_store_put_block": (C.c_int32, [_vp, C.c_int64, _vp]),
+    "tide_store_finalize": (C.c_int32, [_vp]),
+    "tide_store_open": (C.c_int32, [_vp]),
+    "tide_cull_blocks": (C.c_int32, [_vp, _P(tide_camera), C.c_int32, _pi32, _pi32, C.c_int64]),
+    "tide_ensure_resident": (C.c_int32, [_vp, _pi32, C.c_int32, _vp, _P(C.c_double)]),
+    "tide_stream_delta": (C.c_int32, [_vp, _pi32, _pi32, C.c_int32, _vp, _pi32, _pi32, _pi32, _pi32, C.c_int64]),
+    "tide_residency_end_iteration": (C.c_int32, [_vp, _vp]),
+    "tide_residency_sync_bounds": (C.c_int32, [_vp]),
+    "tide_prefetch_hint": (C.c_int32, [_vp, _pi32, C.c_int32, C.c_int32]),
+    "tide_checkpoint": (C.c_int32, [_vp]),
+    "tide_block_record_bytes": (C.c_size_t, [C.c_int32]),
+    "tide_read_block": (C.c_int32, [_vp, C.c_int64, _vp]),
+    "tide_tier_get_stats": (C.c_int32, [_vp, _P(tide_tier_stats)]),
+    "tide_tier_spheres": (C.c_int32, [_vp, _P(C.c_float), C.c_int64]),
     "tide_timer_clear": (C.c_int32, []),
 }
 

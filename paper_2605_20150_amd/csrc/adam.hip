@@ -75,7 +75,8 @@ __global__ void __launch_bounds__(256) k_adam_bounds(const T* __restrict__ param
       const float* S = spheres + 4 * (int64_t)blk;
       const float dx = (float)P[0] - S[0], dy = (float)P[B] - S[1], dz = (float)P[2 * (int64_t)B] - S[2];
       float ls = fmaxf((float)P[3 * (int64_t)B], fmaxf((float)P[4 * (int64_t)B], (float)P[5 * (int64_t)B]));
-      reach = sqrtf(dx * dx + dy * dy + dz * dz) + 3.f * kappa * expf(ls);
+      // rounded up so that single-precision evaluation never undercuts the bound
+      reach = (sqrtf(dx * dx + dy * dy + dz * dz) + 3.f * kappa * expf(ls)) * 1.000001f + 1e-6f;
     }
   }
   // lanes of one wave usually share a block: reduce first, then one update

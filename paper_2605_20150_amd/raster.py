@@ -52,18 +52,21 @@ class Buffers:
 class Pool:
     """Resident parameter pool, block-SoA [n_slots][59][block_rows]."""
 
-    def __init__(self, params, exp_avg, exp_avg_sq, step, slot_block, slot_rows, order):
+    def __init__(self, params, exp_avg, exp_avg_sq, step, slot_block, slot_rows, order, n_order=None):
         self.params, self.exp_avg, self.exp_avg_sq, self.step = params, exp_avg, exp_avg_sq, step
         self.slot_block, self.slot_rows, self.order = slot_block, slot_rows, order
         self.n_slots, _, self.block_rows = params.shape
+        self.n_order = int(order.numel()) if n_order is None else int(n_order)
 
     @classmethod
     def empty(cls, n_slots: int, block_rows: int, device, dtype=torch.float32):
+        """Slots for the block tier: nothing resident, order has room for
+        every slot (the tier fills it)."""
         z = lambda: torch.zeros((n_slots, D, block_rows), dtype=dtype, device=device)
         return cls(z(), z(), z(), torch.zeros((n_slots, block_rows), dtype=torch.int32, device=device),
                    torch.full((n_slots,), -1, dtype=torch.int32, device=device),
                    torch.zeros((n_slots,), dtype=torch.int32, device=device),
-                   torch.zeros((0,), dtype=torch.int32, device=device))
+                   torch.zeros((n_slots,), dtype=torch.int32, device=device), n_order=0)
 
     @classmethod
     def from_dense(cls, theta: torch.Tensor, block_rows: int = 65536, extra_slots: int = 0):
@@ -87,10 +90,6 @@ class Pool:
                    torch.tensor(sb, dtype=torch.int32, device=dev),
                    torch.tensor(rows, dtype=torch.int32, device=dev),
                    torch.arange(K, dtype=torch.int32, device=dev))
-
-    @property
-    def n_order(self) -> int:
-        return int(self.order.numel())
 
     @property
     def n_pidx(self) -> int:

@@ -1,0 +1,204 @@
+"""The block tier on the CPU: the library's host-memory backend stands in for
+the GPU pool (same slot API, copies are memcpy), real segment files stand in
+for the SSD.  Checks the log store, the host cache and write-back, Alg. 1
+against the oracle, Level-1 culling against the oracle, and crash
+consistency of the persisted Index."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2605_20150_amd import synth
+from paper_2605_20150_amd.raster import D, Pool
+from paper_2605_20150_amd.tier import Tier
+
+B = 256
+
+
+def scene(n=2500, seed=40):
+    th = synth.dense_scene(n, seed, extent=3.0, logscale_mu=-3.0)
+    cell = np.floor((th[:, :3] + 3.0) / 1.0).astype(int)
+    return th[np.lexsort((cell[:, 2], cell[:, 1], cell[:, 0]))]
+
+
+def build(tmp_path, th, n_slots=6, capacity=6, cache=4, name="store"):
+    pool = Pool.empty(n_slots, B, "cpu")
+    t = Tier(str(tmp_path / name), th.shape[0], pool, capacity, cache, io_threads=2, host_pool=True, kappa=1.32)
+    for k in range(t.K):
+        rows = th[k * B:(k + 1) * B]
+        t.put_block(k, rows.T)
+    t.finalize()
+    return t, pool
+
+
+def test_store_roundtrip_and_spheres(tmp_path):
+    th = scene()
+    t, pool = build(tmp_path, th)
+    assert t.K == 10
+    for k in range(t.K):
+        r = t.read_block(k)
+        rows = th[k * B:(k + 1) * B]
+        assert np.array_equal(r["params"][:, :len(rows)], rows.T)
+        assert not r["exp_avg"].any() and not r["exp_avg_sq"].any() and not r["step"].any()
+    ref = oracle.block_spheres(th.astype(np.float64), B, 1.32)
+    sp = t.host_spheres()
+    assert np.allclose(sp[:, :3], ref[:, :3], rtol=1e-6, atol=1e-6)
+    assert (sp[:, 3] >= ref[:, 3]).all() and np.allclose(sp[:, 3], ref[:, 3], rtol=1e-5)
+    t.close()
+
+
+def test_cull_matches_oracle(tmp_path):
+    th = scene()
+    t, _ = build(tmp_path, th)
+    rng = np.random.default_rng(41)
+    sp = t.host_spheres().astype(np.float64)
+    for _ in range(50):
+        eye = rng.normal(0, 4, size=3)
+        cam = synth.look_at(eye, rng.normal(0, 1, size=3), rng.normal(size=3), 96, 64, rng.uniform(40, 120),
+                            z_far=rng.uniform(2, 10))
+        got = t.cull([cam])[0]
+        ref = np.where(oracle.cull_blocks(sp, synth.cams_array([cam]))[0])[0]
+        assert got.tolist() == ref.tolist()
+    t.close()
+
+
+def walk_sets(rng, K, steps, J=2, width=3):
+    """Per-camera block sets that drift along the block ids."""
+    pos = 0
+    out = []
+    for _ in range(steps):
+        pos = (pos + int(rng.integers(0, 2))) % K
+        out.append([sorted({(pos + j + int(d)) % K for d in rng.integers(0, width, size=2)}) for j in range(J)])
+    return out
+
+
+def test_alg1_decisions_match_oracle(tmp_path):
+    th = scene()
+    t, pool = build(tmp_path, th, n_slots=6, capacity=6, cache=6)
+    rng = np.random.default_rng(42)
+    sets = walk_sets(rng, t.K, 40)
+    age = np.full(t.K, 1e9)
+    R = []
+    Kt = sorted(set(x for s in sets[0] for x in s))
+    t.ensure_resident(Kt)          # cold start: these blocks are fetched synchronously
+    cold = len(Kt)
+    R = sorted(t.resident_slots())
+    for i in range(1, len(sets)):
+        Rn, sp_ref, sm_ref, age, _ = oracle.alg1(R, Kt, sets[i], age, 0.75, 0.9, 6)
+        t.end_iteration()
+        sp, sm = t.stream_delta(sets[i])
+        t.sync_bounds()
+        assert sp.tolist() == sp_ref and sm.tolist() == sm_ref, i
+        Kt = sorted(set(x for s in sets[i] for x in s))
+        stall = t.ensure_resident(Kt)
+        assert stall >= 0
+        R = sorted(t.resident_slots())
+        assert R == Rn.tolist()
+        assert set(Kt) <= set(R)
+    st = t.stats()
+    assert st["sync_fetches"] == cold and st["blocks_in"] > 0
+    t.close()
+
+
+def test_residency_moves_data_and_writes_back(tmp_path):
+    """Blocks updated while resident are written back through the host cache
+    (dirty) to patch segments; a tiny host cache forces flushes; a reopened
+    store reads the newest versions."""
+    th = scene()
+    t, pool = build(tmp_path, th, n_slots=4, capacity=4, cache=4)
+    rng = np.random.default_rng(43)
+    truth = {k: t.read_block(k) for k in range(t.K)}
+    for it in range(30):
+        Kt = sorted(rng.choice(t.K, 2, replace=False).tolist())
+        t.ensure_resident(Kt)
+        slots = t.resident_slots()
+        for k in Kt:
+            s = slots[k]
+            for name in ("params", "exp_avg", "exp_avg_sq"):
+                assert np.array_equal(getattr(pool, name)[s].numpy(), truth[k][name]), (it, k, name)
+            # "train" the block: change parameters, moments and steps, mark dirty
+            pool.params[s] += 0.5
+            pool.exp_avg[s] += 1.0
+            pool.exp_avg_sq[s] += 2.0
+            pool.step[s] += 1
+            t.dirty[k] = 1
+            truth[k] = dict(params=pool.params[s].numpy().copy(), exp_avg=pool.exp_avg[s].numpy().copy(),
+                            exp_avg_sq=pool.exp_avg_sq[s].numpy().copy(),
+                            step=pool.step[s].numpy().view(np.uint32).copy())
+        t.end_iteration()
+        nxt = sorted(rng.choice(t.K, 2, replace=False).tolist())
+        t.stream_delta([nxt])
+        t.sync_bounds()
+    for k in range(t.K):
+        r = t.read_block(k)
+        for name in ("params", "exp_avg", "exp_avg_sq", "step"):
+            assert np.array_equal(r[name], truth[k][name]), (k, name)
+    st = t.stats()
+    assert st["ssd_write_bytes"] > 0 and st["blocks_out"] > 0 and st["readmissions"] > 0
+    t.checkpoint()
+    t.close()
+    pool2 = Pool.empty(4, B, "cpu")
+    t2 = Tier(str(tmp_path / "store"), th.shape[0], pool2, 4, 4, host_pool=True)
+    t2.open()
+    for k in range(t2.K):
+        r = t2.read_block(k)
+        for name in ("params", "exp_avg", "exp_avg_sq", "step"):
+            assert np.array_equal(r[name], truth[k][name]), (k, name)
+    t2.close()
+
+
+def test_crash_mid_append_keeps_the_persisted_versions(tmp_path):
+    th = scene()
+    t, pool = build(tmp_path, th, n_slots=4, capacity=4, cache=4)
+    t.ensure_resident([0, 1])
+    slots = t.resident_slots()
+    for k in (0, 1):
+        pool.params[slots[k]] += 1.0
+        t.dirty[k] = 1
+    t.end_iteration()
+    t.sync_bounds()
+    t.checkpoint()
+    saved = {k: t.read_block(k)["params"].copy() for k in (0, 1)}
+    # more updates after the checkpoint, flushed to a patch segment
+    for k in (0, 1):
+        pool.params[slots[k]] += 5.0
+        t.dirty[k] = 1
+    t.end_iteration()
+    t.stream_delta([[5, 6]])
+    t.sync_bounds()
+    t.ensure_resident([5, 6])
+    for k in (7, 8, 9, 2):          # pressure the 4-block host cache: dirty entries get flushed
+        t.stream_delta([[k]])
+        t.ensure_resident([k])
+    newest = t.read_block(0)["params"]
+    assert np.allclose(newest, saved[0] + 5.0)        # read-after-write
+    t.close()                                          # "crash": no checkpoint
+    d = tmp_path / "store"
+    patches = sorted(p for p in os.listdir(d) if p.startswith("patch_"))
+    last = d / patches[-1]
+    size = os.path.getsize(last)
+    if size:
+        with open(last, "r+b") as f:                   # a torn append
+            f.truncate(size - t.rec_bytes // 2)
+    pool2 = Pool.empty(4, B, "cpu")
+    t2 = Tier(str(d), th.shape[0], pool2, 4, 4, host_pool=True)
+    t2.open()
+    for k in (0, 1):
+        assert np.array_equal(t2.read_block(k)["params"], saved[k])
+    t2.close()
+
+
+def test_prefetch_feeds_the_host_cache(tmp_path):
+    th = scene()
+    t, pool = build(tmp_path, th, n_slots=4, capacity=4, cache=6)
+    t.ensure_resident([0])
+    t.prefetch([3, 4], horizon=2)
+    t.end_iteration()
+    t.stream_delta([[3, 4]])
+    t.sync_bounds()
+    t.ensure_resident([3, 4])
+    st = t.stats()
+    assert st["prefetch_issued"] == 2 and st["prefetch_used"] == 2
+    t.close()
