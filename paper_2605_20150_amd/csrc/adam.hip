@@ -56,44 +56,54 @@ __global__ void __launch_bounds__(256) k_adam_cols(T* __restrict__ params, T* __
   params[o] -= K.lr[j] * (m * (T)bc.x) / (Mth<T>::sqrt(v) * (T)bc.y + K.eps);
 }
 
+// One workgroup covers up to kBoundRows consecutive rows of one block: the
+// rows are reduced in registers and LDS, then a single atomic max per
+// workgroup raises the block radius.
+constexpr int kBoundRows = 4096;
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_adam_bounds(const T* __restrict__ params, const int32_t* __restrict__ order,
                                                      const int32_t* __restrict__ slot_block, int32_t B, int64_t n_pidx,
                                                      const uint32_t* __restrict__ active, float kappa,
                                                      float* __restrict__ spheres, uint8_t* __restrict__ dirty) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool act = i < n_pidx && active[i] != 0u;
-  int32_t blk = -1;
+  // workgroup -> (block k in the order, chunk c of kBoundRows rows within it)
+  const int64_t chunks = (B + kBoundRows - 1) / kBoundRows;
+  const int64_t k = blockIdx.x / chunks, c = blockIdx.x - k * chunks;
+  const int64_t i0 = k * (int64_t)B + c * kBoundRows;
+  if (i0 >= n_pidx) return;
+  const int32_t slot = order[k];
+  const int32_t blk = slot_block[slot];
+  const float* S = spheres ? spheres + 4 * (int64_t)blk : nullptr;
   float reach = 0.f;
-  if (act) {
-    const int64_t k = i / B;
-    const int32_t row = (int32_t)(i - k * B);
-    const int32_t slot = order[k];
-    blk = slot_block[slot];
-    if (spheres) {
+  bool any = false;
+  const int64_t iend = (k + 1) * (int64_t)B < i0 + kBoundRows ? (k + 1) * (int64_t)B : i0 + kBoundRows;
+  for (int64_t i = i0 + threadIdx.x; i < iend && i < n_pidx; i += 256) {
+    if (!active[i]) continue;
+    any = true;
+    if (S) {
+      const int32_t row = (int32_t)(i - k * B);
       const T* P = params + (int64_t)slot * kD * B + row;
-      const float* S = spheres + 4 * (int64_t)blk;
       const float dx = (float)P[0] - S[0], dy = (float)P[B] - S[1], dz = (float)P[2 * (int64_t)B] - S[2];
-      float ls = fmaxf((float)P[3 * (int64_t)B], fmaxf((float)P[4 * (int64_t)B], (float)P[5 * (int64_t)B]));
+      const float ls = fmaxf((float)P[3 * (int64_t)B], fmaxf((float)P[4 * (int64_t)B], (float)P[5 * (int64_t)B]));
       // rounded up so that single-precision evaluation never undercuts the bound
-      reach = (sqrtf(dx * dx + dy * dy + dz * dz) + 3.f * kappa * expf(ls)) * 1.000001f + 1e-6f;
+      reach = fmaxf(reach, (sqrtf(dx * dx + dy * dy + dz * dz) + 3.f * kappa * expf(ls)) * 1.000001f + 1e-6f);
     }
   }
-  // lanes of one wave usually share a block: reduce first, then one update
-  const int32_t b0 = __shfl(blk, 0, kWave);
-  const bool uniform = __ballot(blk != b0) == 0ull;
-  if (uniform) {
-    if (b0 < 0) return;
-    float r = reach;
+  __shared__ float s_r[256 / kWave];
+  __shared__ int s_any[256 / kWave];
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) r = fmaxf(r, __shfl_xor(r, off, kWave));
-    if (__lane_id() == 0) {
-      if (dirty) dirty[b0] = 1;
-      if (spheres) atomicMax(reinterpret_cast<unsigned int*>(spheres + 4 * (int64_t)b0 + 3), __float_as_uint(r));
+  for (int off = 32; off >= 1; off >>= 1) reach = fmaxf(reach, __shfl_xor(reach, off, kWave));
+  const bool wany = __ballot(any) != 0;
+  if (__lane_id() == 0) { s_r[threadIdx.x / kWave] = reach; s_any[threadIdx.x / kWave] = wany; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float r = 0.f;
+    int a = 0;
+    for (int w = 0; w < 256 / kWave; ++w) { r = fmaxf(r, s_r[w]); a |= s_any[w]; }
+    if (a && blk >= 0) {
+      if (dirty) dirty[blk] = 1;
+      if (spheres) atomicMax(reinterpret_cast<unsigned int*>(spheres + 4 * (int64_t)blk + 3), __float_as_uint(r));
     }
-  } else if (blk >= 0) {
-    if (dirty) dirty[blk] = 1;
-    if (spheres) atomicMax(reinterpret_cast<unsigned int*>(spheres + 4 * (int64_t)blk + 3), __float_as_uint(reach));
   }
 }
 
@@ -120,6 +130,8 @@ extern "C" tide_status tide_adam_sparse(tide_pool* pool, const tide_proj* proj, 
   const int64_t n = proj->n_pidx;
   if (n == 0) return TIDE_OK;
   const uint32_t gx = (uint32_t)ceil_div(n, 256);
+  // bound workgroups: kBoundRows indices each, never straddling a block
+  const uint32_t gb = (uint32_t)((int64_t)pool->n_order * ceil_div(pool->block_rows, kBoundRows));
   float2* bias = (float2*)ws;
   const double lb1 = std::log2((double)cfg->beta1), lb2 = std::log2((double)cfg->beta2);
   hipLaunchKernelGGL(k_adam_rows, dim3(gx), dim3(256), 0, st, pool->step, pool->order, pool->block_rows, n,
@@ -134,7 +146,7 @@ extern "C" tide_status tide_adam_sparse(tide_pool* pool, const tide_proj* proj, 
                                               pool->order, pool->block_rows, n, proj->active, proj->act_idx,
                                               (const float*)grad, grad_ld, K, bias));
     if (spheres || dirty)
-      hipLaunchKernelGGL(k_adam_bounds<float>, dim3(gx), dim3(256), 0, st, (const float*)pool->params, pool->order,
+      hipLaunchKernelGGL(k_adam_bounds<float>, dim3(gb), dim3(256), 0, st, (const float*)pool->params, pool->order,
                          pool->slot_block, pool->block_rows, n, proj->active, cfg->kappa, spheres, dirty);
   } else {
     AdamK<double> K;
@@ -145,7 +157,7 @@ extern "C" tide_status tide_adam_sparse(tide_pool* pool, const tide_proj* proj, 
                                               (double*)pool->exp_avg_sq, pool->order, pool->block_rows, n,
                                               proj->active, proj->act_idx, (const double*)grad, grad_ld, K, bias));
     if (spheres || dirty)
-      hipLaunchKernelGGL(k_adam_bounds<double>, dim3(gx), dim3(256), 0, st, (const double*)pool->params,
+      hipLaunchKernelGGL(k_adam_bounds<double>, dim3(gb), dim3(256), 0, st, (const double*)pool->params,
                          pool->order, pool->slot_block, pool->block_rows, n, proj->active, cfg->kappa, spheres,
                          dirty);
   }

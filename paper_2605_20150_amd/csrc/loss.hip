@@ -139,14 +139,16 @@ __global__ void __launch_bounds__(256) k_ssim_bwd(const T* __restrict__ X, const
   }
 }
 
-__global__ void k_loss_final(const double* part, int64_t nblk, double inv_n, double* loss) {
-  __shared__ double r1[256], r2[256];
+// Fixed-order sum of the block partials: lane-strided partial sums, then a
+// tree in LDS (deterministic for a given grid).
+__global__ void __launch_bounds__(1024) k_loss_final(const double* part, int64_t nblk, double inv_n, double* loss) {
+  __shared__ double r1[1024], r2[1024];
   double a = 0, b = 0;
-  for (int64_t k = threadIdx.x; k < nblk; k += 256) { a += part[2 * k]; b += part[2 * k + 1]; }
+  for (int64_t k = threadIdx.x; k < nblk; k += 1024) { a += part[2 * k]; b += part[2 * k + 1]; }
   r1[threadIdx.x] = a;
   r2[threadIdx.x] = b;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
+  for (int s = 512; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) { r1[threadIdx.x] += r1[threadIdx.x + s]; r2[threadIdx.x] += r2[threadIdx.x + s]; }
     __syncthreads();
   }
@@ -198,7 +200,7 @@ extern "C" tide_status tide_loss(const void* image, const void* target, int32_t 
                        width, w, dm, part));
     TIDE_TIMED("loss_bwd", st, hipLaunchKernelGGL(k_ssim_bwd<float>, grid, dim3(256), 0, st, (const float*)image, (const float*)target, dm,
                        height, width, w, (float)(1.0 / n_all), (float*)d_dimage));
-    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, part, nblk, 1.0 / n_all, d_loss);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(1024), 0, st, part, nblk, 1.0 / n_all, d_loss);
   } else {
     double* dm = cv.take<double>(3 * (size_t)n_views * 3 * height * width);
     double* part = cv.take<double>(2 * nblk);
@@ -207,7 +209,7 @@ extern "C" tide_status tide_loss(const void* image, const void* target, int32_t 
                        height, width, w, dm, part));
     TIDE_TIMED("loss_bwd", st, hipLaunchKernelGGL(k_ssim_bwd<double>, grid, dim3(256), 0, st, (const double*)image, (const double*)target, dm,
                        height, width, w, 1.0 / n_all, (double*)d_dimage));
-    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, part, nblk, 1.0 / n_all, d_loss);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(1024), 0, st, part, nblk, 1.0 / n_all, d_loss);
   }
   TIDE_LAUNCH_CHECK("tide_loss");
   return TIDE_OK;

@@ -158,69 +158,68 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
 }
 
 // ---------------------------------------------- per-pair reduction (fixed order)
-// Thread s sums the contiguous partials of the s-th depth-ordered visible
-// pair (its tiles in row-major order) and stores them SoA by record index.
-// Pairs with more than kBigPair instances (large footprints) would stall
-// their wave, so they are queued and summed by k_reduce_big, one wave per
-// pair with coalesced loads and a fixed reduction tree.
-constexpr uint32_t kBigPair = 24;
-
+// One wave64 workgroup per 64 consecutive depth-ordered visible pairs.  Their
+// partials are contiguous ([inst_off[s0], inst_off[s0 + 64])), so the wave
+// walks them 64 instances at a time with coalesced loads; each lane finds its
+// pair by binary search over the 64 offsets, a segmented inclusive scan
+// (shuffles, segments are contiguous) sums equal-pair lanes, and the last
+// lane of each segment adds into that pair's LDS accumulator.  A pair gets at
+// most one add per step and steps run in order, so the sums are
+// deterministic.  Balanced whatever the footprint sizes.
 template <typename T>
-__global__ void k_reduce_pairs(const uint32_t* __restrict__ vis_rec, const uint32_t* __restrict__ inst_off,
-                               int64_t n_vis, int64_t n_rec, const T* __restrict__ partial, T* __restrict__ g2d,
-                               uint32_t* __restrict__ big_list, uint32_t* __restrict__ big_count) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n_vis) return;
-  const uint32_t e0 = inst_off[s], e1 = inst_off[s + 1];
-  if (e1 - e0 > kBigPair) {
-    big_list[atomicAdd(big_count, 1u)] = (uint32_t)s;
-    return;
-  }
-  const uint32_t r = vis_rec[s];
-  T acc[kG2];
+__global__ void __launch_bounds__(64) k_reduce_pairs(const uint32_t* __restrict__ vis_rec,
+                                                     const uint32_t* __restrict__ inst_off, int64_t n_vis,
+                                                     int64_t n_rec, const T* __restrict__ partial,
+                                                     T* __restrict__ g2d) {
+  const int lane = threadIdx.x;
+  const int64_t s0 = (int64_t)blockIdx.x * kWave;
+  const int np = (int)(n_vis - s0 < kWave ? n_vis - s0 : kWave);
+  __shared__ uint32_t s_off[kWave + 1];
+  __shared__ T s_acc[kWave][kG2];
+  if (lane <= np) s_off[lane] = inst_off[s0 + lane];
+  if (lane == 0 && np == kWave) s_off[kWave] = inst_off[s0 + kWave];
 #pragma unroll
-  for (int m = 0; m < kG2; ++m) acc[m] = 0;
-  for (uint32_t e = e0; e < e1; ++e) {
-    const T* P = partial + (int64_t)e * kG2;
-#pragma unroll
-    for (int m = 0; m < kG2; ++m) acc[m] += P[m];
-  }
-#pragma unroll
-  for (int m = 0; m < kG2; ++m) g2d[(int64_t)m * n_rec + r] = acc[m];
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_reduce_big(const uint32_t* __restrict__ vis_rec,
-                                                    const uint32_t* __restrict__ inst_off, int64_t n_rec,
-                                                    const T* __restrict__ partial, T* __restrict__ g2d,
-                                                    const uint32_t* __restrict__ big_list,
-                                                    const uint32_t* __restrict__ big_count) {
-  const uint32_t nbig = *big_count;
-  const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  const uint32_t nw = gridDim.x * blockDim.x / kWave;
-  const int lane = __lane_id();
-  for (uint32_t w = wid; w < nbig; w += nw) {
-    const uint32_t s = big_list[w];
-    const uint32_t e0 = inst_off[s], e1 = inst_off[s + 1];
-    T acc[kG2];
-#pragma unroll
-    for (int m = 0; m < kG2; ++m) acc[m] = 0;
-    for (uint32_t e = e0 + lane; e < e1; e += kWave) {
-      const T* P = partial + (int64_t)e * kG2;
-#pragma unroll
-      for (int m = 0; m < kG2; ++m) acc[m] += P[m];
+  for (int m = 0; m < kG2; ++m) s_acc[lane][m] = 0;
+  __syncthreads();
+  const uint32_t e0 = s_off[0], e1 = s_off[np];
+  for (uint32_t base = e0; base < e1; base += kWave) {
+    const uint32_t e = base + (uint32_t)lane;
+    const bool valid = e < e1;
+    int lo = 0, hi = np;   // s_off[lo] <= e < s_off[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (s_off[mid] <= e) lo = mid;
+      else hi = mid;
     }
+    const int p = valid ? lo : -1;
+    T v[kG2];
+    const T* P = partial + (int64_t)(valid ? e : e0) * kG2;
 #pragma unroll
-    for (int m = 0; m < kG2; ++m) acc[m] = wave_sum(acc[m]);
-    if (lane == 0) {
-      const uint32_t r = vis_rec[s];
+    for (int m = 0; m < kG2; ++m) v[m] = valid ? P[m] : (T)0;
 #pragma unroll
-      for (int m = 0; m < kG2; ++m) g2d[(int64_t)m * n_rec + r] = acc[m];
+    for (int off = 1; off < kWave; off <<= 1) {
+      const int pn = __shfl_up(p, off, kWave);
+      const bool same = lane >= off && pn == p;
+#pragma unroll
+      for (int m = 0; m < kG2; ++m) {
+        const T y = __shfl_up(v[m], off, kWave);
+        v[m] += same ? y : (T)0;
+      }
     }
+    const int pnext = __shfl_down(p, 1, kWave);
+    const bool seg_end = valid && (lane == kWave - 1 || pnext != p);
+    if (seg_end) {
+#pragma unroll
+      for (int m = 0; m < kG2; ++m) s_acc[p][m] += v[m];
+    }
+    __syncthreads();
+  }
+  if (lane < np) {
+    const uint32_t r = vis_rec[s0 + lane];
+#pragma unroll
+    for (int m = 0; m < kG2; ++m) g2d[(int64_t)m * n_rec + r] = s_acc[lane][m];
   }
 }
-
-__global__ void k_zero_u32(uint32_t* p) { *p = 0u; }
 
 // --------------------------------------------------- preprocess adjoint
 // Thread per processing index; only active rows work.  Recomputes the
@@ -446,8 +445,7 @@ extern "C" size_t tide_render_bwd_ws_bytes(const tide_bins* bins, int32_t dtype)
   if (!bins) return 0;
   const size_t es = dtype == TIDE_F64 ? 8 : 4;
   return align_up((size_t)(bins->n_inst > 0 ? bins->n_inst : 1) * kG2 * es) +
-         align_up((size_t)kG2 * bins->n_cams * bins->n_pidx * es) +
-         align_up((size_t)(bins->n_vis > 0 ? bins->n_vis : 1) * 4) + align_up(4) + 256;
+         align_up((size_t)kG2 * bins->n_cams * bins->n_pidx * es) + 256;
 }
 
 extern "C" tide_status tide_render_bwd(const tide_pool* pool, const tide_camera* cams, int32_t n_cams,
@@ -472,19 +470,15 @@ extern "C" tide_status tide_render_bwd(const tide_pool* pool, const tide_camera*
   if (proj->dtype == TIDE_F32) {
     float* partial = cv.take<float>((size_t)(bins->n_inst > 0 ? bins->n_inst : 1) * kG2);
     float* g2d = cv.take<float>((size_t)kG2 * nrec);
-    uint32_t* big_list = cv.take<uint32_t>((size_t)(bins->n_vis > 0 ? bins->n_vis : 1));
-    uint32_t* big_count = cv.take<uint32_t>(1);
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, big_count);
+
     TIDE_TIMED("render_bwd", st, hipLaunchKernelGGL(k_render_bwd<float>, dim3(grid), dim3(64), 0, st, bins->ranges, bins->inst_e, bins->inst_rec,
                        (const float*)proj->rec, bins->tiles_x, bins->tiles_y, fr->width, fr->height, bg[0], bg[1],
                        bg[2], (const float*)fr->t_final, fr->last, (const float*)d_dimage, partial));
     TIDE_LAUNCH_CHECK("k_render_bwd");
     if (bins->n_vis > 0)
-      TIDE_TIMED("reduce_pairs", st, hipLaunchKernelGGL(k_reduce_pairs<float>, dim3((uint32_t)ceil_div(bins->n_vis, 256)), dim3(256), 0, st,
-                         bins->vis_rec, bins->inst_off, bins->n_vis, nrec, (const float*)partial, g2d, big_list, big_count));
-    TIDE_TIMED("reduce_big", st, hipLaunchKernelGGL(k_reduce_big<float>, dim3(512), dim3(256), 0, st, bins->vis_rec,
-                                                   bins->inst_off, nrec, (const float*)partial, g2d, big_list,
-                                                   big_count));
+      TIDE_TIMED("reduce_pairs", st, hipLaunchKernelGGL(k_reduce_pairs<float>, dim3((uint32_t)ceil_div(bins->n_vis, kWave)),
+                                                        dim3(kWave), 0, st, bins->vis_rec, bins->inst_off, bins->n_vis, nrec,
+                                                        (const float*)partial, g2d));
     TIDE_LAUNCH_CHECK("k_reduce_pairs");
     const CamSet<float> cs = make_camset<float>(cams, n_cams);
     if (proj->n_pidx > 0)
@@ -495,20 +489,16 @@ extern "C" tide_status tide_render_bwd(const tide_pool* pool, const tide_camera*
   } else {
     double* partial = cv.take<double>((size_t)(bins->n_inst > 0 ? bins->n_inst : 1) * kG2);
     double* g2d = cv.take<double>((size_t)kG2 * nrec);
-    uint32_t* big_list = cv.take<uint32_t>((size_t)(bins->n_vis > 0 ? bins->n_vis : 1));
-    uint32_t* big_count = cv.take<uint32_t>(1);
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, big_count);
+
     TIDE_TIMED("render_bwd", st, hipLaunchKernelGGL(k_render_bwd<double>, dim3(grid), dim3(64), 0, st, bins->ranges, bins->inst_e,
                        bins->inst_rec, (const double*)proj->rec, bins->tiles_x, bins->tiles_y, fr->width,
                        fr->height, (double)bg[0], (double)bg[1], (double)bg[2], (const double*)fr->t_final,
                        fr->last, (const double*)d_dimage, partial));
     TIDE_LAUNCH_CHECK("k_render_bwd");
     if (bins->n_vis > 0)
-      TIDE_TIMED("reduce_pairs", st, hipLaunchKernelGGL(k_reduce_pairs<double>, dim3((uint32_t)ceil_div(bins->n_vis, 256)), dim3(256), 0, st,
-                         bins->vis_rec, bins->inst_off, bins->n_vis, nrec, (const double*)partial, g2d, big_list, big_count));
-    TIDE_TIMED("reduce_big", st, hipLaunchKernelGGL(k_reduce_big<double>, dim3(512), dim3(256), 0, st, bins->vis_rec,
-                                                   bins->inst_off, nrec, (const double*)partial, g2d, big_list,
-                                                   big_count));
+      TIDE_TIMED("reduce_pairs", st, hipLaunchKernelGGL(k_reduce_pairs<double>, dim3((uint32_t)ceil_div(bins->n_vis, kWave)),
+                                                        dim3(kWave), 0, st, bins->vis_rec, bins->inst_off, bins->n_vis, nrec,
+                                                        (const double*)partial, g2d));
     TIDE_LAUNCH_CHECK("k_reduce_pairs");
     const CamSet<double> cs = make_camset<double>(cams, n_cams);
     if (proj->n_pidx > 0)

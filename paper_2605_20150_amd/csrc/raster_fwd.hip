@@ -262,58 +262,47 @@ __global__ void k_compact_vis(const uint32_t* __restrict__ tt, const float* __re
   val[o] = (uint32_t)i;
 }
 
-// Instances of the s-th depth-ordered visible pair, tiles row-major.  A pair
-// covering more than kBigRect tiles is queued for k_emit_big, where a whole
-// wave writes its instances.
-constexpr uint32_t kBigRect = 32;
-
-__global__ void k_emit(const uint32_t* __restrict__ vis_rec, const uint32_t* __restrict__ inst_off,
-                       const uint32_t* __restrict__ rect, int64_t n_vis, int64_t n_pidx, int32_t Tx, int32_t Ty,
-                       uint32_t* __restrict__ tkey, uint32_t* __restrict__ inst_rec, uint32_t* __restrict__ big,
-                       uint32_t* __restrict__ big_count) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n_vis) return;
-  if (inst_off[s + 1] - inst_off[s] > kBigRect) {
-    big[atomicAdd(big_count, 1u)] = (uint32_t)s;
-    return;
-  }
-  const uint32_t r = vis_rec[s];
-  const uint32_t c = (uint32_t)(r / (uint64_t)n_pidx);
-  const uint32_t a = rect[2 * (int64_t)r], b = rect[2 * (int64_t)r + 1];
-  const int x0 = a & 0xffff, y0 = a >> 16, x1 = b & 0xffff, y1 = b >> 16;
-  uint32_t e = inst_off[s];
-  const uint32_t tbase = c * (uint32_t)(Tx * Ty);
-  for (int ty = y0; ty < y1; ++ty)
-    for (int tx = x0; tx < x1; ++tx) {
-      tkey[e] = tbase + (uint32_t)(ty * Tx + tx);
-      inst_rec[e] = r;
-      ++e;
-    }
-}
-
-__global__ void __launch_bounds__(256) k_emit_big(const uint32_t* __restrict__ vis_rec,
-                                                  const uint32_t* __restrict__ inst_off,
-                                                  const uint32_t* __restrict__ rect, int64_t n_pidx, int32_t Tx,
-                                                  int32_t Ty, uint32_t* __restrict__ tkey,
-                                                  uint32_t* __restrict__ inst_rec, const uint32_t* __restrict__ big,
-                                                  const uint32_t* __restrict__ big_count) {
-  const uint32_t nbig = *big_count;
-  const uint32_t nw = gridDim.x * blockDim.x / kWave;
-  const int lane = __lane_id();
-  for (uint32_t w = (blockIdx.x * blockDim.x + threadIdx.x) / kWave; w < nbig; w += nw) {
-    const uint32_t s = big[w];
-    const uint32_t r = vis_rec[s];
+// Instances of the depth-ordered visible pairs, each pair's tiles in
+// row-major order.  One wave64 workgroup per 64 consecutive pairs walks their
+// contiguous instance range [inst_off[s0], inst_off[s0 + 64]) 64 at a time
+// (coalesced writes); a lane finds its pair by binary search over the 64
+// offsets and its tile from the pair's rectangle.  Balanced whatever the
+// footprint sizes.
+__global__ void __launch_bounds__(64) k_emit(const uint32_t* __restrict__ vis_rec,
+                                             const uint32_t* __restrict__ inst_off,
+                                             const uint32_t* __restrict__ rect, int64_t n_vis, int64_t n_pidx,
+                                             int32_t Tx, int32_t Ty, uint32_t* __restrict__ tkey,
+                                             uint32_t* __restrict__ inst_rec) {
+  const int lane = threadIdx.x;
+  const int64_t s0 = (int64_t)blockIdx.x * kWave;
+  const int np = (int)(n_vis - s0 < kWave ? n_vis - s0 : kWave);
+  __shared__ uint32_t s_off[kWave + 1];
+  __shared__ uint32_t s_rec[kWave], s_base[kWave], s_x0[kWave], s_w[kWave];
+  if (lane <= np) s_off[lane] = inst_off[s0 + lane];
+  if (lane == 0 && np == kWave) s_off[kWave] = inst_off[s0 + kWave];
+  if (lane < np) {
+    const uint32_t r = vis_rec[s0 + lane];
     const uint32_t c = (uint32_t)(r / (uint64_t)n_pidx);
     const uint32_t a = rect[2 * (int64_t)r], b = rect[2 * (int64_t)r + 1];
-    const int x0 = a & 0xffff, y0 = a >> 16, x1 = b & 0xffff;
-    const uint32_t rw = (uint32_t)(x1 - x0);
-    const uint32_t e0 = inst_off[s], cnt = inst_off[s + 1] - e0;
-    const uint32_t tbase = c * (uint32_t)(Tx * Ty);
-    for (uint32_t k = lane; k < cnt; k += kWave) {
-      const uint32_t ty = (uint32_t)y0 + k / rw, tx = (uint32_t)x0 + k % rw;
-      tkey[e0 + k] = tbase + ty * (uint32_t)Tx + tx;
-      inst_rec[e0 + k] = r;
+    const uint32_t x0 = a & 0xffff, y0 = a >> 16, x1 = b & 0xffff;
+    s_rec[lane] = r;
+    s_x0[lane] = x0;
+    s_w[lane] = x1 - x0;
+    s_base[lane] = c * (uint32_t)(Tx * Ty) + y0 * (uint32_t)Tx;   // key of the rectangle's first row, column 0
+  }
+  __syncthreads();
+  const uint32_t e0 = s_off[0], e1 = s_off[np];
+  for (uint32_t e = e0 + (uint32_t)lane; e < e1; e += kWave) {
+    int lo = 0, hi = np;   // s_off[lo] <= e < s_off[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (s_off[mid] <= e) lo = mid;
+      else hi = mid;
     }
+    const uint32_t k = e - s_off[lo], w = s_w[lo];
+    const uint32_t row = k / w, col = k - row * w;
+    tkey[e] = s_base[lo] + row * (uint32_t)Tx + s_x0[lo] + col;
+    inst_rec[e] = s_rec[lo];
   }
 }
 
@@ -337,7 +326,6 @@ __global__ void k_ranges(const uint32_t* __restrict__ key, int64_t n, uint32_t* 
 
 struct BinLayout {
   uint32_t *vis_off, *ka, *va, *kb, *vb, *inst_off, *tka, *tva, *tkb, *tvb, *inst_rec, *ranges, *hist;
-  uint32_t *emit_big, *emit_cnt;
   unsigned long long *partial, *totals;
   size_t bytes;
 };
@@ -358,8 +346,6 @@ static BinLayout bin_layout(void* ws, int n_cams, int64_t n_pidx, int64_t n_tile
   L.tvb = cv.take<uint32_t>(cap);
   L.inst_rec = cv.take<uint32_t>(cap);
   L.ranges = cv.take<uint32_t>(2 * (size_t)n_cams * n_tiles);
-  L.emit_big = cv.take<uint32_t>(nv > 0 ? nv : 1);
-  L.emit_cnt = cv.take<uint32_t>(1);
   const int64_t big = nv > cap ? nv : cap;
   const size_t nh = radix_hist_count(big);
   L.hist = cv.take<uint32_t>(nh);
@@ -546,14 +532,9 @@ extern "C" tide_status tide_bin_sort(const tide_proj* proj, int32_t tiles_x, int
     return TIDE_ECAPACITY;
   }
   // 4. emit instances in depth order, keyed by global tile id
-  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, L.emit_cnt, 1, 0u);
-  if (n_vis > 0) {
-    TIDE_TIMED("emit", st, hipLaunchKernelGGL(k_emit, dim3((uint32_t)ceil_div(n_vis, 256)), dim3(256), 0, st, vrec,
-                                              L.inst_off, proj->rect, n_vis, N, tiles_x, tiles_y, L.tka, L.inst_rec,
-                                              L.emit_big, L.emit_cnt));
-    hipLaunchKernelGGL(k_emit_big, dim3(256), dim3(256), 0, st, vrec, L.inst_off, proj->rect, N, tiles_x, tiles_y,
-                       L.tka, L.inst_rec, L.emit_big, L.emit_cnt);
-  }
+  if (n_vis > 0)
+    TIDE_TIMED("emit", st, hipLaunchKernelGGL(k_emit, dim3((uint32_t)ceil_div(n_vis, kWave)), dim3(kWave), 0, st, vrec,
+                                              L.inst_off, proj->rect, n_vis, N, tiles_x, tiles_y, L.tka, L.inst_rec));
   TIDE_LAUNCH_CHECK("k_emit");
   // 5. stable sort by tile; values are emission indices
   int bits = 0;
