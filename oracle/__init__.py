@@ -82,10 +82,10 @@ def _declare_tier(L):
 
 
 def _declare_mlp(L):
-    L.orc_mlp_forward.argtypes = [_d, C.c_int, _i32, C.c_int, C.POINTER(_d), C.POINTER(_d), _d]
-    L.orc_mlp_loss_backward.argtypes = [_d, C.c_int, _i32, C.c_int, C.POINTER(_d), C.POINTER(_d),
-                                        _u8, _u8, C.c_int, _d, C.POINTER(_d), C.POINTER(_d)]
+    _pd = C.POINTER(_d)
     L.orc_bf16_round.argtypes = [_d, C.c_int64, _d]
+    L.orc_mlp_forward.argtypes = [_d, C.c_int, _i32, C.c_int, _pd, _pd, _d]
+    L.orc_mlp_loss_backward.argtypes = [_d, C.c_int, _i32, C.c_int, _pd, _pd, _u8, _u8, C.c_int, _d, _pd, _pd]
 
 
 def _p(a, t):
@@ -292,3 +292,48 @@ def alg1(R, Kcur, Knext_per_cam, age, lam, gamma, C):
     Rn = outR[:n].copy()
     sR, sN = set(R.tolist()), set(Rn.tolist())
     return Rn, sorted(sN - sR), sorted(sR - sN), ag, rank[:n].copy()
+
+
+# --------------------------------------------------------------------------
+# prefetch predictor MLP
+# --------------------------------------------------------------------------
+
+def bf16_round(x):
+    a = _f64(x)
+    out = np.empty_like(a)
+    lib().orc_bf16_round(_p(a, _d), a.size, _p(out, _d))
+    return out
+
+
+def _ptrs(arrs):
+    arr = (C.POINTER(C.c_double) * len(arrs))()
+    for i, a in enumerate(arrs):
+        arr[i] = a.ctypes.data_as(C.POINTER(C.c_double))
+    return arr
+
+
+def mlp_forward(x, Ws, bs):
+    """Ws[l]: [out, in] (already rounded as desired), bs[l]: [out]."""
+    x = _f64(x)
+    Ws = [_f64(w) for w in Ws]
+    bs = [_f64(b) for b in bs]
+    dims = np.ascontiguousarray([Ws[0].shape[1]] + [w.shape[0] for w in Ws], dtype=np.int32)
+    out = np.zeros((x.shape[0], dims[-1]))
+    lib().orc_mlp_forward(_p(x, _d), x.shape[0], _p(dims, _i32), len(Ws), _ptrs(Ws), _ptrs(bs), _p(out, _d))
+    return out
+
+
+def mlp_loss_backward(x, Ws, bs, labels, valid):
+    """Mean BCE-with-logits over (sample, valid output) and its gradients."""
+    x = _f64(x)
+    Ws = [_f64(w) for w in Ws]
+    bs = [_f64(b) for b in bs]
+    dims = np.ascontiguousarray([Ws[0].shape[1]] + [w.shape[0] for w in Ws], dtype=np.int32)
+    lab = np.ascontiguousarray(labels, dtype=np.uint8)
+    val = np.ascontiguousarray(valid, dtype=np.uint8)
+    dW = [np.zeros_like(w) for w in Ws]
+    db = [np.zeros_like(b) for b in bs]
+    out = C.c_double(0.0)
+    lib().orc_mlp_loss_backward(_p(x, _d), x.shape[0], _p(dims, _i32), len(Ws), _ptrs(Ws), _ptrs(bs), _p(lab, _u8),
+                                _p(val, _u8), 0, C.byref(out), _ptrs(dW), _ptrs(db))
+    return out.value, dW, db
