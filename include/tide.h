@@ -323,6 +323,13 @@ tide_status tide_residency_create(const tide_store_cfg* cfg, tide_pool* pool, fl
                                   uint8_t* d_dirty, tide_residency** out);
 tide_status tide_residency_destroy(tide_residency* res);
 
+/* Layout order (Sec. 3.3): perm [n] = the rows sorted by the Morton code of
+ * their centres (xyz at xyz + i * stride, host f32), stably (ties keep row
+ * order).  Each axis is quantised to 2^21 cells over the centres' bounding
+ * box; code bit 3i+a is bit i of axis a's cell index (a = 0, 1, 2 = x, y, z).
+ * Block k of the layout is then rows perm[kB .. (k+1)B). */
+tide_status tide_morton_order(const float* xyz, int64_t n, int64_t stride, int64_t* perm);
+
 /* Layout build (Sec. 3.3, 4.1): writes block k's record to the base segment
  * with zero moments and steps.  params: host f32 [59][rows of block k].
  * Computes the block's sphere: c_k = mean of the member means (fixed),
@@ -378,6 +385,94 @@ tide_status tide_read_block(tide_residency* res, int64_t block, void* dst);
 tide_status tide_tier_get_stats(const tide_residency* res, tide_tier_stats* out);
 /* Host copy of the spheres (f32 [K][4]) as the tier currently sees them. */
 tide_status tide_tier_spheres(const tide_residency* res, float* out, int64_t n_blocks);
+
+/* ------------------------------------------------------------------------
+ * Learned prefetch predictor.  Not part of the paper's method: a small ReLU
+ * MLP maps the recent camera poses to per-block visibility for the next few
+ * iterations, so that the SSD reads of blocks about to enter the working set
+ * start early (host prefetch via tide_prefetch_hint).  Exact Level-1 culling
+ * (Sec. 3.3, Eq. for K_t) stays in charge of what is rendered: a block the
+ * predictor misses is streamed by Alg. 1 as before, so rendered results do
+ * not depend on it.
+ *
+ * Network: n_layers affine layers of widths dims[0] -> dims[1] -> ... ->
+ * dims[n_layers]; ReLU after every layer but the last, whose outputs are
+ * logits (sigmoid = visibility probability).  Every width is a positive
+ * multiple of 8; dims[n_layers] is a multiple of 32 (label bitsets).
+ *
+ * Parameter layout (one flat buffer, P = tide_mlp_param_count()): for each
+ * layer l in order, W_l f32 [dims[l+1]][dims[l]] row-major, then b_l f32
+ * [dims[l+1]].  params is the FP32 master copy; params_bf16 holds the same
+ * values rounded to bfloat16 (nearest, ties to even; uint16 bit patterns);
+ * the products read W from params_bf16 and the biases from params.
+ * Activations, gradients and accumulation are FP32.  The products run on
+ * the bf16 matrix cores: an FP32 operand is split into a bf16 pair
+ * (hi = bf16(a), lo = bf16(a - hi)) and both halves are multiplied, so each
+ * product keeps about 16 significant bits of the FP32 operand.
+ * ---------------------------------------------------------------------- */
+#define TIDE_MLP_MAX_LAYERS 8
+
+typedef struct {
+  int32_t n_layers;
+  int32_t dims[TIDE_MLP_MAX_LAYERS + 1];
+  float* params;          /* device f32 [P], FP32 master (16-byte aligned) */
+  uint16_t* params_bf16;  /* device bf16 bits [P] (16-byte aligned) */
+  float* grad;            /* device f32 [P], written by tide_mlp_bwd */
+  float* exp_avg;         /* device f32 [P], Adam first moment */
+  float* exp_avg_sq;      /* device f32 [P], Adam second moment */
+  int64_t step;           /* Adam steps taken; tide_mlp_adam increments it */
+} tide_mlp;
+
+/* Number of parameters P, or -1 if dims are invalid. */
+int64_t tide_mlp_param_count(const int32_t* dims, int32_t n_layers);
+/* Workspace of tide_mlp_fwd / tide_mlp_bwd for a batch: the hidden
+ * activations of the forward (kept for the backward), the backward's
+ * gradient buffers and the loss partial sums. */
+size_t tide_mlp_ws_bytes(const tide_mlp* mlp, int32_t batch);
+/* params_bf16 <- bf16(params) (after initialising or loading params). */
+tide_status tide_mlp_sync_bf16(const tide_mlp* mlp, void* stream);
+/* logits f32 [batch][dims[L]] = MLP(x), x f32 [batch][dims[0]], both device
+ * and row-major.  Keeps the hidden activations in ws for tide_mlp_bwd. */
+tide_status tide_mlp_fwd(const tide_mlp* mlp, const float* x, int32_t batch, float* logits, void* ws,
+                         size_t ws_bytes, void* stream);
+/* Binary cross-entropy with logits, averaged over batch x (valid outputs):
+ *   l(z, y) = max(z, 0) - z y + log(1 + exp(-|z|)).
+ * label_bits u32 [batch][dims[L] / 32] (bit o % 32 of word o / 32 = label of
+ * output o), valid_bits u32 [dims[L] / 32] (outputs that count; padding
+ * blocks are 0), both device.  Must follow tide_mlp_fwd with the same x,
+ * batch and ws; logits is its output.  Writes the mean loss to d_loss
+ * (device f64 scalar) and overwrites mlp->grad with its gradient. */
+tide_status tide_mlp_bwd(const tide_mlp* mlp, const float* x, const float* logits, const uint32_t* label_bits,
+                         const uint32_t* valid_bits, int32_t batch, double* d_loss, void* ws, size_t ws_bytes,
+                         void* stream);
+/* One Adam step on every parameter from mlp->grad (no weight decay):
+ *   m <- b1 m + (1-b1) g,  v <- b2 v + (1-b2) g^2,
+ *   p <- p - lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps),   t = ++step;
+ * then params_bf16 <- bf16(params). */
+tide_status tide_mlp_adam(tide_mlp* mlp, float lr, float beta1, float beta2, float eps, void* stream);
+/* Threshold: out_bits u32 [batch][n_out / 32], bit set where
+ * logits >= threshold_logit (the logit of the probability threshold). */
+tide_status tide_mlp_predict_bits(const float* logits, int32_t batch, int32_t n_out, float threshold_logit,
+                                  uint32_t* out_bits, void* stream);
+
+/* Host helpers of the predictor's data path.
+ * tide_pose_features: one feature row per history of n_poses consecutive
+ * cameras (oldest first): per pose the 12 values of [R | t / t_scale]
+ * (R row-major, then t), then the ground-plane (x, y) displacement of the
+ * camera centre from the previous pose (0 for the first), 14 floats per
+ * pose; out f32 [n_poses * 14].
+ * tide_cull_bits: union over n_cams cameras of the Level-1 block sets for
+ * the given spheres (f32 [K][4], same six-plane test as tide_cull_blocks),
+ * as a bitset out u32 [n_words] (bit k % 32 of word k / 32; words past K are
+ * zero); n_words >= ceil(K / 32).
+ * tide_block_sphere: the bounding sphere tide_store_put_block computes for a
+ * block (Sec. 3.3): params holds the block's first six parameter columns
+ * (mean xyz, log-scale xyz), column j at params + j * ld, rows <= ld;
+ * out f32 [4] = (cx, cy, cz, r). */
+tide_status tide_pose_features(const tide_camera* cams, int32_t n_poses, double t_scale, float* out);
+tide_status tide_cull_bits(const float* spheres, int64_t n_blocks, const tide_camera* cams, int32_t n_cams,
+                           uint32_t* out, int64_t n_words);
+tide_status tide_block_sphere(const float* params, int64_t ld, int64_t rows, double kappa, float* out);
 
 /* ------------------------------------------------------------------------
  * Timing hook for measurement.  Arms a pair of caller-created HIP events

@@ -75,6 +75,7 @@ def _declare_tier(L):
     L.orc_kappa.argtypes = [_d, C.c_int]
     L.orc_kappa.restype = C.c_double
     L.orc_block_spheres.argtypes = [_d, C.c_int64, C.c_int64, C.c_double, _d]
+    L.orc_morton_order.argtypes = [_d, C.c_int64, C.c_int64, _i64]
     L.orc_cull_blocks.argtypes = [_d, C.c_int64, _d, C.c_int, _u8]
     L.orc_alg1.argtypes = [_i32, C.c_int, _i32, C.c_int, _i32, _i32, C.c_int, _d, C.c_int64, C.c_double,
                            C.c_double, C.c_int, _i32, _i32]
@@ -86,6 +87,8 @@ def _declare_mlp(L):
     L.orc_bf16_round.argtypes = [_d, C.c_int64, _d]
     L.orc_mlp_forward.argtypes = [_d, C.c_int, _i32, C.c_int, _pd, _pd, _d]
     L.orc_mlp_loss_backward.argtypes = [_d, C.c_int, _i32, C.c_int, _pd, _pd, _u8, _u8, C.c_int, _d, _pd, _pd]
+    L.orc_mlp_adam.argtypes = [_d, _d, _d, _d, C.c_int64, C.c_int64, C.c_double, C.c_double, C.c_double,
+                               C.c_double]
 
 
 def _p(a, t):
@@ -337,3 +340,18 @@ def mlp_loss_backward(x, Ws, bs, labels, valid):
     lib().orc_mlp_loss_backward(_p(x, _d), x.shape[0], _p(dims, _i32), len(Ws), _ptrs(Ws), _ptrs(bs), _p(lab, _u8),
                                 _p(val, _u8), 0, C.byref(out), _ptrs(dW), _ptrs(db))
     return out.value, dW, db
+
+
+def mlp_adam(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam step at step number t (1-based); returns new (p, m, v)."""
+    p, g, m, v = (_f64(a).copy() for a in (p, g, m, v))
+    lib().orc_mlp_adam(_p(p, _d), _p(g, _d), _p(m, _d), _p(v, _d), p.size, int(t), lr, b1, b2, eps)
+    return p, m, v
+
+
+def morton_order(xyz):
+    """Stable Morton order of the rows of xyz [n, 3] (2^21 cells per axis)."""
+    x = _f64(xyz)
+    perm = np.zeros(x.shape[0], dtype=np.int64)
+    lib().orc_morton_order(_p(x, _d), x.shape[0], x.shape[1], _p(perm, _i64))
+    return perm

@@ -117,4 +117,17 @@ void orc_mlp_loss_backward(const double* x, int batch, const int32_t* dims, int 
   *loss = total / denom;
 }
 
+// One Adam step (no weight decay) on n parameters, FP64, in place:
+//   m <- b1 m + (1-b1) g,  v <- b2 v + (1-b2) g^2,
+//   p <- p - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+void orc_mlp_adam(double* p, const double* g, double* m, double* v, int64_t n, int64_t t, double lr, double b1,
+                  double b2, double eps) {
+  const double c1 = 1.0 - std::pow(b1, (double)t), c2 = 1.0 - std::pow(b2, (double)t);
+  for (int64_t i = 0; i < n; ++i) {
+    m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+    v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+    p[i] -= lr * (m[i] / c1) / (std::sqrt(v[i] / c2) + eps);
+  }
+}
+
 }  // extern "C"

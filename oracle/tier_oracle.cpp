@@ -71,6 +71,34 @@ double orc_kappa(const double* cams, int n_cams) {
   return k;
 }
 
+// Morton layout order (Sec. 3.3): quantise each axis of the centres to 2^21
+// cells over their bounding box (cell = floor((x - lo) * (2^21 / (hi - lo))),
+// clamped to [0, 2^21 - 1], in double), interleave the cell bits with bit i
+// of axis a at position 3 i + a, and sort the rows stably by that code.
+void orc_morton_order(const double* xyz, int64_t n, int64_t stride, int64_t* perm) {
+  if (n <= 0) return;
+  double lo[3], hi[3];
+  for (int a = 0; a < 3; ++a) lo[a] = hi[a] = xyz[a];
+  for (int64_t i = 0; i < n; ++i)
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = std::min(lo[a], xyz[i * stride + a]);
+      hi[a] = std::max(hi[a], xyz[i * stride + a]);
+    }
+  std::vector<uint64_t> code(n, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    for (int a = 0; a < 3; ++a) {
+      const double s = hi[a] > lo[a] ? 2097152.0 / (hi[a] - lo[a]) : 0.0;
+      double q = std::floor((xyz[i * stride + a] - lo[a]) * s);
+      q = std::min(2097151.0, std::max(0.0, q));
+      const uint64_t cell = (uint64_t)q;
+      for (int b = 0; b < 21; ++b)
+        if ((cell >> b) & 1u) code[i] |= 1ull << (3 * b + a);
+    }
+  }
+  for (int64_t i = 0; i < n; ++i) perm[i] = i;
+  std::stable_sort(perm, perm + n, [&](int64_t x, int64_t y) { return code[x] < code[y]; });
+}
+
 // spheres[k] = (cx, cy, cz, r) for blocks of B consecutive rows of theta[n][59].
 void orc_block_spheres(const double* theta, int64_t n, int64_t B, double kappa, double* spheres) {
   const int64_t K = (n + B - 1) / B;

@@ -83,6 +83,15 @@ class tide_tier_stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+TIDE_MLP_MAX_LAYERS = 8
+
+
+class tide_mlp(C.Structure):
+    _fields_ = [("n_layers", C.c_int32), ("dims", C.c_int32 * (TIDE_MLP_MAX_LAYERS + 1)), ("params", C.c_void_p),
+                ("params_bf16", C.c_void_p), ("grad", C.c_void_p), ("exp_avg", C.c_void_p),
+                ("exp_avg_sq", C.c_void_p), ("step", C.c_int64)]
+
+
 TIDE_TIER_HOST_POOL = 1
 TIDE_TIER_ODIRECT = 2
 
@@ -125,6 +134,17 @@ SIGNATURES = {
     "tide_tier_get_stats": (C.c_int32, [_vp, _P(tide_tier_stats)]),
     "tide_tier_spheres": (C.c_int32, [_vp, _P(C.c_float), C.c_int64]),
     "tide_timer_clear": (C.c_int32, []),
+    "tide_mlp_param_count": (C.c_int64, [_pi32, C.c_int32]),
+    "tide_mlp_ws_bytes": (C.c_size_t, [_P(tide_mlp), C.c_int32]),
+    "tide_mlp_sync_bf16": (C.c_int32, [_P(tide_mlp), _vp]),
+    "tide_mlp_fwd": (C.c_int32, [_P(tide_mlp), _vp, C.c_int32, _vp, _vp, C.c_size_t, _vp]),
+    "tide_mlp_bwd": (C.c_int32, [_P(tide_mlp), _vp, _vp, _vp, _vp, C.c_int32, _vp, _vp, C.c_size_t, _vp]),
+    "tide_mlp_adam": (C.c_int32, [_P(tide_mlp), C.c_float, C.c_float, C.c_float, C.c_float, _vp]),
+    "tide_mlp_predict_bits": (C.c_int32, [_vp, C.c_int32, C.c_int32, C.c_float, _vp, _vp]),
+    "tide_pose_features": (C.c_int32, [_P(tide_camera), C.c_int32, C.c_double, _P(C.c_float)]),
+    "tide_cull_bits": (C.c_int32, [_P(C.c_float), C.c_int64, _P(tide_camera), C.c_int32, _P(C.c_uint32), C.c_int64]),
+    "tide_morton_order": (C.c_int32, [_P(C.c_float), C.c_int64, C.c_int64, _P(C.c_int64)]),
+    "tide_block_sphere": (C.c_int32, [_P(C.c_float), C.c_int64, C.c_int64, C.c_double, _P(C.c_float)]),
 }
 
 _lib = None

@@ -20,6 +20,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "blocks.h"
 #include "common.h"
 
 namespace tide {
@@ -614,23 +615,7 @@ tide_status tide_store_put_block(tide_residency* res, int64_t block, const float
   std::vector<char> buf(res->rec, 0);
   float* P = (float*)buf.data();
   for (int j = 0; j < kCols; ++j) std::memcpy(P + (size_t)j * res->B, params + (size_t)j * rows, rows * sizeof(float));
-  // sphere: centre = mean of member means, radius covers every 3-sigma footprint
-  double c[3] = {0, 0, 0};
-  for (int64_t i = 0; i < rows; ++i)
-    for (int a = 0; a < 3; ++a) c[a] += P[(size_t)a * res->B + i];
-  for (int a = 0; a < 3; ++a) c[a] /= (double)rows;
-  double rad = 0;
-  for (int64_t i = 0; i < rows; ++i) {
-    double d2 = 0;
-    for (int a = 0; a < 3; ++a) {
-      const double d = P[(size_t)a * res->B + i] - c[a];
-      d2 += d * d;
-    }
-    const double ls = std::max(P[3 * (size_t)res->B + i], std::max(P[4 * (size_t)res->B + i], P[5 * (size_t)res->B + i]));
-    rad = std::max(rad, std::sqrt(d2) + 3.0 * res->kappa * std::exp(ls));
-  }
-  for (int a = 0; a < 3; ++a) res->h_spheres[4 * block + a] = (float)c[a];
-  res->h_spheres[4 * block + 3] = (float)(rad * (1.0 + 1e-6) + 1e-6);   // rounded up
+  block_sphere(P, res->B, rows, res->kappa, &res->h_spheres[4 * block]);
   if (res->store.odirect) {
     char* al = res->alloc_host(res->rec);
     std::memcpy(al, buf.data(), res->rec);
@@ -685,33 +670,17 @@ tide_status tide_store_open(tide_residency* res) {
   return upload_spheres(res);
 }
 
-// Level 1 (Sec. 3.3): six planes per camera, a sphere is culled when its
-// signed distance to some plane is below -r_k.
+// Level 1 (Sec. 3.3), per camera (CullCam).
 tide_status tide_cull_blocks(const tide_residency* res, const tide_camera* cams, int32_t n_cams, int32_t* out_ids,
                              int32_t* counts, int64_t cap) {
   TIDE_CHECK_ARG(res && cams && out_ids && counts, "null argument");
   TIDE_CHECK_ARG(n_cams >= 1 && n_cams <= TIDE_MAX_CAMS, "bad n_cams");
   int64_t n = 0;
   for (int ci = 0; ci < n_cams; ++ci) {
-    const tide_camera& c = cams[ci];
-    const double Tx = std::ceil(c.width / 16.0), Ty = std::ceil(c.height / 16.0);
-    const double xl = -3.0, xr = 16.0 * Tx + 3.0, yt = -3.0, yb = 16.0 * Ty + 3.0;
-    const double nl = std::sqrt(c.fx * c.fx + (c.cx - xl) * (c.cx - xl));
-    const double nr = std::sqrt(c.fx * c.fx + (xr - c.cx) * (xr - c.cx));
-    const double nt = std::sqrt(c.fy * c.fy + (c.cy - yt) * (c.cy - yt));
-    const double nb = std::sqrt(c.fy * c.fy + (yb - c.cy) * (yb - c.cy));
+    const CullCam cc(cams[ci]);
     int32_t cnt = 0;
     for (int64_t k = 0; k < res->K; ++k) {
-      const float* s = &res->h_spheres[4 * k];
-      double p[3];
-      for (int i = 0; i < 3; ++i) p[i] = c.R[3 * i] * s[0] + c.R[3 * i + 1] * s[1] + c.R[3 * i + 2] * s[2] + c.t[i];
-      const double r = s[3];
-      const bool keep = !(p[2] - c.z_near < -r) && !(c.z_far - p[2] < -r) &&
-                        !((c.fx * p[0] + (c.cx - xl) * p[2]) / nl < -r) &&
-                        !(((xr - c.cx) * p[2] - c.fx * p[0]) / nr < -r) &&
-                        !((c.fy * p[1] + (c.cy - yt) * p[2]) / nt < -r) &&
-                        !(((yb - c.cy) * p[2] - c.fy * p[1]) / nb < -r);
-      if (!keep) continue;
+      if (!cc.keep(&res->h_spheres[4 * k])) continue;
       if (n >= cap) {
         set_error("cull output capacity %lld exceeded", (long long)cap);
         return TIDE_ECAPACITY;

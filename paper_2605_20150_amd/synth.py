@@ -168,3 +168,101 @@ def dense_scene(n: int, seed: int, extent: float = 1.0, logscale_mu: float = -2.
     th = _attributes(rng, n, logscale_mu, logscale_sigma)
     th[:, 0:3] = mu
     return th.astype(np.float32)
+
+
+# ---------------------------------------------------------------------------
+# Street-level city and walks (out-of-core streaming and the predictor)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class City:
+    extent: float          # the city is [-extent/2, extent/2]^2 (metres)
+    pitch: float           # street spacing (street centre lines at multiples of pitch)
+    street_width: float
+
+
+def city_scene(n: int, seed: int, extent: float = 4000.0, pitch: float = 100.0, street_width: float = 20.0,
+               buildings_per_km2: float = 400.0, ground_frac: float = 0.1,
+               logscale_mu: float = -1.0, logscale_sigma: float = 0.7):
+    """A synthetic city of ``n`` Gaussians (rows in generation order, not
+    spatially sorted): streets every ``pitch`` metres, ``street_width`` wide;
+    buildings from a Poisson process over the non-street area with square
+    footprints of side U(10, 40) m and heights U(10, 100) m; each building
+    gets Gaussians in proportion to its footprint area, uniform over its
+    footprint x [0, h]; ``ground_frac`` of the Gaussians lie on the street
+    ground (z ~ N(0, 0.1^2)).  Attributes as the aerial recipe."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    half = extent / 2.0
+    inner = pitch - street_width
+    n_lots = int(round(extent / pitch)) ** 2
+    expected = buildings_per_km2 * (extent / 1000.0) ** 2 * (inner / pitch) ** 2
+    n_b = max(1, int(rng.poisson(expected)))
+    lot = rng.integers(0, n_lots, size=n_b)
+    per_row = int(round(extent / pitch))
+    side = rng.uniform(10.0, 40.0, size=n_b)
+    h = rng.uniform(10.0, 100.0, size=n_b)
+    # footprint centre inside its lot, footprint kept off the street
+    lo = street_width / 2.0 + np.minimum(side / 2.0, inner / 2.0)
+    off_x = rng.uniform(lo, pitch - lo)
+    off_y = rng.uniform(lo, pitch - lo)
+    bx = -half + (lot % per_row) * pitch + off_x
+    by = -half + (lot // per_row) * pitch + off_y
+    n_ground = int(round(ground_frac * n))
+    w = side * side
+    counts = rng.multinomial(n - n_ground, w / w.sum())
+    idx = np.repeat(np.arange(n_b), counts)
+    mu = np.empty((n, 3))
+    m = n - n_ground
+    mu[:m, 0] = bx[idx] + (rng.uniform(-0.5, 0.5, size=m) * side[idx])
+    mu[:m, 1] = by[idx] + (rng.uniform(-0.5, 0.5, size=m) * side[idx])
+    mu[:m, 2] = rng.uniform(0.0, 1.0, size=m) * h[idx]
+    # street ground: along a random street line, across its width
+    along = rng.uniform(-half, half, size=n_ground)
+    line = -half + pitch * (rng.integers(0, per_row, size=n_ground) + 0.5) - pitch / 2.0
+    across = rng.uniform(-street_width / 2.0, street_width / 2.0, size=n_ground)
+    horiz = rng.integers(0, 2, size=n_ground).astype(bool)
+    mu[m:, 0] = np.where(horiz, along, line + across)
+    mu[m:, 1] = np.where(horiz, line + across, along)
+    mu[m:, 2] = rng.normal(0.0, 0.1, size=n_ground)
+    th = _attributes(rng, n, logscale_mu, logscale_sigma)
+    th[:, 0:3] = mu
+    return th.astype(np.float32), City(extent, pitch, street_width)
+
+
+def street_walk(city: City, n_poses: int, seed: int, step: float = 1.0, eye_height: float = 1.7,
+                width: int = 1600, height: int = 900, hfov_deg: float = 60.0, z_far: float = 1000.0,
+                z_near: float = 0.2) -> list[Camera]:
+    """A random walk along the street centre lines: ``step`` metres per pose
+    at ``eye_height``, looking along the direction of travel; at every
+    intersection a uniformly chosen new direction among those that neither
+    turn back nor leave the city."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    half = city.extent / 2.0
+    p = city.pitch
+    n_lines = int(round(city.extent / p))
+    coords = -half + p * np.arange(n_lines + 1)     # street centre lines (incl. the border)
+    dirs = [(1.0, 0.0), (0.0, 1.0), (-1.0, 0.0), (0.0, -1.0)]
+    x = float(coords[rng.integers(1, n_lines)])
+    y = float(coords[rng.integers(1, n_lines)])
+    d = int(rng.integers(0, 4))
+    f = focal_for_hfov(width, hfov_deg)
+    steps_per_block = int(round(p / step))
+    out = []
+    k = 0
+    for _ in range(n_poses):
+        if k % steps_per_block == 0:
+            ok = []
+            for nd in range(4):
+                if nd == (d + 2) % 4:
+                    continue
+                nx, ny = x + dirs[nd][0] * p, y + dirs[nd][1] * p
+                if -half - 1e-6 <= nx <= half + 1e-6 and -half - 1e-6 <= ny <= half + 1e-6:
+                    ok.append(nd)
+            d = ok[int(rng.integers(0, len(ok)))] if ok else (d + 2) % 4
+        eye = (x, y, eye_height)
+        out.append(look_at(eye, (x + dirs[d][0], y + dirs[d][1], eye_height), (0.0, 0.0, 1.0), width, height, f,
+                           z_near, z_far))
+        x += dirs[d][0] * step
+        y += dirs[d][1] * step
+        k += 1
+    return out

@@ -111,3 +111,21 @@ def test_separable_toy_problem_converges():
             v[k] = 0.999 * v[k] + 0.001 * g * g
             p -= 1e-2 * (m[k] / (1 - 0.9 ** t)) / (np.sqrt(v[k] / (1 - 0.999 ** t)) + 1e-8)
     assert first > 0.5 and L < 0.1
+
+
+def test_adam_closed_forms():
+    rng = np.random.default_rng(65)
+    g = rng.normal(size=200)
+    p0 = rng.normal(size=200)
+    # first step: m_hat = g, v_hat = g^2, so the move is lr g / (|g| + eps)
+    p1, m, v = oracle.mlp_adam(p0, g, np.zeros(200), np.zeros(200), 1, 1e-3, eps=1e-8)
+    assert np.allclose(p1, p0 - 1e-3 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+    # a constant gradient keeps m_hat = g and v_hat = g^2 at every step
+    p = p1
+    for t in range(2, 30):
+        p_prev = p
+        p, m, v = oracle.mlp_adam(p, g, m, v, t, 1e-3, eps=0.0)
+        assert np.allclose(p_prev - p, 1e-3 * np.sign(g), rtol=1e-9, atol=1e-15)
+    # zero gradient from a zero state leaves everything at zero
+    z = oracle.mlp_adam(p0, np.zeros(200), np.zeros(200), np.zeros(200), 1, 1e-3)
+    assert np.array_equal(z[0], p0) and not z[1].any() and not z[2].any()

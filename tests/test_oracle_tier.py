@@ -118,3 +118,31 @@ def test_alg1_identities_random():
         if C >= len(Kunion):
             assert Kunion <= sN
         R = Rn.tolist()
+
+
+def test_morton_order_closed_forms():
+    # the corners of a box sort along the Z curve: x is the lowest bit, then y, then z
+    corners = np.array([[x, y, z] for z in (0, 1) for y in (0, 1) for x in (0, 1)], dtype=np.float64) * [4, 2, 7]
+    shuffle = np.random.default_rng(3).permutation(8)
+    perm = oracle.morton_order(corners[shuffle])
+    assert np.array_equal(corners[shuffle][perm], corners)
+    # points on one axis line sort by that coordinate (a plain stable sort)
+    rng = np.random.default_rng(4)
+    x = rng.uniform(-5, 5, size=500)
+    line = np.stack([x, np.full(500, 2.0), np.full(500, -1.0)], 1)
+    assert np.array_equal(oracle.morton_order(line), np.argsort(x, kind="stable"))
+    # equal centres keep their row order
+    dup = np.repeat(rng.uniform(size=(10, 3)), 5, axis=0)[rng.permutation(50)]
+    perm = oracle.morton_order(dup)
+    for i in range(49):
+        if np.array_equal(dup[perm[i]], dup[perm[i + 1]]):
+            assert perm[i] < perm[i + 1]
+    # the order is a permutation and is invariant under a positive affine map of the centres
+    pts = rng.normal(size=(300, 3))
+    p1 = oracle.morton_order(pts)
+    assert sorted(p1.tolist()) == list(range(300))
+    # x-major 2^k grid: the cells of a 4x4x1 grid interleave as a 2-D Z curve
+    g = np.array([[i, j, 0.0] for j in range(4) for i in range(4)]) / 3.0 * (1 - 1e-12)
+    order = oracle.morton_order(g)
+    ij = [(int(round(g[o, 0] * 3)), int(round(g[o, 1] * 3))) for o in order]
+    assert ij[:4] == [(0, 0), (1, 0), (0, 1), (1, 1)] and ij[4:8] == [(2, 0), (3, 0), (2, 1), (3, 1)]
