@@ -209,10 +209,12 @@ class IoPool {
     cv_.notify_all();
     for (auto& t : th_) t.join();
   }
-  void submit(std::function<void()> f) {
+  // Demand work (reads the next iteration needs, write-backs) is served
+  // before speculative prefetch reads; each class in FIFO order.
+  void submit(std::function<void()> f, bool speculative = false) {
     {
       std::lock_guard<std::mutex> lk(mu_);
-      q_.push_back(std::move(f));
+      (speculative ? low_ : q_).push_back(std::move(f));
     }
     cv_.notify_one();
   }
@@ -223,16 +225,17 @@ class IoPool {
       std::function<void()> f;
       {
         std::unique_lock<std::mutex> lk(mu_);
-        cv_.wait(lk, [this] { return stop_ || !q_.empty(); });
-        if (stop_ && q_.empty()) return;
-        f = std::move(q_.front());
-        q_.pop_front();
+        cv_.wait(lk, [this] { return stop_ || !q_.empty() || !low_.empty(); });
+        if (stop_ && q_.empty() && low_.empty()) return;
+        auto& from = q_.empty() ? low_ : q_;
+        f = std::move(from.front());
+        from.pop_front();
       }
       f();
     }
   }
   std::vector<std::thread> th_;
-  std::deque<std::function<void()>> q_;
+  std::deque<std::function<void()>> q_, low_;
   std::mutex mu_;
   std::condition_variable cv_;
   bool stop_ = false;
@@ -276,6 +279,9 @@ struct tide_residency {
     char* buf = nullptr;
     bool valid = false, loading = false, dirty = false, flushing = false, prefetched = false;
     bool undecided = false;      // written back before its dirty flag was read; pinned until then
+    bool spec_read = false;      // the pending read was queued as a speculative prefetch
+    bool read_claimed = false;   // an I/O thread has started the pending read
+    uint64_t read_seq = 0;       // identifies the pending read; stale queued copies skip
     hipEvent_t fence = nullptr;  // last device copy that reads or writes buf
     std::list<int>::iterator it;
   };
@@ -417,12 +423,17 @@ struct tide_residency {
       cv.notify_all();
     });
   }
-  void start_read(int idx) {
-    Entry& e = ent[idx];
-    e.loading = true;
-    const int64_t blk = e.block;
-    char* buf = e.buf;
-    io->submit([this, idx, blk, buf] {
+  // A read of entry idx's block into its buffer.  The same read may be queued
+  // twice (a prefetch promoted to demand priority); the first copy to run
+  // claims it and the other, or any copy left from an older read of the
+  // entry, does nothing.
+  std::function<void()> read_task(int idx, uint64_t seq, int64_t blk, char* buf) {
+    return [this, idx, seq, blk, buf] {
+      {
+        std::lock_guard<std::mutex> g(mu);
+        if (ent[idx].read_seq != seq || ent[idx].read_claimed || !ent[idx].loading) return;
+        ent[idx].read_claimed = true;
+      }
       const tide_status r = store.read(blk, buf);
       std::lock_guard<std::mutex> g(mu);
       if (r != TIDE_OK) io_error = r;
@@ -430,7 +441,22 @@ struct tide_residency {
       ent[idx].loading = false;
       ent[idx].valid = true;
       cv.notify_all();
-    });
+    };
+  }
+  void start_read(int idx, bool speculative = false) {
+    Entry& e = ent[idx];
+    e.loading = true;
+    e.read_claimed = false;
+    e.spec_read = speculative;
+    ++e.read_seq;
+    io->submit(read_task(idx, e.read_seq, e.block, e.buf), speculative);
+  }
+  // A pending prefetch read that is now needed moves to demand priority.
+  void promote(int idx) {
+    Entry& e = ent[idx];
+    if (!e.loading || !e.spec_read || e.read_claimed) return;
+    e.spec_read = false;
+    io->submit(read_task(idx, e.read_seq, e.block, e.buf), false);
   }
   // Entry for block k with its newest data, reading from the SSD if needed
   // (blocking).  Counts a hit or a miss.
@@ -439,6 +465,7 @@ struct tide_residency {
     Entry& e = ent[idx];
     if (e.valid || e.loading) st.host_hits++;
     else { st.host_misses++; start_read(idx); }
+    promote(idx);
     cv.wait(lk, [&] { return !ent[idx].loading; });
     if (ent[idx].prefetched) { st.prefetch_used++; ent[idx].prefetched = false; }
     wait_fence(ent[idx]);   // a write-back copy into this entry may still be in flight on another stream
@@ -903,6 +930,7 @@ tide_status tide_stream_delta(tide_residency* res, const int32_t* knext_ids, con
     } else {
       if (!e.loading) { res->st.host_misses++; res->start_read(idx); }
       else if (e.prefetched) { res->st.prefetch_used++; e.prefetched = false; }
+      res->promote(idx);
       res->pending_h2d.push_back(k);
     }
     return TIDE_OK;
@@ -955,7 +983,7 @@ tide_status tide_prefetch_hint(tide_residency* res, const int32_t* blocks, int32
     if (!room) break;
     const int idx = res->entry_for(k, lk);
     res->ent[idx].prefetched = true;
-    res->start_read(idx);
+    res->start_read(idx, true);
     res->st.prefetch_issued++;
   }
   return TIDE_OK;

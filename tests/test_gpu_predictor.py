@@ -147,14 +147,16 @@ def test_adam_matches_oracle():
         g = (rng.normal(0, 1e-2, mlp.P) * (rng.uniform(size=mlp.P) < 0.9)).astype(np.float32)
         mlp.grad.copy_(torch.from_numpy(g))
         mlp.adam(1e-3, 0.9, 0.999, 1e-8)
-        p0, m0, v0 = oracle.mlp_adam(p0, g.astype(np.float64), m0, v0, t, 1e-3, 0.9, 0.999, 1e-8)
+        # the call takes single-precision hyperparameters: the oracle gets the same values
+        f = [float(np.float32(c)) for c in (1e-3, 0.9, 0.999, 1e-8)]
+        p0, m0, v0 = oracle.mlp_adam(p0, g.astype(np.float64), m0, v0, t, *f)
     torch.cuda.synchronize()
     assert mlp.step == 3
     p = mlp.params.cpu().numpy().astype(np.float64)
     m = mlp.exp_avg.cpu().numpy().astype(np.float64)
     v = mlp.exp_avg_sq.cpu().numpy().astype(np.float64)
-    assert np.abs(m - m0).max() <= 1e-6 * np.abs(m0).max()
-    assert np.abs(v - v0).max() <= 1e-6 * np.abs(v0).max()
+    assert np.abs(m - m0).max() <= 2e-6 * np.abs(m0).max()
+    assert np.abs(v - v0).max() <= 2e-6 * np.abs(v0).max()
     assert np.abs(p - p0).max() <= 1e-6
     # the bf16 copy is the rounding of the new FP32 master
     wb = (mlp.params_bf16.cpu().numpy().astype(np.uint16).astype(np.uint32) << 16).view(np.float32)
@@ -169,3 +171,53 @@ def test_threshold_bits():
     bits = mlp.predict_bits(torch.from_numpy(z).cuda(), 0.25).cpu().numpy().view(np.uint32)
     ref = np.packbits((z >= np.float32(0.25)).astype(np.uint8), axis=1, bitorder="little").view(np.uint32)
     assert np.array_equal(bits, ref)
+
+
+def test_trained_predictor_recall_precision_and_stall_gain():
+    """Dry-run pairs from street walks over a synthetic city, training on the
+    GPU kernels, then a held-out walk: recall / precision against exact
+    culling, and the simulated-clock stall with and without its hints."""
+    sys.path.insert(0, __import__("os").path.dirname(__file__))
+    from tier_clock import ClockConfig, dry_city, simulate, walk_sets
+    sp, city = dry_city(90, 1000.0)
+    K = sp.shape[0]
+    words = (K + 31) // 32
+    z_far = 300.0
+    say(f"case: city {K} blocks, z_far {z_far}")
+    Xs, Ys = [], []
+    for seed in range(100, 116):
+        batches, _ = walk_sets(sp, city, seed, 400, z_far)
+        X, Y = P.log_pairs(sp, batches, words)
+        Xs.append(X)
+        Ys.append(Y)
+    X, Y = np.concatenate(Xs), np.concatenate(Ys)
+    valid = P.valid_mask(K, words)
+    base = np.unpackbits(Y.view(np.uint8)).sum() / (Y.shape[0] * P.HORIZON * K)
+    mlp = P.MLP([112, 512, 512, 512, 512, P.HORIZON * words * 32], seed=3,
+                out_bias=math.log(base / (1 - base)))
+    out = P.train(mlp, X, Y, valid, epochs=20, batch=256, lr=1e-3, seed=4)
+    l = out["losses"]
+    say(f"pairs {X.shape[0]}, base rate {base:.4f}, loss {l[:10].mean():.4f} -> {l[-10:].mean():.4f}, "
+        f"val recall {out['val_recall']:.4f} precision {out['val_precision']:.4f} thr {out['threshold_logit']:.3f}")
+    assert l[-10:].mean() < 0.7 * l[:10].mean()
+    # held-out walk
+    batches, sets = walk_sets(sp, city, 34, 300, z_far)
+    Xt, Yt = P.log_pairs(sp, batches, words)
+    z = torch.cat([mlp.forward(torch.from_numpy(Xt[i:i + 256]).cuda()).clone() for i in range(0, Xt.shape[0], 256)])
+    bits = mlp.predict_bits(z, out["threshold_logit"]).cpu().numpy().view(np.uint32) & valid[None, :]
+    rec, prec = P.recall_precision(bits, Yt)
+    say(f"held-out recall {rec:.4f} precision {prec:.4f}")
+    assert rec >= 0.9 and prec >= 2 * base
+    hints = [None] * len(sets)
+    for t in range(Xt.shape[0]):
+        hints[t] = sorted(set(int(k) for h in range(P.HORIZON)
+                              for k in P.bits_to_ids(bits[t, h * words:(h + 1) * words], K)))
+    sizes = [len(set(k for s in b for k in s)) for b in sets]
+    cfg = ClockConfig(capacity=2 * max(sizes) + 8, host_blocks=4 * max(sizes), ssd_ms=8.0, h2d_ms=1.0, c0_ms=40.0,
+                      c1_ms=0.0)
+    exact = simulate(sets, cfg)
+    pred = simulate(sets, cfg, hints=hints)
+    say(f"|K_t| {min(sizes)}..{max(sizes)}; stall exact-only {exact.total_stall_ms:.1f} ms, with predictor "
+        f"{pred.total_stall_ms:.1f} ms; prefetch reads {pred.prefetch_reads}, used {pred.prefetch_used}")
+    assert pred.render_sets == exact.render_sets
+    assert pred.total_stall_ms < exact.total_stall_ms

@@ -75,3 +75,40 @@ def test_out_of_core_equals_all_resident(tmp_path):
     assert st["sync_fetches"] == len(O.k_sets[0])     # only the cold start
     O.tier.checkpoint()
     O.tier.close()
+
+
+def test_predictor_hints_leave_results_identical(tmp_path):
+    """Out-of-core training with the learned prefetch hints equals the
+    all-resident run bit for bit (hints only move SSD reads earlier)."""
+    from paper_2605_20150_amd import predictor as P
+    theta = strip_scene()
+    B = 4096
+    T = 24
+    batches = walk(T)
+    rast = Rasterizer("cuda")
+    tpool = Pool.from_dense(torch.tensor(synth.perturbed(theta, 0.05, 51), device="cuda"), B)
+    targets = []
+    for t in range(T):
+        _, _, fr = rast.forward(tpool, batches[t])
+        targets.append(fr.image.clone())
+    A = ResidentTrainer(theta, B)
+    O = OutOfCoreTrainer(theta, B, str(tmp_path / "store"), capacity=12, spare_slots=4, host_cache_blocks=10)
+    sp = O.tier.host_spheres()
+    K = sp.shape[0]
+    words = (K + 31) // 32
+    X, Y = P.log_pairs(sp, walk(36), words)      # the walk covers the strip up to x = 340 m
+    mlp = P.MLP([112, 128, 128, P.HORIZON * words * 32], seed=1)
+    out = P.train(mlp, X, Y, P.valid_mask(K, words), epochs=60, batch=16, lr=1e-3, seed=2)
+    say(f"predictor: {X.shape[0]} pairs, val recall {out['val_recall']:.3f} precision {out['val_precision']:.3f}")
+    O.predictor = P.Predictor(mlp, out["threshold_logit"], K, words)
+    for t in range(T):
+        fa, la = A.iterate(batches[t], targets[t])
+        fo, lo = O.iterate(batches[t], targets[t], batches[t + 1])
+        torch.cuda.synchronize()
+        assert image_digest(fa.image) == image_digest(fo.image), f"iteration {t}"
+        assert float(la) == float(lo)
+    st = O.tier.stats()
+    say(f"tier stats: {st}")
+    assert np.array_equal(A.params(), O.params())
+    assert st["prefetch_issued"] > 0 and O.predictor.hinted > 0
+    O.tier.close()
