@@ -31,6 +31,13 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 # Algorithmic work per unit (counted from the formulas each kernel evaluates)
 FLOPS_PER_FWD_VISIT = 21      # offset 2, exponent 8, exp 1, alpha 1, transmittance 2, weight 1, colour 6
 FLOPS_PER_BWD_VISIT = 64      # the forward terms plus T recovery, colour/alpha/conic/mean adjoints
+# HBM traffic per launch of the dominant kernel from two rocprofv3 counter
+# passes (FETCH_SIZE, WRITE_SIZE) of this benchmark, each scaled by what the
+# counter reads for a plain 1 GiB device copy (x1.9999 and x1.0000), and the
+# hash of the kernel's sources when they were taken: the figure is reported
+# only while the sources are unchanged.
+TRAFFIC = {"render_bwd": {"bytes": 3679.8e6, "sources": ["raster_bwd.hip", "raster.h"],
+                          "sha256_16": "12f7a24f566ed829"}}
 KERNELS = ["preprocess", "compact_vis", "emit", "render_fwd", "loss_fwd", "loss_bwd", "render_bwd",
            "reduce_pairs", "adjoint", "adam"]
 
@@ -43,6 +50,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-blobs", type=int, default=200)
     ap.add_argument("--per-blob", type=int, default=5000)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed region, one plain 1 GiB device-to-device copy (a kernel of known "
+                         "traffic for scaling hardware byte counters)")
     return ap.parse_args()
 
 
@@ -65,6 +75,20 @@ def algorithmic_bytes(kernel, n_pidx, n_kept, n_vis, n_inst, n_active, pixels, V
     if kernel in ("loss_bwd",):
         return pixels * 3 * (12 + 8 + 4)
     return 0
+
+
+def measured_traffic(kernel):
+    """Counter-measured bytes per launch, or None if the kernel's sources have
+    changed since the counters were taken."""
+    import hashlib
+    t = TRAFFIC.get(kernel)
+    if t is None:
+        return None
+    h = hashlib.sha256()
+    for f in t["sources"]:
+        with open(os.path.join(ROOT, "paper_2605_20150_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return t["bytes"] if h.hexdigest()[:16] == t["sha256_16"] else None
 
 
 def cpu_baseline(theta, cams, targets0):
@@ -190,12 +214,13 @@ def main():
     if dominant in ("render_fwd", "render_bwd"):
         ach = fwd_tflops if dominant == "render_fwd" else bwd_tflops
         roof = {"kernel": dominant, "bound": "alu", "achieved": round(ach, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(ach / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None}
+                "unit": "TFLOP/s", "frac": round(ach / FP32_VECTOR_PEAK_TFLOPS, 4),
+                "traffic": measured_traffic(dominant)}
     else:
         by = algorithmic_bytes(dominant, pool.n_pidx, n_kept, n_vis, n_inst, n_active, pixels, V)
         ach = by / (kern_ms[dominant] * 1e-3) / 1e9
         roof = {"kernel": dominant, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dominant)}
 
     out = {
         "metric": METRIC, "value": round(iters, 3), "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
@@ -214,6 +239,13 @@ def main():
         "stall_s_per_iter": 0.0,
         "roofline": roof,
     }
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_cpu_baseline:
         tg0 = targets[0][:1].double().cpu().numpy()
         out["cpu_baseline"] = cpu_baseline(theta, cams, tg0)
