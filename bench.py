@@ -50,6 +50,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-blobs", type=int, default=200)
     ap.add_argument("--per-blob", type=int, default=5000)
+    ap.add_argument("--workload", choices=["aerial", "city"], default="aerial",
+                    help="aerial: resident training (default); city: out-of-core street city, exact-only "
+                         "streaming against predictor-hinted streaming")
+    ap.add_argument("--city-blocks", type=int, default=954, help="blocks of 65536 Gaussians (954 = 1 km^2)")
+    ap.add_argument("--city-iters", type=int, default=150)
+    ap.add_argument("--city-dir", default="/tmp/tide_city_store")
+    ap.add_argument("--city-host-blocks", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, one plain 1 GiB device-to-device copy (a kernel of known "
                          "traffic for scaling hardware byte counters)")
@@ -120,12 +127,84 @@ def cpu_baseline(theta, cams, targets0):
             "visits_per_s_fwd": float(r["visits"].sum()) / (t1 - t0)}
 
 
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def city_main(args):
+    """Out-of-core street city: the same held-out walk trained from the same
+    store with exact-culling-only streaming and with the predictor's hints."""
+    import math
+    import shutil
+
+    import numpy as np
+    import torch
+
+    from paper_2605_20150_amd import city as CT
+    from paper_2605_20150_amd import predictor as P
+
+    B = 65536
+    rec = B * (3 * 59 * 4 + 4)
+    free = CT.free_bytes(args.city_dir)
+    n_blocks = min(args.city_blocks, int(0.6 * free // rec))
+    extent = 1000.0 * math.sqrt(n_blocks / 954.0)
+    z_far = 300.0
+    log(f"city: {n_blocks} blocks of {B} over {extent:.0f} m, store {n_blocks * rec / 1e9:.1f} GB "
+        f"({free / 1e9:.0f} GB free)")
+    shutil.rmtree(args.city_dir, ignore_errors=True)
+    N, city, spheres, build_s = CT.build_store(args.city_dir, n_blocks, B, 30, extent, log=log)
+    predictor, pinfo = CT.train_predictor(spheres, city, z_far, range(100, 116), 400, log=log)
+    T = args.city_iters
+    batches = CT.walk_batches(city, 34, T + 1, z_far, 1600, 900)
+    K = spheres.shape[0]
+    words = predictor.words
+    sizes = [len(P.bits_to_ids(P.cull_bits(spheres, b, words), K)) for b in batches]
+    capacity = 2 * max(sizes) + 8
+    # the predictor judged against exact culling on this walk
+    X, Y = P.log_pairs(spheres, batches, words)
+    mlp = predictor.mlp
+    z = torch.cat([mlp.forward(torch.from_numpy(X[i:i + 256]).cuda()).clone() for i in range(0, X.shape[0], 256)])
+    bits = mlp.predict_bits(z, predictor.thr).cpu().numpy().view(np.uint32) & P.valid_mask(K, words)[None, :]
+    recall, precision = P.recall_precision(bits, Y)
+    del z
+    targets = CT.targets_for(batches, 35, 900, 1600)
+    log(f"walk: {T} iterations, |K_t| {min(sizes)}..{max(sizes)}, capacity {capacity}, host cache "
+        f"{args.city_host_blocks} blocks; predictor recall {recall:.4f} precision {precision:.4f}")
+    exact, dig_e, loss_e = CT.run(args.city_dir, N, B, batches, targets, capacity, 8, args.city_host_blocks,
+                                  None, log=log)
+    log(f"exact-only: {exact}")
+    pred, dig_p, loss_p = CT.run(args.city_dir, N, B, batches, targets, capacity, 8, args.city_host_blocks,
+                                 predictor, log=log)
+    log(f"with predictor: {pred}")
+    shutil.rmtree(args.city_dir, ignore_errors=True)
+    pred["hinted_blocks"] = predictor.hinted
+    pred["wasted_prefetch_GB"] = round((pred["prefetch_issued"] - pred["prefetch_used"]) * rec / 1e9, 3)
+    out = {
+        "metric": METRIC, "value": pred["iters_per_s"], "unit": "iters/s", "n_gpus": 1, "steps": T, "warmup": 0,
+        "ms_per_step": round(1e3 / pred["iters_per_s"], 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"out-of-core street city, {n_blocks} blocks x {B} Gaussians ({N}), "
+                               f"batch 4 x 1600x900, {T}-iteration street walk, predictor-hinted streaming",
+                   "gaussians": N, "blocks": n_blocks, "extent_m": round(extent, 1), "z_far_m": z_far,
+                   "capacity_blocks": capacity, "host_cache_blocks": args.city_host_blocks, "o_direct": True,
+                   "parallelism": "single GPU"},
+        "stall_s_per_iter": pred["stall_s_per_iter"],
+        "exact_only": exact, "with_predictor": pred,
+        "predictor": dict(pinfo, walk_recall=round(recall, 4), walk_precision=round(precision, 4)),
+        "identical_images": dig_e == dig_p, "identical_losses": loss_e == loss_p,
+        "layout_build_s": round(build_s, 1),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; the multi-GPU path is a design "
                           "(block ownership + all-to-all of projected records), not an executable"}))
         sys.exit(2)
+    if args.workload == "city":
+        return city_main(args)
     import numpy as np
     import torch
 

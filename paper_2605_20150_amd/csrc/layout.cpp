@@ -2,7 +2,6 @@
 // contiguous runs of B rows (the blocks) are spatially compact.
 #include <algorithm>
 #include <cmath>
-#include <numeric>
 #include <thread>
 #include <vector>
 
@@ -41,7 +40,9 @@ extern "C" tide_status tide_morton_order(const float* xyz, int64_t n, int64_t st
   const double cells = 2097152.0;   // 2^21 per axis
   double scale[3];
   for (int a = 0; a < 3; ++a) scale[a] = hi[a] > lo[a] ? cells / (hi[a] - lo[a]) : 0.0;
-  std::vector<uint64_t> code((size_t)n);
+  // (code, row) pairs are unique, so an unstable sort of the pairs is the
+  // stable order by code; chunks are sorted on threads and merged pairwise.
+  std::vector<std::pair<uint64_t, int64_t>> kv((size_t)n);
   auto fill = [&](int64_t b, int64_t e) {
     for (int64_t i = b; i < e; ++i) {
       uint64_t c = 0;
@@ -50,14 +51,29 @@ extern "C" tide_status tide_morton_order(const float* xyz, int64_t n, int64_t st
         const uint64_t u = (uint64_t)std::min(cells - 1.0, std::max(0.0, q));
         c |= spread3(u) << a;
       }
-      code[(size_t)i] = c;
+      kv[(size_t)i] = {c, i};
     }
   };
   const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(16, n / 65536));
-  std::vector<std::thread> th;
-  for (int k = 0; k < nt; ++k) th.emplace_back(fill, n * k / nt, n * (k + 1) / nt);
-  for (auto& t : th) t.join();
-  std::iota(perm, perm + n, (int64_t)0);
-  std::stable_sort(perm, perm + n, [&](int64_t a, int64_t b) { return code[(size_t)a] < code[(size_t)b]; });
+  std::vector<int64_t> cut(nt + 1);
+  for (int k = 0; k <= nt; ++k) cut[k] = n * k / nt;
+  {
+    std::vector<std::thread> th;
+    for (int k = 0; k < nt; ++k)
+      th.emplace_back([&, k] {
+        fill(cut[k], cut[k + 1]);
+        std::sort(kv.begin() + cut[k], kv.begin() + cut[k + 1]);
+      });
+    for (auto& t : th) t.join();
+  }
+  for (int width = 1; width < nt; width *= 2) {
+    std::vector<std::thread> th;
+    for (int k = 0; k + width < nt; k += 2 * width) {
+      const int64_t a = cut[k], m = cut[k + width], b = cut[std::min(nt, k + 2 * width)];
+      th.emplace_back([&, a, m, b] { std::inplace_merge(kv.begin() + a, kv.begin() + m, kv.begin() + b); });
+    }
+    for (auto& t : th) t.join();
+  }
+  for (int64_t i = 0; i < n; ++i) perm[i] = kv[(size_t)i].second;
   return TIDE_OK;
 }

@@ -32,7 +32,7 @@ D = 59
 def _attributes(rng: np.random.Generator, n: int, logscale_mu: float,
                 logscale_sigma: float) -> np.ndarray:
     """Everything except the means, drawn as the tiny-scene recipe states."""
-    th = np.empty((n, D), dtype=np.float64)
+    th = np.zeros((n, D), dtype=np.float64)
     th[:, 3:6] = rng.normal(logscale_mu, logscale_sigma, size=(n, 3))
     q = rng.normal(0.0, 1.0, size=(n, 4))
     q /= np.linalg.norm(q, axis=1, keepdims=True)
@@ -181,24 +181,23 @@ class City:
     street_width: float
 
 
-def city_scene(n: int, seed: int, extent: float = 4000.0, pitch: float = 100.0, street_width: float = 20.0,
-               buildings_per_km2: float = 400.0, ground_frac: float = 0.1,
-               logscale_mu: float = -1.0, logscale_sigma: float = 0.7):
-    """A synthetic city of ``n`` Gaussians (rows in generation order, not
-    spatially sorted): streets every ``pitch`` metres, ``street_width`` wide;
-    buildings from a Poisson process over the non-street area with square
-    footprints of side U(10, 40) m and heights U(10, 100) m; each building
-    gets Gaussians in proportion to its footprint area, uniform over its
-    footprint x [0, h]; ``ground_frac`` of the Gaussians lie on the street
-    ground (z ~ N(0, 0.1^2)).  Attributes as the aerial recipe."""
+def city_means(n: int, seed: int, extent: float = 4000.0, pitch: float = 100.0, street_width: float = 20.0,
+               buildings_per_km2: float = 400.0, ground_frac: float = 0.1):
+    """Centres of ``n`` Gaussians of a synthetic city (generation order, not
+    spatially sorted): streets every ``pitch`` metres, ``street_width``
+    wide; buildings from a Poisson process over the non-street area with
+    square footprints of side U(10, 40) m and heights U(10, 100) m; each
+    building gets Gaussians in proportion to its footprint area, uniform
+    over its footprint x [0, h]; ``ground_frac`` of the Gaussians lie on the
+    street ground (z ~ N(0, 0.1^2)).  Returns (f64 [n, 3], City)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     half = extent / 2.0
     inner = pitch - street_width
-    n_lots = int(round(extent / pitch)) ** 2
+    per_row = int(round(extent / pitch))
+    n_lots = per_row ** 2
     expected = buildings_per_km2 * (extent / 1000.0) ** 2 * (inner / pitch) ** 2
     n_b = max(1, int(rng.poisson(expected)))
     lot = rng.integers(0, n_lots, size=n_b)
-    per_row = int(round(extent / pitch))
     side = rng.uniform(10.0, 40.0, size=n_b)
     h = rng.uniform(10.0, 100.0, size=n_b)
     # footprint centre inside its lot, footprint kept off the street
@@ -218,15 +217,41 @@ def city_scene(n: int, seed: int, extent: float = 4000.0, pitch: float = 100.0, 
     mu[:m, 2] = rng.uniform(0.0, 1.0, size=m) * h[idx]
     # street ground: along a random street line, across its width
     along = rng.uniform(-half, half, size=n_ground)
-    line = -half + pitch * (rng.integers(0, per_row, size=n_ground) + 0.5) - pitch / 2.0
+    line = -half + pitch * rng.integers(0, per_row, size=n_ground)
     across = rng.uniform(-street_width / 2.0, street_width / 2.0, size=n_ground)
     horiz = rng.integers(0, 2, size=n_ground).astype(bool)
     mu[m:, 0] = np.where(horiz, along, line + across)
     mu[m:, 1] = np.where(horiz, line + across, along)
     mu[m:, 2] = rng.normal(0.0, 0.1, size=n_ground)
+    return mu, City(extent, pitch, street_width)
+
+
+def city_scene(n: int, seed: int, extent: float = 4000.0, pitch: float = 100.0, street_width: float = 20.0,
+               buildings_per_km2: float = 400.0, ground_frac: float = 0.1,
+               logscale_mu: float = -1.0, logscale_sigma: float = 0.7):
+    """city_means plus the aerial-recipe attributes: (f32 [n, 59], City)."""
+    mu, city = city_means(n, seed, extent, pitch, street_width, buildings_per_km2, ground_frac)
+    rng = np.random.Generator(np.random.PCG64([seed, 1]))
     th = _attributes(rng, n, logscale_mu, logscale_sigma)
     th[:, 0:3] = mu
-    return th.astype(np.float32), City(extent, pitch, street_width)
+    return th.astype(np.float32), city
+
+
+def block_attributes(seed: int, block: int, n: int, logscale_mu: float = -1.0,
+                     logscale_sigma: float = 0.7) -> np.ndarray:
+    """Attributes (every column but the means, which stay zero) of block
+    ``block``'s n Gaussians, drawn in single precision from a stream keyed
+    by (seed, block), so that a large scene is generated one block at a
+    time: f32 [n, 59] with the aerial recipe's distributions."""
+    rng = np.random.Generator(np.random.PCG64([seed, block]))
+    th = np.zeros((n, D), dtype=np.float32)
+    th[:, 3:6] = rng.standard_normal((n, 3), dtype=np.float32) * np.float32(logscale_sigma) + np.float32(logscale_mu)
+    q = rng.standard_normal((n, 4), dtype=np.float32)
+    th[:, 6:10] = q / np.linalg.norm(q, axis=1, keepdims=True)
+    th[:, 10] = rng.standard_normal(n, dtype=np.float32)
+    th[:, 11:14] = rng.standard_normal((n, 3), dtype=np.float32) * np.float32(0.3)
+    th[:, 14:59] = rng.standard_normal((n, 45), dtype=np.float32) * np.float32(0.05)
+    return th
 
 
 def street_walk(city: City, n_poses: int, seed: int, step: float = 1.0, eye_height: float = 1.7,

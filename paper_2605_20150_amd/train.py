@@ -49,18 +49,25 @@ class OutOfCoreTrainer:
     -> compute -> end iteration -> K_{t+1} -> Alg. 1 delta (transfers on a
     side stream, overlapping the compute that is still running)."""
 
-    def __init__(self, theta: np.ndarray, block_rows: int, directory: str, capacity: int, spare_slots: int,
-                 host_cache_blocks: int, device="cuda", kappa=1.32, io_threads=4, predictor=None):
+    def __init__(self, theta, block_rows: int, directory: str, capacity: int, spare_slots: int,
+                 host_cache_blocks: int, device="cuda", kappa=1.32, io_threads=4, predictor=None,
+                 n_rows: int | None = None, odirect: bool = False):
+        """theta: the [N][59] table to lay out in a new store, or None to
+        reopen the store already in ``directory`` (n_rows rows, from its
+        persisted Index)."""
         self.rast = Rasterizer(device)
-        self.N = theta.shape[0]
+        self.N = theta.shape[0] if theta is not None else int(n_rows)
         self.B = block_rows
         self.pool = Pool.empty(capacity + spare_slots, block_rows, device)
         self.tier = Tier(directory, self.N, self.pool, capacity, host_cache_blocks, io_threads=io_threads,
-                         kappa=kappa)
-        for k in range(self.tier.K):
-            rows = theta[k * block_rows:(k + 1) * block_rows]
-            self.tier.put_block(k, np.ascontiguousarray(rows.T))
-        self.tier.finalize()
+                         kappa=kappa, odirect=odirect)
+        if theta is not None:
+            for k in range(self.tier.K):
+                rows = theta[k * block_rows:(k + 1) * block_rows]
+                self.tier.put_block(k, np.ascontiguousarray(rows.T))
+            self.tier.finalize()
+        else:
+            self.tier.open()
         self.cfg = adam_cfg(LR59, kappa=kappa)
         self.grad = torch.empty((59, self.pool.n_slots * block_rows), dtype=torch.float32, device=device)
         self.side = torch.cuda.Stream(device=device)
