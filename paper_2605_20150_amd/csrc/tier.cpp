@@ -13,6 +13,7 @@
 #include <deque>
 #include <functional>
 #include <list>
+#include <memory>
 #include <mutex>
 #include <set>
 #include <string>
@@ -98,7 +99,28 @@ class LogStore {
     return TIDE_OK;
   }
 
+  // With O_DIRECT every transfer goes through an aligned buffer of the
+  // calling thread: pinned memory from the GPU runtime is not guaranteed to
+  // be usable as the target of direct I/O.
+  char* bounce() {
+    thread_local std::unique_ptr<char, void (*)(void*)> buf(nullptr, std::free);
+    thread_local size_t cap = 0;
+    if (cap < rec) {
+      void* p = nullptr;
+      if (posix_memalign(&p, 4096, rec) != 0) return nullptr;
+      buf.reset((char*)p);
+      cap = rec;
+    }
+    return buf.get();
+  }
+
   tide_status write_base(int64_t k, const void* src) {
+    if (odirect) {
+      char* b = bounce();
+      if (!b) return fail("out of host memory for a direct-I/O buffer");
+      std::memcpy(b, src, rec);
+      src = b;
+    }
     if (::pwrite(fds[0], src, rec, (off_t)(k * rec)) != (ssize_t)rec) return fail("base write failed");
     return TIDE_OK;
   }
@@ -111,12 +133,15 @@ class LogStore {
       e = index[k];
       fd = fds[e.file_id];
     }
+    char* to = (char*)dst;
+    if (odirect && !(to = bounce())) return fail("out of host memory for a direct-I/O buffer");
     size_t got = 0;
     while (got < (size_t)e.size) {
-      const ssize_t r = ::pread(fd, (char*)dst + got, e.size - got, (off_t)(e.offset + got));
+      const ssize_t r = ::pread(fd, to + got, e.size - got, (off_t)(e.offset + got));
       if (r <= 0) return fail("segment read failed");
       got += (size_t)r;
     }
+    if (to != (char*)dst) std::memcpy(dst, to, (size_t)e.size);
     return TIDE_OK;
   }
 
@@ -129,6 +154,12 @@ class LogStore {
       patch_off += (int64_t)rec;
       fid = (int)fds.size() - 1;
       fd = fds[fid];
+    }
+    if (odirect) {
+      char* b = bounce();
+      if (!b) return fail("out of host memory for a direct-I/O buffer");
+      std::memcpy(b, src, rec);
+      src = b;
     }
     size_t put = 0;
     while (put < rec) {
@@ -294,6 +325,11 @@ struct tide_residency {
   LogStore store;
   IoPool* io = nullptr;
   tide_status io_error = TIDE_OK;
+  std::string io_msg;   // message of the first failed I/O task (set on an I/O thread)
+  tide_status io_failed() const {
+    set_error("block I/O failed: %s", io_msg.c_str());
+    return io_error;
+  }
   // device sync
   hipStream_t last_side = nullptr;
   hipEvent_t ev_compute = nullptr, ev_side = nullptr, ev_bounds = nullptr;
@@ -416,7 +452,7 @@ struct tide_residency {
     io->submit([this, idx, blk, buf] {
       const tide_status r = store.append(blk, buf);
       std::lock_guard<std::mutex> g(mu);
-      if (r != TIDE_OK) io_error = r;
+      if (r != TIDE_OK && io_error == TIDE_OK) { io_error = r; io_msg = tide_last_error(); }
       st.ssd_write_bytes += (int64_t)rec;
       ent[idx].flushing = false;
       ent[idx].dirty = false;
@@ -436,7 +472,7 @@ struct tide_residency {
       }
       const tide_status r = store.read(blk, buf);
       std::lock_guard<std::mutex> g(mu);
-      if (r != TIDE_OK) io_error = r;
+      if (r != TIDE_OK && io_error == TIDE_OK) { io_error = r; io_msg = tide_last_error(); }
       st.ssd_read_bytes += (int64_t)rec;
       ent[idx].loading = false;
       ent[idx].valid = true;
@@ -727,7 +763,7 @@ tide_status tide_ensure_resident(tide_residency* res, const int32_t* K, int32_t 
   hipStream_t cs = (hipStream_t)compute_stream;
   const double t0 = now_s();
   std::unique_lock<std::mutex> lk(res->mu);
-  if (res->io_error != TIDE_OK) return res->io_error;
+  if (res->io_error != TIDE_OK) return res->io_failed();
   std::vector<int32_t> need(K, K + n);
   std::sort(need.begin(), need.end());
   need.erase(std::unique(need.begin(), need.end()), need.end());
@@ -847,7 +883,7 @@ tide_status tide_stream_delta(tide_residency* res, const int32_t* knext_ids, con
   TIDE_CHECK_ARG(res && knext_counts && n_cams >= 1 && n_cams <= TIDE_MAX_CAMS, "bad arguments");
   hipStream_t ss = (hipStream_t)side_stream;
   std::unique_lock<std::mutex> lk(res->mu);
-  if (res->io_error != TIDE_OK) return res->io_error;
+  if (res->io_error != TIDE_OK) return res->io_failed();
   // 1. next working set, per camera and united
   std::vector<std::vector<int32_t>> Kj(n_cams);
   std::set<int32_t> Kn;
@@ -1020,7 +1056,7 @@ tide_status tide_checkpoint(tide_residency* res) {
       if (e.flushing) return false;
     return true;
   });
-  if (res->io_error != TIDE_OK) return res->io_error;
+  if (res->io_error != TIDE_OK) return res->io_failed();
   lk.unlock();
   r = res->store.persist();
   if (r != TIDE_OK) return r;

@@ -23,12 +23,13 @@ def scene(n=2500, seed=40):
     return th[np.lexsort((cell[:, 2], cell[:, 1], cell[:, 0]))]
 
 
-def build(tmp_path, th, n_slots=6, capacity=6, cache=4, name="store"):
-    pool = Pool.empty(n_slots, B, "cpu")
-    t = Tier(str(tmp_path / name), th.shape[0], pool, capacity, cache, io_threads=2, host_pool=True, kappa=1.32)
+def build(tmp_path, th, n_slots=6, capacity=6, cache=4, name="store", odirect=False, rows=B):
+    pool = Pool.empty(n_slots, rows, "cpu")
+    t = Tier(str(tmp_path / name), th.shape[0], pool, capacity, cache, io_threads=2, host_pool=True, kappa=1.32,
+             odirect=odirect)
     for k in range(t.K):
-        rows = th[k * B:(k + 1) * B]
-        t.put_block(k, rows.T)
+        r = th[k * rows:(k + 1) * rows]
+        t.put_block(k, r.T)
     t.finalize()
     return t, pool
 
@@ -102,12 +103,12 @@ def test_alg1_decisions_match_oracle(tmp_path):
     t.close()
 
 
-def test_residency_moves_data_and_writes_back(tmp_path):
+def test_residency_moves_data_and_writes_back(tmp_path, odirect=False):
     """Blocks updated while resident are written back through the host cache
     (dirty) to patch segments; a tiny host cache forces flushes; a reopened
     store reads the newest versions."""
     th = scene()
-    t, pool = build(tmp_path, th, n_slots=4, capacity=4, cache=4)
+    t, pool = build(tmp_path, th, n_slots=4, capacity=4, cache=4, odirect=odirect)
     rng = np.random.default_rng(43)
     truth = {k: t.read_block(k) for k in range(t.K)}
     for it in range(30):
@@ -140,7 +141,7 @@ def test_residency_moves_data_and_writes_back(tmp_path):
     t.checkpoint()
     t.close()
     pool2 = Pool.empty(4, B, "cpu")
-    t2 = Tier(str(tmp_path / "store"), th.shape[0], pool2, 4, 4, host_pool=True)
+    t2 = Tier(str(tmp_path / "store"), th.shape[0], pool2, 4, 4, host_pool=True, odirect=odirect)
     t2.open()
     for k in range(t2.K):
         r = t2.read_block(k)
@@ -202,3 +203,34 @@ def test_prefetch_feeds_the_host_cache(tmp_path):
     st = t.stats()
     assert st["prefetch_issued"] == 2 and st["prefetch_used"] == 2
     t.close()
+
+
+def test_direct_io_write_back_and_reopen(tmp_path):
+    """The same data path with O_DIRECT segment files (block_rows a multiple
+    of 512): updates written back through the host cache survive a reopen."""
+    th = scene(n=3000)
+    R = 512
+    t, pool = build(tmp_path, th, n_slots=3, capacity=3, cache=4, odirect=True, rows=R)
+    assert t.K == 6
+    truth = {k: t.read_block(k)["params"].copy() for k in range(t.K)}
+    rng = np.random.default_rng(44)
+    for it in range(12):
+        Kt = sorted(rng.choice(t.K, 2, replace=False).tolist())
+        t.ensure_resident(Kt)
+        slots = t.resident_slots()
+        for k in Kt:
+            assert np.array_equal(pool.params[slots[k]].numpy(), truth[k])
+            pool.params[slots[k]] += 0.25
+            t.dirty[k] = 1
+            truth[k] = pool.params[slots[k]].numpy().copy()
+        t.end_iteration()
+        t.stream_delta([sorted(rng.choice(t.K, 2, replace=False).tolist())])
+        t.sync_bounds()
+    t.checkpoint()
+    t.close()
+    pool2 = Pool.empty(3, R, "cpu")
+    t2 = Tier(str(tmp_path / "store"), th.shape[0], pool2, 3, 4, host_pool=True, odirect=True)
+    t2.open()
+    for k in range(t2.K):
+        assert np.array_equal(t2.read_block(k)["params"], truth[k]), k
+    t2.close()
