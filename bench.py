@@ -57,6 +57,7 @@ def parse():
     ap.add_argument("--city-iters", type=int, default=150)
     ap.add_argument("--city-dir", default="/tmp/tide_city_store")
     ap.add_argument("--city-host-blocks", type=int, default=200)
+    ap.add_argument("--city-zfar", type=float, default=150.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, one plain 1 GiB device-to-device copy (a kernel of known "
                          "traffic for scaling hardware byte counters)")
@@ -148,7 +149,7 @@ def city_main(args):
     free = CT.free_bytes(args.city_dir)
     n_blocks = min(args.city_blocks, int(0.6 * free // rec))
     extent = 1000.0 * math.sqrt(n_blocks / 954.0)
-    z_far = 300.0
+    z_far = args.city_zfar
     log(f"city: {n_blocks} blocks of {B} over {extent:.0f} m, store {n_blocks * rec / 1e9:.1f} GB "
         f"({free / 1e9:.0f} GB free)")
     shutil.rmtree(args.city_dir, ignore_errors=True)

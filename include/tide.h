@@ -368,8 +368,14 @@ tide_status tide_residency_end_iteration(tide_residency* res, void* compute_stre
 /* Waits for that read-back; the next culling uses the refreshed bounds. */
 tide_status tide_residency_sync_bounds(tide_residency* res);
 
-/* Prefetch hint: read these blocks from the SSD into the host cache ahead
- * of need (horizon = iterations ahead, for statistics). */
+/* Prefetch hint: read these blocks (most urgent first) from the SSD into the
+ * host cache ahead of need, as speculative reads that the I/O threads serve
+ * only when no demand read or write-back is waiting.  Resident and cached
+ * blocks are skipped.  At most 2 x io_threads speculative reads are
+ * outstanding and a hint only takes a clean, idle host entry that was not
+ * filled by a prefetch in the last 4 iterations; the rest of the list is
+ * dropped (hints are meant to be renewed every iteration).  horizon =
+ * iterations ahead, informational. */
 tide_status tide_prefetch_hint(tide_residency* res, const int32_t* blocks, int32_t n, int32_t horizon);
 
 /* Consistency barrier (Sec. 3.4): device-to-host of every dirty resident

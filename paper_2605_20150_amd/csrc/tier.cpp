@@ -28,6 +28,7 @@ namespace tide {
 namespace {
 
 constexpr int kCols = TIDE_D;
+constexpr int64_t kPrefetchTtl = 4;   // iterations an unused prefetch is kept from other prefetches
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -311,6 +312,7 @@ struct tide_residency {
     bool valid = false, loading = false, dirty = false, flushing = false, prefetched = false;
     bool undecided = false;      // written back before its dirty flag was read; pinned until then
     bool spec_read = false;      // the pending read was queued as a speculative prefetch
+    int64_t prefetch_iter = 0;   // iteration of the prefetch hint that filled the entry
     bool read_claimed = false;   // an I/O thread has started the pending read
     uint64_t read_seq = 0;       // identifies the pending read; stale queued copies skip
     hipEvent_t fence = nullptr;  // last device copy that reads or writes buf
@@ -326,6 +328,7 @@ struct tide_residency {
   IoPool* io = nullptr;
   tide_status io_error = TIDE_OK;
   std::string io_msg;   // message of the first failed I/O task (set on an I/O thread)
+  int n_io = 1;         // I/O threads
   tide_status io_failed() const {
     set_error("block I/O failed: %s", io_msg.c_str());
     return io_error;
@@ -413,7 +416,12 @@ struct tide_residency {
   // Returns the entry holding block k, creating it (not valid) if needed.
   // Dirty victims are handed to the I/O threads and skipped.  Called with
   // mu held.
-  int entry_for(int64_t k, std::unique_lock<std::mutex>& lk) {
+  // A speculative caller (spec) never takes an entry filled by a recent
+  // prefetch that has not been used yet.
+  bool protected_prefetch(const Entry& e) const {
+    return e.prefetched && st.iterations - e.prefetch_iter <= kPrefetchTtl;
+  }
+  int entry_for(int64_t k, std::unique_lock<std::mutex>& lk, bool spec = false) {
     auto f = map.find(k);
     if (f != map.end()) {
       lru.splice(lru.begin(), lru, ent[f->second].it);
@@ -424,6 +432,7 @@ struct tide_residency {
         Entry& e = ent[*it];
         if (e.loading || e.flushing || e.undecided) continue;
         if (e.block >= 0 && slot_of[e.block] >= 0 && pending_contains(e.block)) continue;
+        if (spec && protected_prefetch(e)) continue;
         if (e.dirty) {
           start_flush(*it);
           continue;
@@ -649,6 +658,7 @@ tide_status tide_residency_create(const tide_store_cfg* cfg, tide_pool* pool, fl
     (void)hipEventCreateWithFlags(&r->ev_bounds, hipEventDisableTiming);
   }
   r->io = new IoPool(cfg->io_threads);
+  r->n_io = cfg->io_threads;
   *out = r;
   return TIDE_OK;
 }
@@ -1003,24 +1013,30 @@ tide_status tide_prefetch_hint(tide_residency* res, const int32_t* blocks, int32
   TIDE_CHECK_ARG(res && (blocks || n == 0), "null argument");
   (void)horizon;
   std::unique_lock<std::mutex> lk(res->mu);
-  for (int32_t i = 0; i < n; ++i) {
+  int outstanding = 0;
+  for (const auto& e : res->ent) outstanding += (e.loading && e.spec_read) ? 1 : 0;
+  const int cap = 2 * res->n_io;
+  for (int32_t i = 0; i < n && outstanding < cap; ++i) {
     const int32_t k = blocks[i];
     TIDE_CHECK_ARG(k >= 0 && k < res->K, "block id out of range");
     if (res->slot_of[k] >= 0 || res->map.count(k)) continue;
-    // only a clean, idle entry may be given up for a prefetch
+    // only a clean, idle entry that no recent prefetch filled may be given up
     bool room = false;
     for (auto it = res->lru.rbegin(); it != res->lru.rend(); ++it) {
       auto& e = res->ent[*it];
-      if (!e.loading && !e.flushing && !e.dirty && !(e.block >= 0 && res->pending_contains(e.block))) {
+      if (!e.loading && !e.flushing && !e.dirty && !e.undecided && !res->protected_prefetch(e) &&
+          !(e.block >= 0 && res->pending_contains(e.block))) {
         room = true;
         break;
       }
     }
     if (!room) break;
-    const int idx = res->entry_for(k, lk);
+    const int idx = res->entry_for(k, lk, true);
     res->ent[idx].prefetched = true;
+    res->ent[idx].prefetch_iter = res->st.iterations;
     res->start_read(idx, true);
     res->st.prefetch_issued++;
+    ++outstanding;
   }
   return TIDE_OK;
 }

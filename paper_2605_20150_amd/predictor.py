@@ -278,7 +278,12 @@ def train(mlp: MLP, X: np.ndarray, Y: np.ndarray, valid: np.ndarray, epochs: int
 
 class Predictor:
     """Online use: features of the last 8 poses -> logits -> threshold ->
-    prefetch hints for the blocks predicted for the next HORIZON batches."""
+    prefetch hints for the blocks predicted for the next HORIZON batches.
+
+    The network runs on a stream of its own, so that it overlaps the
+    iteration's rendering instead of waiting behind it: launch() enqueues
+    it, hint() waits for that stream only and passes the predicted blocks
+    to the tier, nearest horizon first."""
 
     def __init__(self, mlp: MLP, threshold_logit: float, n_blocks: int, words_per_h: int):
         self.mlp = mlp
@@ -287,19 +292,41 @@ class Predictor:
         self.words = int(words_per_h)
         self.x = torch.empty((1, HISTORY_POSES * POSE_DIM), dtype=torch.float32, device=mlp.device)
         self.logits = torch.empty((1, mlp.dims[-1]), dtype=torch.float32, device=mlp.device)
+        self.stream = torch.cuda.Stream(device=mlp.device)
+        self.host_x = torch.empty((1, HISTORY_POSES * POSE_DIM), dtype=torch.float32).pin_memory()
+        self.host_bits = torch.empty((1, mlp.dims[-1] // 32), dtype=torch.int32).pin_memory()
+        self.done = torch.cuda.Event()
         self.hinted = 0
 
-    def predict(self, history) -> list[np.ndarray]:
+    def launch(self, history):
+        self.host_x.copy_(torch.from_numpy(pose_features(history)).view(1, -1))
+        with torch.cuda.stream(self.stream):
+            self.x.copy_(self.host_x, non_blocking=True)
+            self.mlp.forward(self.x, self.logits)
+            bits = self.mlp.predict_bits(self.logits, self.thr)
+            self.host_bits.copy_(bits, non_blocking=True)
+            self.done.record(self.stream)
+
+    def collect(self) -> list[np.ndarray]:
         """Block ids predicted for each of the next HORIZON batches."""
-        self.x.copy_(torch.from_numpy(pose_features(history)).view(1, -1))
-        self.mlp.forward(self.x, self.logits)
-        bits = self.mlp.predict_bits(self.logits, self.thr).cpu().numpy().view(np.uint32)[0]
+        self.done.synchronize()
+        bits = self.host_bits.numpy().view(np.uint32)[0]
         return [bits_to_ids(bits[h * self.words:(h + 1) * self.words], self.K) for h in range(HORIZON)]
 
-    def hint(self, tier, cams, next_cams):
-        pred = self.predict(list(cams) + list(next_cams))
-        for h, ids in enumerate(pred):
-            if len(ids):
-                tier.prefetch(ids, horizon=h + 2)
-                self.hinted += len(ids)
+    def predict(self, history) -> list[np.ndarray]:
+        self.launch(history)
+        return self.collect()
+
+    def hint(self, tier):
+        pred = self.collect()
+        seen = set()
+        order = []
+        for ids in pred:                 # nearest horizon first
+            for k in ids.tolist():
+                if k not in seen:
+                    seen.add(k)
+                    order.append(k)
+        if order:
+            tier.prefetch(order, horizon=2)
+            self.hinted += len(order)
         return pred

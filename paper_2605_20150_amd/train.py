@@ -82,12 +82,15 @@ class OutOfCoreTrainer:
         K = sorted(set(int(x) for s in t.cull(cams) for x in s))
         self.k_sets.append(K)
         self.stall += t.ensure_resident(K, cs)
+        hinting = self.predictor is not None and next_cams is not None
+        if hinting:
+            self.predictor.launch(list(cams) + list(next_cams))   # its own stream: overlaps the compute
         fr, loss = step(self.rast, self.pool, cams, target, self.cfg, self.grad, t.spheres, t.dirty)
         t.end_iteration(cs)
         if next_cams is not None:
-            if self.predictor is not None:
-                self.predictor.hint(t, cams, next_cams)
             t.stream_delta(t.cull(next_cams), self.side.cuda_stream)
+            if hinting:
+                self.predictor.hint(t)
         return fr, loss
 
     def params(self) -> np.ndarray:
