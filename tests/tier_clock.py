@@ -17,7 +17,10 @@ library's schedule:
 The SSD serves demand reads before speculative ones (one non-preemptive
 server, each class FIFO), the host-to-device link is one FIFO server.  The
 host cache is an LRU of H blocks; an entry whose read is still in flight is
-never evicted, and a hint that finds no evictable entry is dropped."""
+never evicted.  As in the library, a hint never takes an entry filled by a
+prefetch of the last 4 iterations that is still unused, at most
+``spec_cap`` speculative reads are outstanding, and the rest of a hint list
+is dropped."""
 from __future__ import annotations
 
 from collections import OrderedDict
@@ -38,6 +41,8 @@ class ClockConfig:
     c1_ms: float
     lam: float = 0.75
     gamma: float = 0.9
+    spec_cap: int | None = None   # outstanding speculative reads (None: unbounded)
+    prefetch_ttl: int = 4
 
 
 @dataclass
@@ -82,22 +87,29 @@ def simulate(per_cam_sets, cfg: ClockConfig, hints=None) -> ClockResult:
     res = ClockResult()
     ssd = _Ssd(cfg.ssd_ms)
     host = OrderedDict()        # block -> time its host copy is ready (may be in the future)
-    spec = set()                # host entries filled by a prefetch and not yet used
+    spec = {}                   # host entries filled by a prefetch and not yet used -> iteration
     pcie = 0.0
     gpu_ready = {}
     R = []
     age = np.full(n_blocks, 1e9)
     now = 0.0
 
-    def host_insert(k, ready, t):
+    def host_insert(k, ready, t, it=None):
+        """it: the iteration of a speculative insert (protects recent unused prefetches)."""
+        if it is not None:
+            victim = next((b for b, r in host.items() if r <= t and not
+                           (b in spec and it - spec[b] <= cfg.prefetch_ttl)), None)
+            if len(host) >= cfg.host_blocks and victim is None:
+                return False
         host[k] = ready
         host.move_to_end(k)
         while len(host) > cfg.host_blocks:
-            victim = next((b for b, r in host.items() if r <= t and b != k), None)
+            victim = next((b for b, r in host.items() if r <= t and b != k and not
+                           (it is not None and b in spec and it - spec[b] <= cfg.prefetch_ttl)), None)
             if victim is None:
                 return False
             del host[victim]
-            spec.discard(victim)
+            spec.pop(victim, None)
         return True
 
     def to_gpu(k, t):
@@ -107,7 +119,7 @@ def simulate(per_cam_sets, cfg: ClockConfig, hints=None) -> ClockResult:
             ready = host[k]
             host.move_to_end(k)
             if k in spec:
-                spec.discard(k)
+                del spec[k]
                 res.prefetch_used += 1
             # a queued speculative read of k becomes a demand read
             for i, (_, b) in enumerate(ssd.low):
@@ -142,15 +154,19 @@ def simulate(per_cam_sets, cfg: ClockConfig, hints=None) -> ClockResult:
         if hints is not None and hints[t] is not None:
             ssd.advance(now, host)
             Rset = set(R)
+            outstanding = sum(1 for b in spec if host.get(b, 0.0) > now)
             for k in hints[t]:
                 k = int(k)
+                if cfg.spec_cap is not None and outstanding >= cfg.spec_cap:
+                    break
                 if k in Rset or k in host:
                     continue
-                if not host_insert(k, float("inf"), now):
+                if not host_insert(k, float("inf"), now, it=t):
                     break
                 ssd.low.append((now, k))
-                spec.add(k)
+                spec[k] = t
                 res.prefetch_reads += 1
+                outstanding += 1
         if t + 1 < T:
             Rn, Sp, Sm, age, _ = oracle.alg1(R, Kt, per_cam_sets[t + 1], age, cfg.lam, cfg.gamma, cfg.capacity)
             for k in Sm:
