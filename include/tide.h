@@ -153,6 +153,8 @@ typedef struct {
   const uint32_t* inst_e;      /* [n_inst] emission index of the j-th sorted instance */
   const uint32_t* inst_rec;    /* [n_inst] record index of emission index e */
   const uint32_t* ranges;      /* [n_cams*n_tiles][2] sorted-instance [start, end) */
+  const uint32_t* tile_order;  /* [n_cams*n_tiles] global tile ids by descending list length
+                                  (ties in tile order): the compositing launch order */
   int64_t n_vis;
   int64_t n_inst;
   int32_t n_cams;

@@ -19,7 +19,8 @@ constexpr int kG2 = 9;  // du, dv, dA, dB, dC, dopacity, dr, dg, db
 // 64 entries is done, lane k adds entry k's four row sums (fixed order) and
 // stores its partial.  Entries no pixel reaches get zero partials.
 template <typename T>
-__global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ ranges,
+__global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ order,
+                                                   const uint32_t* __restrict__ ranges,
                                                    const uint32_t* __restrict__ inst_e,
                                                    const uint32_t* __restrict__ inst_rec, const T* __restrict__ rec,
                                                    int32_t Tx, int32_t Ty, int32_t W, int32_t H, T bg0, T bg1,
@@ -27,7 +28,7 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
                                                    const uint32_t* __restrict__ last_in,
                                                    const T* __restrict__ dimg, T* __restrict__ partial) {
   const int nt = Tx * Ty;
-  const int g = blockIdx.x;
+  const int g = (int)order[blockIdx.x];
   const int c = g / nt, t = g - c * nt;
   const int tx = t % Tx, ty = t / Tx;
   const int lane = threadIdx.x;
@@ -471,7 +472,7 @@ extern "C" tide_status tide_render_bwd(const tide_pool* pool, const tide_camera*
     float* partial = cv.take<float>((size_t)(bins->n_inst > 0 ? bins->n_inst : 1) * kG2);
     float* g2d = cv.take<float>((size_t)kG2 * nrec);
 
-    TIDE_TIMED("render_bwd", st, hipLaunchKernelGGL(k_render_bwd<float>, dim3(grid), dim3(64), 0, st, bins->ranges, bins->inst_e, bins->inst_rec,
+    TIDE_TIMED("render_bwd", st, hipLaunchKernelGGL(k_render_bwd<float>, dim3(grid), dim3(64), 0, st, bins->tile_order, bins->ranges, bins->inst_e, bins->inst_rec,
                        (const float*)proj->rec, bins->tiles_x, bins->tiles_y, fr->width, fr->height, bg[0], bg[1],
                        bg[2], (const float*)fr->t_final, fr->last, (const float*)d_dimage, partial));
     TIDE_LAUNCH_CHECK("k_render_bwd");
@@ -490,7 +491,7 @@ extern "C" tide_status tide_render_bwd(const tide_pool* pool, const tide_camera*
     double* partial = cv.take<double>((size_t)(bins->n_inst > 0 ? bins->n_inst : 1) * kG2);
     double* g2d = cv.take<double>((size_t)kG2 * nrec);
 
-    TIDE_TIMED("render_bwd", st, hipLaunchKernelGGL(k_render_bwd<double>, dim3(grid), dim3(64), 0, st, bins->ranges, bins->inst_e,
+    TIDE_TIMED("render_bwd", st, hipLaunchKernelGGL(k_render_bwd<double>, dim3(grid), dim3(64), 0, st, bins->tile_order, bins->ranges, bins->inst_e,
                        bins->inst_rec, (const double*)proj->rec, bins->tiles_x, bins->tiles_y, fr->width,
                        fr->height, (double)bg[0], (double)bg[1], (double)bg[2], (const double*)fr->t_final,
                        fr->last, (const double*)d_dimage, partial));

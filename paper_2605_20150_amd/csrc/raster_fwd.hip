@@ -324,8 +324,19 @@ __global__ void k_ranges(const uint32_t* __restrict__ key, int64_t n, uint32_t* 
   if (j == n - 1 || key[j + 1] != k) ranges[2 * (int64_t)k + 1] = (uint32_t)(j + 1);
 }
 
+// Launch order of the compositing kernels: tiles by descending list length
+// (ties in tile order), so that the longest lists start first and the tail
+// of the launch is made of short ones.  Key = 2^24 - 1 - min(length, 2^24 - 1).
+__global__ void k_tile_keys(const uint32_t* __restrict__ ranges, int64_t n, uint32_t* __restrict__ key) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const uint32_t len = ranges[2 * g + 1] - ranges[2 * g];
+  key[g] = 0xffffffu - (len < 0xffffffu ? len : 0xffffffu);
+}
+
 struct BinLayout {
   uint32_t *vis_off, *ka, *va, *kb, *vb, *inst_off, *tka, *tva, *tkb, *tvb, *inst_rec, *ranges, *hist;
+  uint32_t *oka, *ova, *okb, *ovb;   // tile launch-order sort
   unsigned long long *partial, *totals;
   size_t bytes;
 };
@@ -346,7 +357,13 @@ static BinLayout bin_layout(void* ws, int n_cams, int64_t n_pidx, int64_t n_tile
   L.tvb = cv.take<uint32_t>(cap);
   L.inst_rec = cv.take<uint32_t>(cap);
   L.ranges = cv.take<uint32_t>(2 * (size_t)n_cams * n_tiles);
-  const int64_t big = nv > cap ? nv : cap;
+  const int64_t ntt = (int64_t)n_cams * n_tiles;
+  L.oka = cv.take<uint32_t>(ntt);
+  L.ova = cv.take<uint32_t>(ntt);
+  L.okb = cv.take<uint32_t>(ntt);
+  L.ovb = cv.take<uint32_t>(ntt);
+  int64_t big = nv > cap ? nv : cap;
+  big = big > ntt ? big : ntt;
   const size_t nh = radix_hist_count(big);
   L.hist = cv.take<uint32_t>(nh);
   const size_t np = scan_partial_count((int64_t)(nh > (size_t)big ? nh : (size_t)big));
@@ -364,7 +381,8 @@ static BinLayout bin_layout(void* ws, int n_cams, int64_t n_pidx, int64_t n_tile
 // terms that depend only on the lane's column are formed once per entry and
 // shared by its four pixels.
 template <typename T>
-__global__ void __launch_bounds__(64) k_render_fwd(const uint32_t* __restrict__ ranges,
+__global__ void __launch_bounds__(64) k_render_fwd(const uint32_t* __restrict__ order,
+                                                   const uint32_t* __restrict__ ranges,
                                                    const uint32_t* __restrict__ inst_e,
                                                    const uint32_t* __restrict__ inst_rec, const T* __restrict__ rec,
                                                    int32_t Tx, int32_t Ty, int32_t W, int32_t H, T bg0, T bg1,
@@ -372,7 +390,7 @@ __global__ void __launch_bounds__(64) k_render_fwd(const uint32_t* __restrict__ 
                                                    uint32_t* __restrict__ last_out,
                                                    unsigned long long* __restrict__ visits) {
   const int nt = Tx * Ty;
-  const int g = blockIdx.x;
+  const int g = (int)order[blockIdx.x];
   const int c = g / nt, t = g - c * nt;
   const int tx = t % Tx, ty = t / Tx;
   const int lane = threadIdx.x;
@@ -418,11 +436,12 @@ __global__ void __launch_bounds__(64) k_render_fwd(const uint32_t* __restrict__ 
         const bool pass = entry_alpha<T>(adx2, bdx, Ch, op, fyp[q] - v, G, araw, alpha);
         const bool live = Tr[q] > 0;
         nvis += (unsigned long long)__popcll(__ballot(live));
-        const T tn = Tr[q] * ((T)1 - alpha);
+        const T wr = alpha * Tr[q];
+        const T tn = Tr[q] - wr;   // T (1 - alpha)
         const bool ok = pass && live;
         const bool stop = ok && tn < (T)1e-4;
         const bool take = ok && !stop;
-        const T w = take ? alpha * Tr[q] : (T)0;
+        const T w = take ? wr : (T)0;
         C0[q] += cr * w; C1[q] += cg * w; C2[q] += cb * w;
         Tr[q] = take ? tn : (stop ? -Tr[q] : Tr[q]);
         lst[q] = take ? idx : lst[q];
@@ -548,6 +567,13 @@ extern "C" tide_status tide_bin_sort(const tide_proj* proj, int32_t tiles_x, int
   if (n_inst > 0)
     hipLaunchKernelGGL(k_ranges, dim3((uint32_t)ceil_div(n_inst, 256)), dim3(256), 0, st, tk, n_inst, L.ranges);
   TIDE_LAUNCH_CHECK("k_ranges");
+  // 7. launch order of the tiles: longest lists first
+  const int64_t ntt = (int64_t)V * nt;
+  hipLaunchKernelGGL(k_tile_keys, dim3((uint32_t)ceil_div(ntt, 256)), dim3(256), 0, st, L.ranges, ntt, L.oka);
+  TIDE_LAUNCH_CHECK("k_tile_keys");
+  uint32_t *ok, *order;
+  radix_sort_pairs(L.oka, L.ova, L.okb, L.ovb, ntt, 24, true, L.hist, L.partial, &L.totals[3], st, &ok, &order);
+  out->tile_order = order;
   out->vis_rec = vrec;
   out->inst_off = L.inst_off;
   out->inst_e = te;
@@ -575,11 +601,11 @@ extern "C" tide_status tide_render_fwd(const tide_proj* proj, const tide_bins* b
   hipStream_t st = (hipStream_t)stream;
   const uint32_t grid = (uint32_t)(bins->n_cams * bins->tiles_x * bins->tiles_y);
   if (proj->dtype == TIDE_F32)
-    TIDE_TIMED("render_fwd", st, hipLaunchKernelGGL(k_render_fwd<float>, dim3(grid), dim3(64), 0, st, bins->ranges, bins->inst_e, bins->inst_rec,
+    TIDE_TIMED("render_fwd", st, hipLaunchKernelGGL(k_render_fwd<float>, dim3(grid), dim3(64), 0, st, bins->tile_order, bins->ranges, bins->inst_e, bins->inst_rec,
                        (const float*)proj->rec, bins->tiles_x, bins->tiles_y, fr->width, fr->height, bg[0], bg[1],
                        bg[2], (float*)fr->image, (float*)fr->t_final, fr->last, fr->visits));
   else
-    TIDE_TIMED("render_fwd", st, hipLaunchKernelGGL(k_render_fwd<double>, dim3(grid), dim3(64), 0, st, bins->ranges, bins->inst_e,
+    TIDE_TIMED("render_fwd", st, hipLaunchKernelGGL(k_render_fwd<double>, dim3(grid), dim3(64), 0, st, bins->tile_order, bins->ranges, bins->inst_e,
                        bins->inst_rec, (const double*)proj->rec, bins->tiles_x, bins->tiles_y, fr->width,
                        fr->height, (double)bg[0], (double)bg[1], (double)bg[2], (double*)fr->image,
                        (double*)fr->t_final, fr->last, fr->visits));

@@ -337,4 +337,4 @@ def bins_views(rast: Rasterizer, bins: L.tide_bins) -> dict:
     V, T = bins.n_cams, bins.tiles_x * bins.tiles_y
     return dict(vis_rec=view(bins.vis_rec, bins.n_vis), inst_off=view(bins.inst_off, bins.n_vis + 1),
                 inst_e=view(bins.inst_e, bins.n_inst), inst_rec=view(bins.inst_rec, bins.n_inst),
-                ranges=view(bins.ranges, 2 * V * T).view(V * T, 2))
+                ranges=view(bins.ranges, 2 * V * T).view(V * T, 2), tile_order=view(bins.tile_order, V * T))

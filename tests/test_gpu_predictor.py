@@ -232,7 +232,6 @@ def test_city_walk_predictor_against_exact_streaming_simulated():
     held-out walk (seed 34).  Timing from this machine's measured rates:
     46.7 MB blocks at 2.2 GB/s from the SSD (21 ms) and ~40 GB/s to the GPU
     (1.2 ms), compute 5 ms + 0.24 ms per resident block."""
-    import concurrent.futures as cf
     sys.path.insert(0, __import__("os").path.dirname(__file__))
     from tier_clock import ClockConfig, dry_city, simulate, walk_sets
     sp, city = dry_city(30, 4000.0)
@@ -242,12 +241,12 @@ def test_city_walk_predictor_against_exact_streaming_simulated():
     say(f"case: city {K} blocks, z_far {z_far}")
 
     def pairs(seed):
-        batches = [synth.street_walk(city, 4000, seed, z_far=z_far)[4 * t:4 * t + 4] for t in range(1000)]
-        return P.log_pairs(sp, batches, words)
-    with cf.ThreadPoolExecutor(8) as ex:
-        res = list(ex.map(pairs, range(100, 120)))
+        cams = synth.street_walk(city, 4000, seed, z_far=z_far)
+        return P.log_pairs(sp, [cams[4 * t:4 * t + 4] for t in range(1000)], words)
+    res = [pairs(seed) for seed in range(100, 120)]
     X = np.concatenate([r[0] for r in res])
     Y = np.concatenate([r[1] for r in res])
+    say(f"logged {X.shape[0]} pairs")
     valid = P.valid_mask(K, words)
     base = float(np.unpackbits(Y.view(np.uint8)).sum()) / (Y.shape[0] * P.HORIZON * K)
     mlp = P.MLP(P.DEFAULT_DIMS, seed=3, out_bias=math.log(base / (1 - base)))
@@ -273,7 +272,9 @@ def test_city_walk_predictor_against_exact_streaming_simulated():
     sizes = [len(set(k for s in b for k in s)) for b in sets]
     cfg = ClockConfig(capacity=4000, host_blocks=1379, ssd_ms=21.0, h2d_ms=1.2, c0_ms=5.0, c1_ms=0.24, spec_cap=16)
     exact = simulate(sets, cfg)
+    say(f"simulated exact-only: {exact.total_stall_ms:.0f} ms")
     pred = simulate(sets, cfg, hints=hints)
+    say(f"simulated with the predictor: {pred.total_stall_ms:.0f} ms")
     best = simulate(sets, cfg, hints=future)
     T = len(sets)
     say(f"walk: {T} iterations, |K_t| {min(sizes)}..{max(sizes)} (mean {np.mean(sizes):.0f}); held-out recall "

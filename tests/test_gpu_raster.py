@@ -95,50 +95,77 @@ def test_tiny_scene_image_matches_oracle():
     assert np.abs(fr.t_final.double().cpu().numpy() - ref["t_final"])[~tie].max() <= 1e-5
 
 
-def test_binning_is_bit_exact_on_gpu_inputs():
-    say("case: dense scene, 3000 Gaussians, 3 cameras 150x110 (ragged tiles), block 1024")
-    th, cams = dense_case()
+def oracle_inputs_into(rast, proj, th, cams):
+    """Stage inputs from the oracle: its FP64 projection of every (camera,
+    Gaussian), rounded to FP32 as the GPU stores it, with tile rectangles
+    recomputed by the oracle from the rounded centres; written over the GPU
+    projection buffers.  Returns the FP32 values (as float64) for the oracle."""
     V, N = len(cams), th.shape[0]
-    rast, pool, proj, bins, fr = gpu_forward(th, cams, block_rows=1024)
-    rec, tt = gpu_records(proj, V, N)
-    keep = tt > 0
     cm = synth.cams_array(cams)
-    u, v = rec[..., 0], rec[..., 1]
-    depth = proj.depth.view(V, -1)[:, :N].double().cpu().numpy()
-    radius = np.rint(rec[..., 10]).astype(np.int32)
-    radius[~keep] = 0
-    gid, ranges = oracle.bin_sort(u, v, depth, radius, keep, cm)
+    p = oracle.project(th.astype(np.float64), cm)
+    Tx, Ty = (cams[0].width + 15) // 16, (cams[0].height + 15) // 16
+    rec = np.zeros((V, proj.n_pidx, 12), np.float32)
+    rec[:, :N, 0], rec[:, :N, 1] = p["u"], p["v"]
+    rec[:, :N, 2:5] = p["conic"]
+    rec[:, :N, 5] = p["opacity"]
+    rec[:, :N, 6:9] = p["rgb"]
+    rec[:, :N, 9] = p["depth"]
+    rec[:, :N, 10] = p["radius"]
+    radius = np.where(p["keep"], p["radius"], 0).astype(np.int32)
+    keep = np.zeros((V, N), bool)
+    rect = np.zeros((V, proj.n_pidx, 2), np.uint32)
+    tt = np.zeros((V, proj.n_pidx), np.uint32)
+    for c in range(V):
+        for i in np.where(p["keep"][c])[0]:
+            x0, y0, x1, y1 = oracle.tile_rect(float(rec[c, i, 0]), float(rec[c, i, 1]), int(radius[c, i]), Tx, Ty)
+            if x1 > x0 and y1 > y0:
+                keep[c, i] = True
+                rect[c, i] = (x0 | (y0 << 16), x1 | (y1 << 16))
+                tt[c, i] = (x1 - x0) * (y1 - y0)
+    depth = np.zeros((V, proj.n_pidx), np.float32)
+    depth[:, :N] = rec[:, :N, 9]
+    proj.rec.copy_(torch.from_numpy(rec.reshape(-1)).to(proj.rec.device).view_as(proj.rec))
+    proj.depth.copy_(torch.from_numpy(depth.reshape(-1)).to(proj.depth.device).view_as(proj.depth))
+    proj.rect.copy_(torch.from_numpy(rect.reshape(-1).view(np.int32)).to(proj.rect.device).view_as(proj.rect))
+    proj.tiles_touched.copy_(torch.from_numpy(tt.reshape(-1).view(np.int32)).to(proj.tiles_touched.device)
+                             .view_as(proj.tiles_touched))
+    bins = rast.bin_sort(proj, Tx, Ty)
+    fr = rast.render(proj, bins, cams[0].width, cams[0].height)
+    torch.cuda.synchronize()
+    r64 = rec[:, :N].astype(np.float64)
+    return r64, radius, keep, bins, fr
+
+
+def test_binning_is_bit_exact_on_oracle_inputs():
+    say("case: dense scene, 3000 Gaussians, 3 cameras 150x110 (ragged tiles), block 1024; oracle inputs")
+    th, cams = dense_case()
+    rast, pool, proj, _, _ = gpu_forward(th, cams, block_rows=1024)
+    rec, radius, keep, bins, _ = oracle_inputs_into(rast, proj, th, cams)
+    cm = synth.cams_array(cams)
+    gid, ranges = oracle.bin_sort(rec[..., 0], rec[..., 1], rec[..., 9], radius, keep, cm)
     b = bins_views(rast, bins)
     inst_rec = b["inst_rec"].cpu().numpy().astype(np.int64)
     inst_e = b["inst_e"].cpu().numpy().astype(np.int64)
     g_ranges = b["ranges"].cpu().numpy().astype(np.int64)
     assert bins.n_inst == len(gid)
     assert np.array_equal(g_ranges, ranges)
-    npx = proj.n_pidx
-    g_list = inst_rec[inst_e] % npx
+    g_list = inst_rec[inst_e] % proj.n_pidx
     assert np.array_equal(g_list, gid)
-    # tile rectangles and counts against the oracle's coverage rule
-    rect = proj.rect.view(V, -1, 2)[:, :N].cpu().numpy().astype(np.int64)
-    Tx, Ty = bins.tiles_x, bins.tiles_y
-    for c in range(V):
-        for i in np.where(keep[c])[0][:400]:
-            r = oracle.tile_rect(u[c, i], v[c, i], radius[c, i], Tx, Ty)
-            a, bb = rect[c, i]
-            assert [a & 0xFFFF, a >> 16, bb & 0xFFFF, bb >> 16] == list(r)
+    # the launch order is a permutation of the tiles, longest lists first
+    order = b["tile_order"].cpu().numpy().astype(np.int64)
+    lens = ranges[:, 1] - ranges[:, 0]
+    assert sorted(order.tolist()) == list(range(len(lens)))
+    assert np.array_equal(order, np.argsort(-lens, kind="stable"))
     say(f"instances {bins.n_inst}, visible pairs {bins.n_vis}: lists identical")
 
 
-def test_compositing_matches_oracle_on_gpu_records():
-    say("case: dense scene, stage-isolated compositing")
+def test_compositing_matches_oracle_on_oracle_records():
+    say("case: dense scene, stage-isolated compositing on oracle records")
     th, cams = dense_case()
-    V, N = len(cams), th.shape[0]
-    rast, pool, proj, bins, fr = gpu_forward(th, cams, block_rows=1024)
-    rec, tt = gpu_records(proj, V, N)
+    rast, pool, proj, _, _ = gpu_forward(th, cams, block_rows=1024)
+    rec, radius, keep, bins, fr = oracle_inputs_into(rast, proj, th, cams)
     cm = synth.cams_array(cams)
-    keep = tt > 0
-    depth = proj.depth.view(V, -1)[:, :N].double().cpu().numpy()
-    radius = np.rint(rec[..., 10]).astype(np.int32)
-    gid, ranges = oracle.bin_sort(rec[..., 0], rec[..., 1], depth, radius, keep, cm)
+    gid, ranges = oracle.bin_sort(rec[..., 0], rec[..., 1], rec[..., 9], radius, keep, cm)
     ref = oracle.composite(gid, ranges, rec[..., :9], cm)
     tie = near_tie_pixels(ref)
     img = fr.image.double().cpu().numpy()
