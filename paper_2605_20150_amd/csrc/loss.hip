@@ -1,13 +1,21 @@
 // Photometric loss 0.8 L1 + 0.2 (1 - SSIM) and its gradient.  SSIM windows
 // are separable 11-tap Gaussians (sigma 1.5, zero padding); both passes run
-// out of LDS on 32 x 16 output tiles with a 5-pixel halo.
+// out of LDS on output tiles with a 5-pixel halo: 64 x 32 in single
+// precision (halo re-reads 1.5x the tile, 79 KB of LDS, two workgroups per
+// CU), 32 x 16 in double precision.
 #include <cmath>
 
 #include "common.h"
 
 namespace tide {
 
-constexpr int kOW = 32, kOH = 16, kHalo = 5, kIW = kOW + 2 * kHalo, kIH = kOH + 2 * kHalo;
+constexpr int kHalo = 5;
+template <typename T>
+struct Tile {
+  static constexpr int OW = sizeof(T) == 4 ? 64 : 32, OH = sizeof(T) == 4 ? 32 : 16;
+  static constexpr int IW = OW + 2 * kHalo, IH = OH + 2 * kHalo;
+  static constexpr int NT = sizeof(T) == 4 ? 512 : 256;   // threads per workgroup
+};
 
 template <typename T>
 struct Win {
@@ -19,18 +27,19 @@ struct Win {
 // m2 = w*x^2, m12 = w*xy).  Block partial sums of |x - y| and SSIM go to
 // part[block][2] for a fixed-order final sum.
 template <typename T>
-__global__ void __launch_bounds__(256) k_ssim_fwd(const T* __restrict__ X, const T* __restrict__ Y, int32_t H,
+__global__ void __launch_bounds__(Tile<T>::NT) k_ssim_fwd(const T* __restrict__ X, const T* __restrict__ Y, int32_t H,
                                                   int32_t W, Win<T> win, T* __restrict__ dmaps,
                                                   double* __restrict__ part) {
+  constexpr int kOW = Tile<T>::OW, kOH = Tile<T>::OH, kIW = Tile<T>::IW, kIH = Tile<T>::IH, kNT = Tile<T>::NT;
   __shared__ T sx[kIH][kIW], sy[kIH][kIW];
   __shared__ T hc[5][kIH][kOW];
-  __shared__ double red[2][256 / kWave];
+  __shared__ double red[2][kNT / kWave];
   const int64_t plane = blockIdx.z;
   const int64_t HW = (int64_t)H * W;
   const T* x = X + plane * HW;
   const T* y = Y + plane * HW;
   const int ox = blockIdx.x * kOW, oy = blockIdx.y * kOH;
-  for (int k = threadIdx.x; k < kIH * kIW; k += 256) {
+  for (int k = threadIdx.x; k < kIH * kIW; k += kNT) {
     const int r = k / kIW, c = k % kIW;
     const int gy = oy - kHalo + r, gx = ox - kHalo + c;
     const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
@@ -38,7 +47,7 @@ __global__ void __launch_bounds__(256) k_ssim_fwd(const T* __restrict__ X, const
     sy[r][c] = in ? y[(int64_t)gy * W + gx] : (T)0;
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < kIH * kOW; k += 256) {
+  for (int k = threadIdx.x; k < kIH * kOW; k += kNT) {
     const int r = k / kOW, c = k % kOW;
     T a = 0, b = 0, aa = 0, bb = 0, ab = 0;
 #pragma unroll
@@ -51,7 +60,7 @@ __global__ void __launch_bounds__(256) k_ssim_fwd(const T* __restrict__ X, const
   __syncthreads();
   const T C1 = (T)1e-4, C2 = (T)9e-4;
   double l1 = 0, ss = 0;
-  for (int k = threadIdx.x; k < kOH * kOW; k += 256) {
+  for (int k = threadIdx.x; k < kOH * kOW; k += kNT) {
     const int r = k / kOW, c = k % kOW;
     const int gy = oy + r, gx = ox + c;
     if (gy >= H || gx >= W) continue;
@@ -84,7 +93,7 @@ __global__ void __launch_bounds__(256) k_ssim_fwd(const T* __restrict__ X, const
   __syncthreads();
   if (threadIdx.x == 0) {
     double a = 0, b = 0;
-    for (int q = 0; q < 256 / kWave; ++q) { a += red[0][q]; b += red[1][q]; }
+    for (int q = 0; q < kNT / kWave; ++q) { a += red[0][q]; b += red[1][q]; }
     const int64_t blk = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
     part[2 * blk] = a;
     part[2 * blk + 1] = b;
@@ -93,15 +102,16 @@ __global__ void __launch_bounds__(256) k_ssim_fwd(const T* __restrict__ X, const
 
 // Pass 2: dL/dx = (0.8 sign(x - y) - 0.2 (w*d1 + 2 x w*d2 + y w*d12)) / (3 H W V).
 template <typename T>
-__global__ void __launch_bounds__(256) k_ssim_bwd(const T* __restrict__ X, const T* __restrict__ Y,
+__global__ void __launch_bounds__(Tile<T>::NT) k_ssim_bwd(const T* __restrict__ X, const T* __restrict__ Y,
                                                   const T* __restrict__ dmaps, int32_t H, int32_t W, Win<T> win,
                                                   T scale, T* __restrict__ dx_out) {
+  constexpr int kOW = Tile<T>::OW, kOH = Tile<T>::OH, kIW = Tile<T>::IW, kIH = Tile<T>::IH, kNT = Tile<T>::NT;
   __shared__ T sd[3][kIH][kIW];
   __shared__ T hc[3][kIH][kOW];
   const int64_t plane = blockIdx.z;
   const int64_t HW = (int64_t)H * W, PS = (int64_t)gridDim.z * HW;
   const int ox = blockIdx.x * kOW, oy = blockIdx.y * kOH;
-  for (int k = threadIdx.x; k < kIH * kIW; k += 256) {
+  for (int k = threadIdx.x; k < kIH * kIW; k += kNT) {
     const int r = k / kIW, c = k % kIW;
     const int gy = oy - kHalo + r, gx = ox - kHalo + c;
     const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
@@ -111,7 +121,7 @@ __global__ void __launch_bounds__(256) k_ssim_bwd(const T* __restrict__ X, const
     sd[2][r][c] = in ? dmaps[p + 2 * PS] : (T)0;
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < kIH * kOW; k += 256) {
+  for (int k = threadIdx.x; k < kIH * kOW; k += kNT) {
     const int r = k / kOW, c = k % kOW;
     T a = 0, b = 0, e = 0;
 #pragma unroll
@@ -122,7 +132,7 @@ __global__ void __launch_bounds__(256) k_ssim_bwd(const T* __restrict__ X, const
     hc[0][r][c] = a; hc[1][r][c] = b; hc[2][r][c] = e;
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < kOH * kOW; k += 256) {
+  for (int k = threadIdx.x; k < kOH * kOW; k += kNT) {
     const int r = k / kOW, c = k % kOW;
     const int gy = oy + r, gx = ox + c;
     if (gy >= H || gx >= W) continue;
@@ -171,7 +181,9 @@ using namespace tide;
 extern "C" size_t tide_loss_ws_bytes(int32_t n_views, int32_t height, int32_t width, int32_t dtype) {
   const size_t es = dtype == TIDE_F64 ? 8 : 4;
   const size_t planes = (size_t)n_views * 3;
-  const size_t nblk = planes * ceil_div(width, kOW) * ceil_div(height, kOH);
+  const int ow = dtype == TIDE_F64 ? Tile<double>::OW : Tile<float>::OW;
+  const int oh = dtype == TIDE_F64 ? Tile<double>::OH : Tile<float>::OH;
+  const size_t nblk = planes * ceil_div(width, ow) * ceil_div(height, oh);
   return align_up(3 * planes * (size_t)height * width * es) + align_up(2 * nblk * sizeof(double)) + 256;
 }
 
@@ -188,7 +200,9 @@ extern "C" tide_status tide_loss(const void* image, const void* target, int32_t 
     return TIDE_ECAPACITY;
   }
   hipStream_t st = (hipStream_t)stream;
-  const dim3 grid((uint32_t)ceil_div(width, kOW), (uint32_t)ceil_div(height, kOH), (uint32_t)(n_views * 3));
+  const int ow = dtype == TIDE_F64 ? Tile<double>::OW : Tile<float>::OW;
+  const int oh = dtype == TIDE_F64 ? Tile<double>::OH : Tile<float>::OH;
+  const dim3 grid((uint32_t)ceil_div(width, ow), (uint32_t)ceil_div(height, oh), (uint32_t)(n_views * 3));
   const int64_t nblk = (int64_t)grid.x * grid.y * grid.z;
   const double n_all = 3.0 * height * width * n_views;
   Carver cv(ws);
@@ -196,18 +210,18 @@ extern "C" tide_status tide_loss(const void* image, const void* target, int32_t 
     float* dm = cv.take<float>(3 * (size_t)n_views * 3 * height * width);
     double* part = cv.take<double>(2 * nblk);
     const Win<float> w = make_window<float>();
-    TIDE_TIMED("loss_fwd", st, hipLaunchKernelGGL(k_ssim_fwd<float>, grid, dim3(256), 0, st, (const float*)image, (const float*)target, height,
+    TIDE_TIMED("loss_fwd", st, hipLaunchKernelGGL(k_ssim_fwd<float>, grid, dim3(Tile<float>::NT), 0, st, (const float*)image, (const float*)target, height,
                        width, w, dm, part));
-    TIDE_TIMED("loss_bwd", st, hipLaunchKernelGGL(k_ssim_bwd<float>, grid, dim3(256), 0, st, (const float*)image, (const float*)target, dm,
+    TIDE_TIMED("loss_bwd", st, hipLaunchKernelGGL(k_ssim_bwd<float>, grid, dim3(Tile<float>::NT), 0, st, (const float*)image, (const float*)target, dm,
                        height, width, w, (float)(1.0 / n_all), (float*)d_dimage));
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(1024), 0, st, part, nblk, 1.0 / n_all, d_loss);
   } else {
     double* dm = cv.take<double>(3 * (size_t)n_views * 3 * height * width);
     double* part = cv.take<double>(2 * nblk);
     const Win<double> w = make_window<double>();
-    TIDE_TIMED("loss_fwd", st, hipLaunchKernelGGL(k_ssim_fwd<double>, grid, dim3(256), 0, st, (const double*)image, (const double*)target,
+    TIDE_TIMED("loss_fwd", st, hipLaunchKernelGGL(k_ssim_fwd<double>, grid, dim3(Tile<double>::NT), 0, st, (const double*)image, (const double*)target,
                        height, width, w, dm, part));
-    TIDE_TIMED("loss_bwd", st, hipLaunchKernelGGL(k_ssim_bwd<double>, grid, dim3(256), 0, st, (const double*)image, (const double*)target, dm,
+    TIDE_TIMED("loss_bwd", st, hipLaunchKernelGGL(k_ssim_bwd<double>, grid, dim3(Tile<double>::NT), 0, st, (const double*)image, (const double*)target, dm,
                        height, width, w, 1.0 / n_all, (double*)d_dimage));
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(1024), 0, st, part, nblk, 1.0 / n_all, d_loss);
   }
