@@ -280,8 +280,8 @@ def test_city_walk_predictor_against_exact_streaming_simulated():
     say(f"walk: {T} iterations, |K_t| {min(sizes)}..{max(sizes)} (mean {np.mean(sizes):.0f}); held-out recall "
         f"{rec:.4f} precision {prec:.4f}")
     say(f"stall s/iter: exact-only {exact.total_stall_ms / T / 1e3:.4f}, predictor {pred.total_stall_ms / T / 1e3:.4f} "
-        f"(prefetch reads {pred.prefetch_reads}, used {pred.prefetch_used}), true-future bound "
-        f"{best.total_stall_ms / T / 1e3:.4f}")
+        f"(prefetch reads {pred.prefetch_reads}, used {pred.prefetch_used}); hints = the exact sets of "
+        f"t+2..t+5: {best.total_stall_ms / T / 1e3:.4f}")
     assert rec >= 0.95
     assert pred.render_sets == exact.render_sets
     assert pred.total_stall_ms <= exact.total_stall_ms

@@ -378,7 +378,11 @@ def test_aerial_full_size_view_matches_oracle():
     tie = near_tie_pixels(ref)
     err = np.abs(img - ref["image"]).max(axis=1)
     say(f"near-tie pixels {int(tie.sum())} of {tie.size}; max-abs error {err[~tie].max():.3e}; "
-        f"pixels over 1e-4: {int((err[~tie] > 1e-4).sum())}")
+        f"pixels over 1e-4: {int((err[~tie] > 1e-4).sum())}; near-tie pixels over 1e-4: "
+        f"{int((err[tie] > 1e-4).sum())} (max {err[tie].max() if tie.any() else 0.0:.3e})")
     assert err[~tie].max() <= 1e-4
+    # a near-tie decision that flips moves a pixel by at most one entry's
+    # contribution at the 1/255 alpha floor (or by T below 1e-4): <= 1e-2
+    assert err.max() <= 1e-2
     vis_ref = int(ref["visits"].sum())
     say(f"visits gpu {int(fr.visits[0])} oracle {vis_ref}")
