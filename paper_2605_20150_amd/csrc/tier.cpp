@@ -485,8 +485,27 @@ struct tide_residency {
       st.ssd_read_bytes += (int64_t)rec;
       ent[idx].loading = false;
       ent[idx].valid = true;
+      if (r == TIDE_OK) issue_pending(idx);
       cv.notify_all();
     };
+  }
+  // A block that the last delta admitted while its SSD read was still running
+  // goes host -> GPU on that delta's side stream as soon as the read is done
+  // (called with mu held).  The side stream orders it after the delta's
+  // write-back copies, which may have used the same slot.
+  void issue_pending(int idx) {
+    Entry& e = ent[idx];
+    const int32_t k = (int32_t)e.block;
+    auto it = std::find(pending_h2d.begin(), pending_h2d.end(), k);
+    if (it == pending_h2d.end()) return;
+    pending_h2d.erase(it);
+    if (k < 0 || slot_of[k] < 0) return;
+    const tide_status r = h2d_block(slot_of[k], e.buf, last_side);
+    if (r != TIDE_OK) {
+      if (io_error == TIDE_OK) { io_error = r; io_msg = tide_last_error(); }
+      return;
+    }
+    e.fence = next_fence(last_side);
   }
   void start_read(int idx, bool speculative = false) {
     Entry& e = ent[idx];
@@ -780,18 +799,15 @@ tide_status tide_ensure_resident(tide_residency* res, const int32_t* K, int32_t 
   for (int32_t k : need) TIDE_CHECK_ARG(k >= 0 && k < res->K, "block id %d out of range", k);
   const std::set<int32_t> want(need.begin(), need.end());
   bool copied = false;
-  // S+ blocks of the last delta still waiting for their SSD read
-  std::vector<int32_t> still;
-  for (int32_t k : res->pending_h2d) {
-    if (res->slot_of[k] < 0) continue;
-    if (!want.count(k)) { still.push_back(k); continue; }
-    const int idx = res->fetch_blocking(k, lk);
-    tide_status r = res->h2d_block(res->slot_of[k], res->ent[idx].buf, cs);
-    if (r != TIDE_OK) return r;
-    res->ent[idx].fence = res->next_fence(cs);
-    copied = true;
+  // S+ blocks of K_t whose SSD read is still running: the read completes and
+  // issues their copy on the side stream; wait (host) for that
+  for (int32_t k : need) {
+    if (res->slot_of[k] < 0 || !res->pending_contains(k)) continue;
+    const auto f = res->map.find(k);
+    if (f != res->map.end()) res->promote(f->second);
+    res->cv.wait(lk, [&] { return !res->pending_contains(k) || res->io_error != TIDE_OK; });
+    if (res->io_error != TIDE_OK) return res->io_failed();
   }
-  res->pending_h2d = still;
   // blocks of K_t that are not resident at all: synchronous fetch
   for (int32_t k : need) {
     if (res->slot_of[k] >= 0) continue;
@@ -823,10 +839,14 @@ tide_status tide_ensure_resident(tide_residency* res, const int32_t* K, int32_t 
     res->st.sync_fetches++;
     copied = true;
   }
+  // the compute waits for every side-stream transfer issued so far (the
+  // last delta's copies and the completed reads' copies)
+  if (!res->host_pool && res->last_side) {
+    TIDE_HIP(hipEventRecord(res->ev_side, res->last_side));
+    TIDE_HIP(hipStreamWaitEvent(cs, res->ev_side, 0));
+  }
   lk.unlock();
   if (copied && !res->host_pool) TIDE_HIP(hipStreamSynchronize(cs));
-  // the compute waits for the side-stream transfers of the last delta
-  if (!res->host_pool && res->last_side) TIDE_HIP(hipStreamWaitEvent(cs, res->ev_side, 0));
   // render order: slots of K_t by ascending block id (pidx order = global-id order)
   res->h_order.clear();
   for (int32_t k : need) res->h_order.push_back(res->slot_of[k]);
@@ -977,7 +997,7 @@ tide_status tide_stream_delta(tide_residency* res, const int32_t* knext_ids, con
       if (!e.loading) { res->st.host_misses++; res->start_read(idx); }
       else if (e.prefetched) { res->st.prefetch_used++; e.prefetched = false; }
       res->promote(idx);
-      res->pending_h2d.push_back(k);
+      if (!res->pending_contains(k)) res->pending_h2d.push_back(k);
     }
     return TIDE_OK;
   };
