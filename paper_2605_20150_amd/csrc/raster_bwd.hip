@@ -218,7 +218,7 @@ __global__ void __launch_bounds__(64) k_reduce_pairs(const uint32_t* __restrict_
   if (lane < np) {
     const uint32_t r = vis_rec[s0 + lane];
 #pragma unroll
-    for (int m = 0; m < kG2; ++m) g2d[(int64_t)m * n_rec + r] = s_acc[lane][m];
+    for (int m = 0; m < kG2; ++m) g2d[(int64_t)r * kG2 + m] = s_acc[lane][m];
   }
 }
 
@@ -239,7 +239,6 @@ __global__ void __launch_bounds__(128) k_adjoint(const T* __restrict__ params, c
   const int32_t row = (int32_t)(i - k * B);
   const int32_t slot = order[k];
   const T* P = params + (int64_t)slot * kD * B + row;
-  const int64_t nrec = (int64_t)cs.n * n_pidx;
   const T mu0 = P[0], mu1 = P[B], mu2 = P[2 * (int64_t)B];
   const T s0 = Mth<T>::exp(P[3 * (int64_t)B]), s1 = Mth<T>::exp(P[4 * (int64_t)B]),
           s2 = Mth<T>::exp(P[5 * (int64_t)B]);
@@ -276,9 +275,9 @@ __global__ void __launch_bounds__(128) k_adjoint(const T* __restrict__ params, c
     const int64_t o = (int64_t)c * n_pidx + i;
     if (tt[o] == 0) continue;
     const DevCam<T>& cm = cs.c[c];
-    const T gu = g2d[0 * nrec + o], gv = g2d[1 * nrec + o], gA = g2d[2 * nrec + o], gB = g2d[3 * nrec + o],
-            gC = g2d[4 * nrec + o], gop = g2d[5 * nrec + o];
-    const T gcol[3] = {g2d[6 * nrec + o], g2d[7 * nrec + o], g2d[8 * nrec + o]};
+    const T* G2 = g2d + o * kG2;
+    const T gu = G2[0], gv = G2[1], gA = G2[2], gB = G2[3], gC = G2[4], gop = G2[5];
+    const T gcol[3] = {G2[6], G2[7], G2[8]};
     // ---- colour
     T dx = mu0 - cm.pos[0], dy = mu1 - cm.pos[1], dz = mu2 - cm.pos[2];
     const T len = Mth<T>::sqrt(dx * dx + dy * dy + dz * dz);
