@@ -158,11 +158,16 @@ inline double rel_int_dist(double x) {  // distance of x to the nearest integer
 // Near-tie model.  A discrete decision taken in single precision can differ
 // from the double-precision one when its margin is within the rounding error
 // its inputs carry.  Every margin below is divided by a first-order estimate
-// of that error, so a ratio below 1 marks a near tie:
-//   position  perr = 2^-20 (|u| + |cx| + f (|mu| + |t|) / p_z)  pixels
-//   depth     derr = 2^-20 (|mu| + |t|)
+// of that error (16 units of the precision the decision is evaluated in), so
+// a ratio below 1 marks a near tie.  The camera-space mean, the pixel
+// position and the near/far tests are double-precision quantities rounded
+// once to single precision (u, v, depth); everything else is single:
+//   position  perr = 2^-20 (|u| + |v| + |cx| + |cy|) + 2^-48 f (|mu| + |t|) / p_z   pixels
+//   depth     derr = 2^-20 |p_z| + 2^-48 (|mu| + |t|)  (the sort key)
+//   near/far  2^-48 (|mu| + |t|)
 //   any other quantity x: 2^-20 |x| (relative).
 constexpr double kTieRel = 1.0 / 1048576.0;
+constexpr double kTieRel64 = 1.0 / 281474976710656.0;   // 2^-48
 
 // Tile-coverage rectangle of O4 with exact integer-vs-real comparisons:
 // x0 = smallest tx with 16(tx+1) + r > u, x1 = 1 + largest tx with 16 tx - r <= u,
@@ -198,9 +203,10 @@ void project_one(const double* th, const Cam& c, Fwd& f) {
   f.depth = pz;
   const double mun = std::sqrt(mu[0] * mu[0] + mu[1] * mu[1] + mu[2] * mu[2]);
   const double tn = std::sqrt(c.t[0] * c.t[0] + c.t[1] * c.t[1] + c.t[2] * c.t[2]);
-  f.derr = kTieRel * (mun + tn);
-  f.margin = std::min(f.margin, std::fabs(pz - c.znear) / f.derr);
-  f.margin = std::min(f.margin, std::fabs(pz - c.zfar) / f.derr);
+  const double nf_err = kTieRel64 * (mun + tn);
+  f.derr = kTieRel * std::fabs(pz) + nf_err;
+  f.margin = std::min(f.margin, std::fabs(pz - c.znear) / nf_err);
+  f.margin = std::min(f.margin, std::fabs(pz - c.zfar) / nf_err);
   if (!(pz > c.znear) || pz > c.zfar) return;
 
   // activations
@@ -225,8 +231,8 @@ void project_one(const double* th, const Cam& c, Fwd& f) {
   // pinhole projection
   f.u = c.fx * f.p[0] / pz + c.cx;
   f.v = c.fy * f.p[1] / pz + c.cy;
-  f.perr = kTieRel * (std::fabs(f.u) + std::fabs(f.v) + std::fabs(c.cx) + std::fabs(c.cy) +
-                      std::max(c.fx, c.fy) * (mun + tn) / std::fabs(pz));
+  f.perr = kTieRel * (std::fabs(f.u) + std::fabs(f.v) + std::fabs(c.cx) + std::fabs(c.cy)) +
+           kTieRel64 * std::max(c.fx, c.fy) * (mun + tn) / std::fabs(pz);
 
   // EWA: J evaluated at the clamped tangents
   const double limx = 1.3 * (0.5 * c.W) / c.fx, limy = 1.3 * (0.5 * c.H) / c.fy;

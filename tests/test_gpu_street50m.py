@@ -108,10 +108,17 @@ def test_street_50m_rates_crop_gradient_and_finite_differences():
     g_gpu = gd[torch.from_numpy(rows).cuda()].double().cpu().numpy()
     img_err = np.abs(fr.image.double().cpu().numpy() - ref["image"]).max(axis=1)
     tie_px = ref["pix_margin"] < NEAR_TIE
-    say(f"crop image max-abs error {img_err[~tie_px].max():.3e} ({int(tie_px.sum())} near-tie pixels)")
+    say(f"crop image max-abs error {img_err[~tie_px].max():.3e} ({int(tie_px.sum())} near-tie pixels of "
+        f"{tie_px.size}; all pixels {img_err.max():.3e})")
     assert img_err[~tie_px].max() <= 1e-4
+    # a near-tie decision that flips moves a pixel by at most one entry's
+    # contribution at the 1/255 alpha floor (or by T below 1e-4)
+    assert img_err.max() <= 1e-2
     tie_rows = (ref["pair_margin"] < NEAR_TIE).any(axis=0)
     ok = ~tie_rows
+    act_sub = np.isin(rows, active)
+    say(f"active rows compared: {int((act_sub & ok).sum())} of {int(act_sub.sum())}")
+    assert (act_sub & ok).sum() >= 0.5 * act_sub.sum()
     rel = np.linalg.norm(g_gpu[ok] - g_ref[ok]) / np.linalg.norm(g_ref[ok])
     bound = 1e-3 * np.abs(g_ref[ok]) + 1e-4 * np.abs(g_ref[ok]).max()
     bad = int((np.abs(g_gpu[ok] - g_ref[ok]) > bound).sum())
