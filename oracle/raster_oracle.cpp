@@ -163,11 +163,24 @@ inline double rel_int_dist(double x) {  // distance of x to the nearest integer
 // position and the near/far tests are double-precision quantities rounded
 // once to single precision (u, v, depth); everything else is single:
 //   position  perr = 2^-20 (|u| + |v| + |cx| + |cy|) + 2^-48 f (|mu| + |t|) / p_z   pixels
-//   depth     derr = 2^-20 |p_z| + 2^-48 (|mu| + |t|)  (the sort key)
+//   depth     the sort key is single precision on both sides; its only risk
+//             is a rounding midpoint within 2^-48 (|mu| + |t|) of p_z
 //   near/far  2^-48 (|mu| + |t|)
 //   any other quantity x: 2^-20 |x| (relative).
 constexpr double kTieRel = 1.0 / 1048576.0;
 constexpr double kTieRel64 = 1.0 / 281474976710656.0;   // 2^-48
+
+// Depth sort key (reading of the total order (tile, depth, gid) with the
+// depth taken in single precision, as the binning keys are).
+inline double sort_key(double depth) { return (double)(float)depth; }
+
+// Distance of x to the nearest single-precision rounding midpoint.
+inline double key_midpoint_distance(double x) {
+  const float f = (float)x;
+  const double lo = 0.5 * ((double)f + (double)std::nextafter(f, -INFINITY));
+  const double hi = 0.5 * ((double)f + (double)std::nextafter(f, INFINITY));
+  return std::min(std::fabs(x - lo), std::fabs(hi - x));
+}
 
 // Tile-coverage rectangle of O4 with exact integer-vs-real comparisons:
 // x0 = smallest tx with 16(tx+1) + r > u, x1 = 1 + largest tx with 16 tx - r <= u,
@@ -204,7 +217,12 @@ void project_one(const double* th, const Cam& c, Fwd& f) {
   const double mun = std::sqrt(mu[0] * mu[0] + mu[1] * mu[1] + mu[2] * mu[2]);
   const double tn = std::sqrt(c.t[0] * c.t[0] + c.t[1] * c.t[1] + c.t[2] * c.t[2]);
   const double nf_err = kTieRel64 * (mun + tn);
-  f.derr = kTieRel * std::fabs(pz) + nf_err;
+  // The sort key is the single-precision depth (ties by gid): the only way
+  // an order can differ is a double-precision depth so close to a rounding
+  // midpoint of single precision that another evaluation order of p_z
+  // rounds it the other way.
+  f.derr = 0;
+  f.margin = std::min(f.margin, key_midpoint_distance(pz) / nf_err);
   f.margin = std::min(f.margin, std::fabs(pz - c.znear) / nf_err);
   f.margin = std::min(f.margin, std::fabs(pz - c.zfar) / nf_err);
   if (!(pz > c.znear) || pz > c.zfar) return;
@@ -520,7 +538,7 @@ int orc_render(const double* theta, int64_t n, const double* cams, int n_cams, c
   std::vector<double> u(n_cams * n), v(n_cams * n), d(n_cams * n), rec(n_cams * n * 9), unc(n_cams * n * 3);
   std::vector<int32_t> r(n_cams * n), k(n_cams * n);
   for (int64_t q = 0; q < n_cams * n; ++q) {
-    u[q] = pf[16 * q]; v[q] = pf[16 * q + 1]; d[q] = pf[16 * q + 2];
+    u[q] = pf[16 * q]; v[q] = pf[16 * q + 1]; d[q] = sort_key(pf[16 * q + 2]);
     r[q] = pi[7 * q + 1]; k[q] = pi[7 * q];
     for (int j = 0; j < 9; ++j) rec[9 * q + j] = pf[16 * q + (j < 2 ? j : j + 1)];
     unc[3 * q] = d[q]; unc[3 * q + 1] = pf[16 * q + 14]; unc[3 * q + 2] = pf[16 * q + 15];
@@ -616,7 +634,7 @@ int orc_backward(const double* theta, int64_t n, const double* cams, int n_cams,
     std::vector<int32_t> r(n), k(n);
     std::vector<Rec> R(n);
     for (int64_t i = 0; i < n; ++i) {
-      u[i] = F[i].u; v[i] = F[i].v; d[i] = F[i].depth; r[i] = F[i].r; k[i] = F[i].keep;
+      u[i] = F[i].u; v[i] = F[i].v; d[i] = sort_key(F[i].depth); r[i] = F[i].r; k[i] = F[i].keep;
       R[i] = Rec{F[i].u, F[i].v, F[i].A, F[i].B, F[i].C, F[i].op, {F[i].rgb[0], F[i].rgb[1], F[i].rgb[2]},
                  F[i].depth, F[i].perr, F[i].derr};
     }

@@ -236,6 +236,26 @@ def test_two_gaussians_front_to_back():
     assert np.abs(out["image"][0, :, py, px] - expect).max() < 1e-14
 
 
+def test_depth_ties_in_single_precision_keep_gid_order():
+    """The order is (tile, single-precision depth, gid): two depths that
+    round to the same float are composited in gid order even when the
+    double-precision depths say otherwise."""
+    th = np.concatenate([one_gaussian((0.0, 0.0, 1e-8), (-1.5, -1.5, -1.5), ologit=0.0, dc=(1.0, -1.0, -1.0)),
+                         one_gaussian((0.0, 0.0, 0.0), (-1.5, -1.5, -1.5), ologit=0.5, dc=(-1.0, 1.0, -1.0))])
+    p = oracle.project(th, cam_row())
+    assert p["depth"][0, 0] > p["depth"][0, 1] and np.float32(p["depth"][0, 0]) == np.float32(p["depth"][0, 1])
+    out = oracle.render(th, cam_row())
+    px, py = 32, 32
+    alphas, cols = [], []
+    for i in range(2):
+        A, B, C = p["conic"][0, i]
+        dx, dy = px + 0.5 - p["u"][0, i], py + 0.5 - p["v"][0, i]
+        alphas.append(min(0.99, p["opacity"][0, i] * math.exp(-0.5 * (A * dx * dx + C * dy * dy) - B * dx * dy)))
+        cols.append(p["rgb"][0, i])
+    expect = cols[0] * alphas[0] + cols[1] * alphas[1] * (1 - alphas[0])      # gid 0 first
+    assert np.abs(out["image"][0, :, py, px] - expect).max() < 1e-14
+
+
 def _brute_render(th, cams):
     """Tile-free renderer: for each pixel gather every kept Gaussian whose
     rect contains the pixel's tile, order by (depth, gid), composite."""
@@ -254,7 +274,7 @@ def _brute_render(th, cams):
                         continue
                     x0, y0, x1, y1 = p["rect"][c, i]
                     if x0 <= tx < x1 and y0 <= ty < y1:
-                        cand.append((p["depth"][c, i], i))
+                        cand.append((float(np.float32(p["depth"][c, i])), i))
                 T, col = 1.0, np.zeros(3)
                 for _, i in sorted(cand):
                     A, B, C = p["conic"][c, i]
