@@ -36,14 +36,15 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
   const int py0 = ty * kTile + (lane >> 4);
   const T fxp = (T)px + (T)0.5;
   const int64_t HW = (int64_t)H * W;
-  T fyp[4], Tr[4], g0[4], g1[4], g2[4], rb0[4], rb1[4], rb2[4];
+  // Pb = (colour behind the current entry) . dL/dpixel, per pixel: the only
+  // way the backward needs the colour behind, so it is carried as one scalar.
+  T fyp[4], Tr[4], g0[4], g1[4], g2[4], Pb[4];
   uint32_t lst[4];
   uint32_t maxl = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int py = py0 + 4 * q;
     fyp[q] = (T)py + (T)0.5;
-    rb0[q] = bg0; rb1[q] = bg1; rb2[q] = bg2;
     if (px < W && py < H) {
       const int64_t p = (int64_t)py * W + px;
       Tr[q] = tfin[(int64_t)c * HW + p];
@@ -54,6 +55,7 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
     } else {
       Tr[q] = 1; lst[q] = 0; g0[q] = g1[q] = g2[q] = 0;
     }
+    Pb[q] = bg0 * g0[q] + bg1 * g1[q] + bg2 * g2[q];
     maxl = lst[q] > maxl ? lst[q] : maxl;
   }
 #pragma unroll
@@ -115,9 +117,9 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
         Tr[q] = Tn;
         const T w = a_ok * Tn;
         a_r += w * g0[q]; a_g += w * g1[q]; a_b += w * g2[q];
-        const T d0 = cr - rb0[q], d1 = cg - rb1[q], d2 = cb - rb2[q];
-        const T dal = Tn * (d0 * g0[q] + d1 * g1[q] + d2 * g2[q]);
-        rb0[q] += a_ok * d0; rb1[q] += a_ok * d1; rb2[q] += a_ok * d2;
+        const T e = (cr * g0[q] + cg * g1[q] + cb * g2[q]) - Pb[q];   // (c - behind) . dL/dpixel
+        const T dal = Tn * e;
+        Pb[q] += a_ok * e;
         a_o += dal * G_ok;
         const T dp = dal * r_ok;
         const T dpdy = dp * dy;
