@@ -288,6 +288,17 @@ typedef struct tide_residency tide_residency;
 
 #define TIDE_TIER_HOST_POOL 1   /* pool / spheres / dirty are host memory (CPU-only runs) */
 #define TIDE_TIER_ODIRECT 2     /* O_DIRECT reads and writes of the segment files */
+/* Ablations of the paper's techniques (Sec. 4.4, the ablation table):
+ * NO_TIDE     no differential streaming: R_{t+1} = K_{t+1}, every block of
+ *             K_{t+1} is transferred again and every resident block leaves
+ *             (written back when dirty or in use);
+ * NO_OVERLAP  transfers serialised with compute: tide_stream_delta waits for
+ *             the current compute, then for its reads and copies, before it
+ *             returns, and tide_prefetch_hint waits for its reads (the
+ *             blocked time is counted as stall).
+ * Neither changes which blocks a render sees, so results are unchanged. */
+#define TIDE_TIER_NO_TIDE 4
+#define TIDE_TIER_NO_OVERLAP 8
 
 typedef struct {
   const char* dir;            /* directory of the segment files (created if missing) */

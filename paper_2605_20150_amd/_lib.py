@@ -94,6 +94,8 @@ class tide_mlp(C.Structure):
 
 TIDE_TIER_HOST_POOL = 1
 TIDE_TIER_ODIRECT = 2
+TIDE_TIER_NO_TIDE = 4
+TIDE_TIER_NO_OVERLAP = 8
 
 _P = C.POINTER
 _vp = C.c_void_p

@@ -286,6 +286,7 @@ struct tide_residency {
   int32_t B = 0, C = 0;
   int64_t host_cap = 0;
   bool host_pool = false;
+  bool no_tide = false, no_overlap = false;   // ablation switches
   double lambda = 0.75, gamma = 0.9, kappa = 1.32;
   size_t pbytes = 0, sbytes = 0, rec = 0;
   // caller memory
@@ -630,6 +631,8 @@ tide_status tide_residency_create(const tide_store_cfg* cfg, tide_pool* pool, fl
   r->C = cfg->capacity;
   r->host_cap = cfg->host_cache_blocks;
   r->host_pool = (cfg->flags & TIDE_TIER_HOST_POOL) != 0;
+  r->no_tide = (cfg->flags & TIDE_TIER_NO_TIDE) != 0;
+  r->no_overlap = (cfg->flags & TIDE_TIER_NO_OVERLAP) != 0;
   r->lambda = cfg->lambda_;
   r->gamma = cfg->gamma;
   r->kappa = cfg->kappa;
@@ -960,12 +963,23 @@ tide_status tide_stream_delta(tide_residency* res, const int32_t* knext_ids, con
     if (!chosen.count(k)) rest.push_back(k);
   std::stable_sort(rest.begin(), rest.end(), better);
   for (size_t i = 0; i < rest.size() && (int)chosen.size() < res->C; ++i) chosen.insert(rest[i]);
-  // 6. set differences
+  // 6. set differences (the no-Tide ablation moves all of K_{t+1} again and
+  //    lets every resident block go)
   std::vector<int32_t> Sp, Sm;
-  for (int32_t k : chosen)
-    if (!res->R.count(k)) Sp.push_back(k);
-  for (int32_t k : res->R)
-    if (!chosen.count(k)) Sm.push_back(k);
+  if (res->no_tide) {
+    // blocks that are not resident first: they can take free slots at once
+    TIDE_CHECK_ARG((int64_t)Kn.size() <= res->C, "K_{t+1} (%zu blocks) exceeds the capacity", Kn.size());
+    for (int32_t k : Kn)
+      if (!res->R.count(k)) Sp.push_back(k);
+    for (int32_t k : Kn)
+      if (res->R.count(k)) Sp.push_back(k);
+    Sm.assign(res->R.begin(), res->R.end());
+  } else {
+    for (int32_t k : chosen)
+      if (!res->R.count(k)) Sp.push_back(k);
+    for (int32_t k : res->R)
+      if (!chosen.count(k)) Sm.push_back(k);
+  }
   if (out_plus) TIDE_CHECK_ARG((int64_t)Sp.size() <= cap && (int64_t)Sm.size() <= cap, "delta output capacity");
   if (n_plus) *n_plus = (int32_t)Sp.size();
   if (n_minus) *n_minus = (int32_t)Sm.size();
@@ -1001,8 +1015,12 @@ tide_status tide_stream_delta(tide_residency* res, const int32_t* knext_ids, con
     }
     return TIDE_OK;
   };
+  const double t_serial = now_s();
+  if (res->no_overlap && !res->host_pool && res->compute_recorded) TIDE_HIP(hipEventSynchronize(res->ev_compute));
   size_t i = 0;
-  for (; i < Sp.size() && next < free_now.size(); ++i) {
+  // (with no_tide a resident block leaves and comes back in the same delta:
+  // its admission waits for its eviction)
+  for (; i < Sp.size() && next < free_now.size() && !(res->no_tide && res->R.count(Sp[i])); ++i) {
     tide_status r = admit(Sp[i], free_now[next++]);
     if (r != TIDE_OK) return r;
   }
@@ -1014,6 +1032,7 @@ tide_status tide_stream_delta(tide_residency* res, const int32_t* knext_ids, con
     if (r != TIDE_OK) return r;
     freed.push_back(slot);
   }
+  if (res->no_tide) freed.insert(freed.end(), free_now.begin() + (std::ptrdiff_t)next, free_now.end());
   std::sort(freed.begin(), freed.end());
   for (size_t f = 0; i < Sp.size() && f < freed.size(); ++i, ++f) {
     tide_status r = admit(Sp[i], freed[f]);
@@ -1026,6 +1045,14 @@ tide_status tide_stream_delta(tide_residency* res, const int32_t* knext_ids, con
   if (!res->host_pool) TIDE_HIP(hipEventRecord(res->ev_side, ss));
   res->last_side = ss;
   res->st.resident = (int64_t)res->R.size();
+  if (res->no_overlap) {
+    // serialised: every read and copy of this delta completes before the
+    // next compute can be enqueued
+    res->cv.wait(lk, [&] { return res->pending_h2d.empty() || res->io_error != TIDE_OK; });
+    if (res->io_error != TIDE_OK) return res->io_failed();
+    if (!res->host_pool) TIDE_HIP(hipStreamSynchronize(ss));
+    res->st.stall_seconds += now_s() - t_serial;
+  }
   return TIDE_OK;
 }
 
@@ -1057,6 +1084,18 @@ tide_status tide_prefetch_hint(tide_residency* res, const int32_t* blocks, int32
     res->start_read(idx, true);
     res->st.prefetch_issued++;
     ++outstanding;
+  }
+  if (res->no_overlap) {
+    // serialised: the read-ahead also completes before the next compute
+    const double t0 = now_s();
+    res->cv.wait(lk, [&] {
+      if (res->io_error != TIDE_OK) return true;
+      for (const auto& e : res->ent)
+        if (e.loading && e.spec_read) return false;
+      return true;
+    });
+    res->st.stall_seconds += now_s() - t0;
+    if (res->io_error != TIDE_OK) return res->io_failed();
   }
   return TIDE_OK;
 }

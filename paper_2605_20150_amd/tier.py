@@ -25,7 +25,9 @@ def _ptr(a):
 class Tier:
     def __init__(self, directory: str, n_rows: int, pool: Pool, capacity: int, host_cache_blocks: int,
                  io_threads: int = 4, lam: float = 0.75, gamma: float = 0.9, kappa: float = 1.32,
-                 host_pool: bool = False, odirect: bool = False):
+                 host_pool: bool = False, odirect: bool = False, no_tide: bool = False, no_overlap: bool = False):
+        """no_tide / no_overlap: the paper's ablations (full retransmission of
+        K_{t+1}; transfers serialised with compute)."""
         self.lib = L.load()
         self.pool = pool
         self.B = pool.block_rows
@@ -43,7 +45,8 @@ class Tier:
         cfg.capacity = int(capacity)
         cfg.host_cache_blocks = int(host_cache_blocks)
         cfg.io_threads = int(io_threads)
-        cfg.flags = (L.TIDE_TIER_HOST_POOL if host_pool else 0) | (L.TIDE_TIER_ODIRECT if odirect else 0)
+        cfg.flags = ((L.TIDE_TIER_HOST_POOL if host_pool else 0) | (L.TIDE_TIER_ODIRECT if odirect else 0) |
+                     (L.TIDE_TIER_NO_TIDE if no_tide else 0) | (L.TIDE_TIER_NO_OVERLAP if no_overlap else 0))
         cfg.lambda_, cfg.gamma, cfg.kappa = float(lam), float(gamma), float(kappa)
         self.cfg = cfg
         h = C.c_void_p()

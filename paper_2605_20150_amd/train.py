@@ -51,7 +51,8 @@ class OutOfCoreTrainer:
 
     def __init__(self, theta, block_rows: int, directory: str, capacity: int, spare_slots: int,
                  host_cache_blocks: int, device="cuda", kappa=1.32, io_threads=4, predictor=None,
-                 n_rows: int | None = None, odirect: bool = False):
+                 n_rows: int | None = None, odirect: bool = False, no_tide: bool = False,
+                 no_overlap: bool = False):
         """theta: the [N][59] table to lay out in a new store, or None to
         reopen the store already in ``directory`` (n_rows rows, from its
         persisted Index)."""
@@ -60,7 +61,7 @@ class OutOfCoreTrainer:
         self.B = block_rows
         self.pool = Pool.empty(capacity + spare_slots, block_rows, device)
         self.tier = Tier(directory, self.N, self.pool, capacity, host_cache_blocks, io_threads=io_threads,
-                         kappa=kappa, odirect=odirect)
+                         kappa=kappa, odirect=odirect, no_tide=no_tide, no_overlap=no_overlap)
         if theta is not None:
             for k in range(self.tier.K):
                 rows = theta[k * block_rows:(k + 1) * block_rows]

@@ -23,10 +23,10 @@ def scene(n=2500, seed=40):
     return th[np.lexsort((cell[:, 2], cell[:, 1], cell[:, 0]))]
 
 
-def build(tmp_path, th, n_slots=6, capacity=6, cache=4, name="store", odirect=False, rows=B):
+def build(tmp_path, th, n_slots=6, capacity=6, cache=4, name="store", odirect=False, rows=B, **flags):
     pool = Pool.empty(n_slots, rows, "cpu")
     t = Tier(str(tmp_path / name), th.shape[0], pool, capacity, cache, io_threads=2, host_pool=True, kappa=1.32,
-             odirect=odirect)
+             odirect=odirect, **flags)
     for k in range(t.K):
         r = th[k * rows:(k + 1) * rows]
         t.put_block(k, r.T)
@@ -234,3 +234,54 @@ def test_direct_io_write_back_and_reopen(tmp_path):
     for k in range(t2.K):
         assert np.array_equal(t2.read_block(k)["params"], truth[k]), k
     t2.close()
+
+
+def _trained_walk(tmp_path, name, **flags):
+    """A drifting two-camera walk in which every rendered block is updated:
+    per delta S+ and S-, the resident set after each ensure, the final
+    blocks and the counters."""
+    th = scene()
+    t, pool = build(tmp_path, th, n_slots=6, capacity=6, cache=4, name=name, **flags)
+    sets = walk_sets(np.random.default_rng(45), t.K, 30)
+    deltas, resident = [], []
+    for i, cams in enumerate(sets):
+        Kt = sorted(set(x for c in cams for x in c))
+        t.ensure_resident(Kt)
+        resident.append(sorted(t.resident_slots()))
+        slots = t.resident_slots()
+        for k in Kt:
+            pool.params[slots[k]] += 0.125 * (k + 1)
+            pool.step[slots[k]] += 1
+            t.dirty[k] = 1
+        t.end_iteration()
+        if i + 1 < len(sets):
+            sp, sm = t.stream_delta(sets[i + 1])
+            deltas.append((sp.tolist(), sm.tolist()))
+        t.sync_bounds()
+    blocks = [t.read_block(k) for k in range(t.K)]
+    st = t.stats()
+    t.close()
+    return sets, deltas, resident, blocks, st
+
+
+@pytest.mark.parametrize("flag", ["no_tide", "no_overlap"])
+def test_ablation_switches_change_the_schedule_not_the_data(tmp_path, flag):
+    """Sec. 4.4's ablations.  Without differential streaming every block of
+    K_{t+1} moves again (S+ = K_{t+1}, S- = R_t, R_{t+1} = K_{t+1}) and the
+    host-to-device traffic grows; without overlap the decisions are the full
+    method's.  Either way every block ends with the same bytes."""
+    sets, d_full, r_full, b_full, s_full = _trained_walk(tmp_path, "full")
+    _, d_abl, r_abl, b_abl, s_abl = _trained_walk(tmp_path, flag, **{flag: True})
+    for k, (a, b) in enumerate(zip(b_full, b_abl)):
+        for name in ("params", "exp_avg", "exp_avg_sq", "step"):
+            assert np.array_equal(a[name], b[name]), (flag, k, name)
+    if flag == "no_overlap":
+        assert d_abl == d_full and r_abl == r_full
+        assert s_abl["h2d_bytes"] == s_full["h2d_bytes"]
+    else:
+        for i, (sp, sm) in enumerate(d_abl):
+            nxt = sorted(set(x for c in sets[i + 1] for x in c))
+            assert sorted(sp) == nxt and sorted(sm) == r_abl[i], i
+            assert r_abl[i + 1] == nxt, i
+        assert s_abl["h2d_bytes"] > s_full["h2d_bytes"]
+        assert s_abl["blocks_in"] == sum(len(sp) for sp, _ in d_abl)
