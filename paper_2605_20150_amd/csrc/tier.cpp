@@ -429,13 +429,16 @@ struct tide_residency {
       return f->second;
     }
     for (;;) {
+      bool transient = false;   // some entry will free itself (a read or flush completes)
       for (auto it = lru.rbegin(); it != lru.rend(); ++it) {
         Entry& e = ent[*it];
-        if (e.loading || e.flushing || e.undecided) continue;
-        if (e.block >= 0 && slot_of[e.block] >= 0 && pending_contains(e.block)) continue;
+        if (e.loading || e.flushing) { transient = true; continue; }
+        if (e.undecided) continue;
+        if (e.block >= 0 && slot_of[e.block] >= 0 && pending_contains(e.block)) { transient = true; continue; }
         if (spec && protected_prefetch(e)) continue;
         if (e.dirty) {
           start_flush(*it);
+          transient = true;
           continue;
         }
         wait_fence(e);
@@ -447,9 +450,18 @@ struct tide_residency {
         lru.splice(lru.begin(), lru, e.it);
         return idx;
       }
+      if (io_error != TIDE_OK) return -1;
+      if (!transient) {
+        // every entry is pinned until the next sync_bounds: waiting would never end
+        set_error("host cache of %lld blocks too small: every entry holds a block of the iteration in flight",
+                  (long long)host_cap);
+        return -1;
+      }
       cv.wait(lk);   // every entry is busy: wait for a read or flush to finish
     }
   }
+  // status of a failed entry_for
+  tide_status no_entry() const { return io_error != TIDE_OK ? io_failed() : TIDE_ECAPACITY; }
   bool pending_contains(int64_t k) const {
     return std::find(pending_h2d.begin(), pending_h2d.end(), (int32_t)k) != pending_h2d.end();
   }
@@ -527,6 +539,7 @@ struct tide_residency {
   // (blocking).  Counts a hit or a miss.
   int fetch_blocking(int64_t k, std::unique_lock<std::mutex>& lk) {
     const int idx = entry_for(k, lk);
+    if (idx < 0) return -1;
     Entry& e = ent[idx];
     if (e.valid || e.loading) st.host_hits++;
     else { st.host_misses++; start_read(idx); }
@@ -580,6 +593,7 @@ struct tide_residency {
     const bool in_flight = std::binary_search(Kcur.begin(), Kcur.end(), (int32_t)k);
     if (gpu_dirty[k] || in_flight) {
       const int idx = entry_for(k, lk);
+      if (idx < 0) return no_entry();
       Entry& e = ent[idx];
       cv.wait(lk, [&] { return !ent[idx].loading && !ent[idx].flushing; });
       tide_status r = d2h_block(slot, e.buf, s);
@@ -834,6 +848,7 @@ tide_status tide_ensure_resident(tide_residency* res, const int32_t* K, int32_t 
       slot = vs;
     }
     const int idx = res->fetch_blocking(k, lk);
+    if (idx < 0) return res->no_entry();
     res->occupy(slot, k);
     res->R.insert(k);
     tide_status r = res->h2d_block(slot, res->ent[idx].buf, cs);
@@ -1000,6 +1015,7 @@ tide_status tide_stream_delta(tide_residency* res, const int32_t* knext_ids, con
     res->occupy(slot, k);
     res->R.insert(k);
     const int idx = res->entry_for(k, lk);
+    if (idx < 0) return res->no_entry();
     auto& e = res->ent[idx];
     if (e.valid && !e.loading) {
       res->st.host_hits++;
@@ -1079,6 +1095,7 @@ tide_status tide_prefetch_hint(tide_residency* res, const int32_t* blocks, int32
     }
     if (!room) break;
     const int idx = res->entry_for(k, lk, true);
+    if (idx < 0) return res->no_entry();
     res->ent[idx].prefetched = true;
     res->ent[idx].prefetch_iter = res->st.iterations;
     res->start_read(idx, true);
@@ -1109,6 +1126,7 @@ tide_status tide_checkpoint(tide_residency* res) {
   for (int32_t k : res->R) {
     if (!res->gpu_dirty[k]) continue;
     const int idx = res->entry_for(k, lk);
+    if (idx < 0) return res->no_entry();
     res->cv.wait(lk, [&] { return !res->ent[idx].loading && !res->ent[idx].flushing; });
     if (res->host_pool) {
       r = res->d2h_block(res->slot_of[k], res->ent[idx].buf, nullptr);

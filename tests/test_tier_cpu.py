@@ -285,3 +285,17 @@ def test_ablation_switches_change_the_schedule_not_the_data(tmp_path, flag):
             assert r_abl[i + 1] == nxt, i
         assert s_abl["h2d_bytes"] > s_full["h2d_bytes"]
         assert s_abl["blocks_in"] == sum(len(sp) for sp, _ in d_abl)
+
+
+def test_host_cache_pinned_by_the_iteration_in_flight_is_an_error(tmp_path):
+    """Blocks of the iteration in flight that leave the GPU stay pinned in the
+    host cache until the next sync_bounds.  When they fill it, the delta
+    reports the cache as too small instead of waiting forever."""
+    th = scene()
+    t, pool = build(tmp_path, th, n_slots=6, capacity=6, cache=4, no_tide=True)
+    Kt = [0, 1, 2, 3, 4]
+    t.ensure_resident(Kt)
+    t.end_iteration()
+    with pytest.raises(RuntimeError, match="too small"):
+        t.stream_delta([[5, 6, 7, 8, 9]])
+    t.close()
