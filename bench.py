@@ -50,9 +50,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-blobs", type=int, default=200)
     ap.add_argument("--per-blob", type=int, default=5000)
-    ap.add_argument("--workload", choices=["aerial", "city"], default="aerial",
+    ap.add_argument("--workload", choices=["aerial", "city", "city-ablation"], default="aerial",
                     help="aerial: resident training (default); city: out-of-core street city, exact-only "
-                         "streaming against predictor-hinted streaming")
+                         "streaming against predictor-hinted streaming; city-ablation: the same city "
+                         "without differential streaming, without overlap and without the Morton layout")
     ap.add_argument("--city-blocks", type=int, default=954, help="blocks of 65536 Gaussians (954 = 1 km^2)")
     ap.add_argument("--city-iters", type=int, default=150)
     ap.add_argument("--city-dir", default="/tmp/tide_city_store")
@@ -132,6 +133,92 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def city_size(args, rec):
+    from paper_2605_20150_amd import city as CT
+    import math
+    free = CT.free_bytes(args.city_dir)
+    n_blocks = min(args.city_blocks, int(0.6 * free // rec))
+    extent = 1000.0 * math.sqrt(n_blocks / 954.0)
+    return n_blocks, extent, free
+
+
+def ablation_main(args):
+    """Sec. 4.4's component ablations on the out-of-core street city, one
+    walk, exact culling only: the full method (Alg. 1, transfers overlapped
+    with compute), without differential streaming (every block of K_{t+1}
+    moves again), without overlap (transfers serialised with compute), and
+    without the Morton layout (the same centres in random order, a store of
+    its own)."""
+    import shutil
+
+    import numpy as np
+
+    from paper_2605_20150_amd import city as CT
+    from paper_2605_20150_amd import predictor as P
+
+    B = 65536
+    rec = B * (3 * 59 * 4 + 4)
+    n_blocks, extent, free = city_size(args, rec)
+    z_far = args.city_zfar
+    T = args.city_iters
+    H = args.city_host_blocks
+    log(f"ablation city: {n_blocks} blocks of {B} over {extent:.0f} m, store {n_blocks * rec / 1e9:.1f} GB "
+        f"({free / 1e9:.0f} GB free), {T} iterations, host cache {H} blocks")
+
+    def sizes_of(spheres, batches):
+        K = spheres.shape[0]
+        words = (K + 31) // 32
+        return [len(P.bits_to_ids(P.cull_bits(spheres, b, words), K)) for b in batches]
+
+    shutil.rmtree(args.city_dir, ignore_errors=True)
+    N, city, spheres, build_m = CT.build_store(args.city_dir, n_blocks, B, 30, extent, log=log)
+    batches = CT.walk_batches(city, 34, T + 1, z_far, 1600, 900)
+    sizes = sizes_of(spheres, batches)
+    capacity = 2 * max(sizes) + 8
+    targets = CT.targets_for(batches, 35, 900, 1600)
+    runs, digests = {}, {}
+    for name, kw in (("full", {}), ("no_tide", dict(no_tide=True)), ("no_overlap", dict(no_overlap=True))):
+        log(f"run {name}: capacity {capacity}, |K_t| {min(sizes)}..{max(sizes)}")
+        res, dig, _ = CT.run(args.city_dir, N, B, batches, targets, capacity, 8, H, None, log=log, **kw)
+        log(f"{name}: {res}")
+        runs[name], digests[name] = res, dig
+    shutil.rmtree(args.city_dir, ignore_errors=True)
+
+    _, _, spheres_r, build_r = CT.build_store(args.city_dir, n_blocks, B, 30, extent, layout="random", log=log)
+    sizes_r = sizes_of(spheres_r, batches)
+    cap_r = max(sizes_r) + 8
+    log(f"run no_morton: |K_t| {min(sizes_r)}..{max(sizes_r)} of {n_blocks} blocks; at capacity {capacity} "
+        f"{'feasible' if max(sizes_r) <= capacity else 'infeasible'}; run at capacity {cap_r}")
+    res, dig_r, _ = CT.run(args.city_dir, N, B, batches, targets, cap_r, 8, H, None, log=log)
+    log(f"no_morton: {res}")
+    shutil.rmtree(args.city_dir, ignore_errors=True)
+    res["feasible_at_full_capacity"] = bool(max(sizes_r) <= capacity)
+    res["capacity_blocks"] = cap_r
+    res["k_t_fraction_of_blocks"] = round(float(np.mean(sizes_r)) / n_blocks, 4)
+    runs["no_morton"] = res
+
+    def row(r):
+        return dict(iter_ms=round(1e3 / r["iters_per_s"], 2), pcie_GB_per_iter=r["pcie_GB_per_iter"],
+                    host_hit_rate=r["host_hit_rate"], stall_s_per_iter=r["stall_s_per_iter"])
+
+    full = runs["full"]
+    out = {
+        "metric": METRIC, "value": full["iters_per_s"], "unit": "iters/s", "n_gpus": 1, "steps": T, "warmup": 0,
+        "ms_per_step": round(1e3 / full["iters_per_s"], 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"component ablations, out-of-core street city, {n_blocks} blocks x {B} Gaussians "
+                               f"({N}), batch 4 x 1600x900, {T}-iteration street walk, exact culling",
+                   "gaussians": N, "blocks": n_blocks, "extent_m": round(extent, 1), "z_far_m": z_far,
+                   "capacity_blocks": capacity, "host_cache_blocks": H, "o_direct": True,
+                   "parallelism": "single GPU"},
+        "table": {k: row(v) for k, v in runs.items()},
+        "runs": runs,
+        "identical_images": {k: digests[k] == digests["full"] for k in ("no_tide", "no_overlap")},
+        "layout_build_s": {"morton": round(build_m, 1), "random": round(build_r, 1)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def city_main(args):
     """Out-of-core street city: the same held-out walk trained from the same
     store with exact-culling-only streaming and with the predictor's hints."""
@@ -146,9 +233,7 @@ def city_main(args):
 
     B = 65536
     rec = B * (3 * 59 * 4 + 4)
-    free = CT.free_bytes(args.city_dir)
-    n_blocks = min(args.city_blocks, int(0.6 * free // rec))
-    extent = 1000.0 * math.sqrt(n_blocks / 954.0)
+    n_blocks, extent, free = city_size(args, rec)
     z_far = args.city_zfar
     log(f"city: {n_blocks} blocks of {B} over {extent:.0f} m, store {n_blocks * rec / 1e9:.1f} GB "
         f"({free / 1e9:.0f} GB free)")
@@ -206,6 +291,8 @@ def main():
         sys.exit(2)
     if args.workload == "city":
         return city_main(args)
+    if args.workload == "city-ablation":
+        return ablation_main(args)
     import numpy as np
     import torch
 

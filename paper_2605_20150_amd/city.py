@@ -35,16 +35,23 @@ from .train import OutOfCoreTrainer
 
 
 def build_store(directory: str, n_blocks: int, B: int, seed: int, extent: float, kappa: float = 1.32,
-                log=print):
+                layout: str = "morton", log=print):
     """Lays out a city of n_blocks * B Gaussians in a new store; returns
-    (N, City, host spheres f32 [K][4], seconds)."""
+    (N, City, host spheres f32 [K][4], seconds).  layout "random" is the
+    ablation without spatial locality (Sec. 4.4): the same centres in a
+    seeded random order."""
+    if layout not in ("morton", "random"):
+        raise ValueError(f"unknown layout {layout!r}")
     t0 = time.perf_counter()
     N = n_blocks * B
     mu, city = synth.city_means(N, seed, extent)
     mu32 = mu.astype(np.float32)
     del mu
-    perm = P.morton_order(mu32)
-    log(f"layout: {N} centres generated and Morton-ordered in {time.perf_counter() - t0:.1f} s")
+    if layout == "morton":
+        perm = P.morton_order(mu32)
+    else:
+        perm = np.random.Generator(np.random.PCG64(seed + 7)).permutation(N).astype(np.int64)
+    log(f"layout: {N} centres generated and put in {layout} order in {time.perf_counter() - t0:.1f} s")
     pool = Pool.empty(1, B, "cpu")
     tier = Tier(directory, N, pool, 1, 4, io_threads=1, kappa=kappa, host_pool=True, odirect=True)
     for k in range(n_blocks):
@@ -104,10 +111,11 @@ def targets_for(batches, seed: int, height: int, width: int, device="cuda"):
 
 
 def run(directory: str, N: int, B: int, batches, targets, capacity: int, spare: int, host_cache: int,
-        predictor=None, io_threads: int = 8, log=print):
-    """One training run over the walk from the persisted base store."""
+        predictor=None, io_threads: int = 8, no_tide: bool = False, no_overlap: bool = False, log=print):
+    """One training run over the walk from the persisted base store
+    (no_tide / no_overlap: the tier's ablation switches)."""
     tr = OutOfCoreTrainer(None, B, directory, capacity, spare, host_cache, n_rows=N, odirect=True,
-                          io_threads=io_threads, predictor=predictor)
+                          io_threads=io_threads, predictor=predictor, no_tide=no_tide, no_overlap=no_overlap)
     T = len(batches) - 1
     weights = None
     digests, losses, stalls, kset = [], [], [], []
@@ -140,6 +148,7 @@ def run(directory: str, N: int, B: int, batches, targets, capacity: int, spare: 
                pcie_GB_per_iter=round((st["h2d_bytes"] + st["d2h_bytes"]) / 1e9 / T, 4),
                blocks_in=st["blocks_in"], blocks_out=st["blocks_out"], readmissions=st["readmissions"],
                sync_fetches=st["sync_fetches"], host_hits=st["host_hits"], host_misses=st["host_misses"],
+               host_hit_rate=round(st["host_hits"] / max(1, st["host_hits"] + st["host_misses"]), 4),
                prefetch_issued=st["prefetch_issued"], prefetch_used=st["prefetch_used"])
     return res, [int(d.item()) for d in digests], [float(l) for l in losses]
 
