@@ -299,6 +299,19 @@ typedef struct tide_residency tide_residency;
  * Neither changes which blocks a render sees, so results are unchanged. */
 #define TIDE_TIER_NO_TIDE 4
 #define TIDE_TIER_NO_OVERLAP 8
+/* The paper's default placement and budget (Sec. 3.5), which give up the
+ * bit-identity with all-resident training:
+ * COLD_RESTART  Adam moments and steps live only while a block is resident:
+ *               an admitted block gets its parameters and zero m, v and step;
+ *               an evicted block sends back its parameters only.  The moments
+ *               held in the segment files are neither read nor maintained
+ *               (a store written this way is reopened with the same flag).
+ * BOUNDED       the budget C binds: tide_ensure_resident renders R_t and K_t's
+ *               intersection and fetches nothing (the blocks of K_t outside
+ *               R_t are counted in `skipped`).  The first batch is made
+ *               resident by a tide_stream_delta from the empty set. */
+#define TIDE_TIER_COLD_RESTART 16
+#define TIDE_TIER_BOUNDED 32
 
 typedef struct {
   const char* dir;            /* directory of the segment files (created if missing) */
@@ -324,6 +337,7 @@ typedef struct {
   double stall_seconds;                   /* host time blocked in tide_ensure_resident */
   int64_t resident;                       /* |R_t| */
   int64_t prefetch_issued, prefetch_used; /* hinted blocks read ahead / later admitted */
+  int64_t skipped;                        /* blocks of K_t left out of the render (BOUNDED) */
 } tide_tier_stats;
 
 /* Creates the tier over pool (n_slots >= cfg->capacity; block_rows = B).
@@ -363,7 +377,8 @@ tide_status tide_cull_blocks(const tide_residency* res, const tide_camera* cams,
 /* Makes every block of K (ascending ids) resident and writes the pool's
  * order array (slots of K in ascending block id) and n_order; the compute
  * stream waits for the transfers.  Host-blocking time is added to
- * stall_seconds (and returned in *stall_s if non-null). */
+ * stall_seconds (and returned in *stall_s if non-null).  With
+ * TIDE_TIER_BOUNDED the order array holds the resident blocks of K only. */
 tide_status tide_ensure_resident(tide_residency* res, const int32_t* K, int32_t n, void* compute_stream,
                                  double* stall_s);
 
@@ -404,6 +419,10 @@ tide_status tide_read_block(tide_residency* res, int64_t block, void* dst);
 tide_status tide_tier_get_stats(const tide_residency* res, tide_tier_stats* out);
 /* Host copy of the spheres (f32 [K][4]) as the tier currently sees them. */
 tide_status tide_tier_spheres(const tide_residency* res, float* out, int64_t n_blocks);
+/* The resident set R (Sec. 3.5) as the tier's host tables hold it: ascending
+ * block ids into out (capacity cap), their number in *n; TIDE_ECAPACITY if
+ * cap is too small.  Host-only (no device synchronisation). */
+tide_status tide_tier_resident(const tide_residency* res, int32_t* out, int64_t cap, int32_t* n);
 
 /* ------------------------------------------------------------------------
  * Learned prefetch predictor.  Not part of the paper's method: a small ReLU

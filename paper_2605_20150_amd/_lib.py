@@ -77,7 +77,8 @@ class tide_tier_stats(C.Structure):
                 ("readmissions", C.c_int64), ("h2d_bytes", C.c_int64), ("d2h_bytes", C.c_int64),
                 ("ssd_read_bytes", C.c_int64), ("ssd_write_bytes", C.c_int64), ("host_hits", C.c_int64),
                 ("host_misses", C.c_int64), ("sync_fetches", C.c_int64), ("stall_seconds", C.c_double),
-                ("resident", C.c_int64), ("prefetch_issued", C.c_int64), ("prefetch_used", C.c_int64)]
+                ("resident", C.c_int64), ("prefetch_issued", C.c_int64), ("prefetch_used", C.c_int64),
+                ("skipped", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -96,6 +97,8 @@ TIDE_TIER_HOST_POOL = 1
 TIDE_TIER_ODIRECT = 2
 TIDE_TIER_NO_TIDE = 4
 TIDE_TIER_NO_OVERLAP = 8
+TIDE_TIER_COLD_RESTART = 16
+TIDE_TIER_BOUNDED = 32
 
 _P = C.POINTER
 _vp = C.c_void_p
@@ -135,6 +138,7 @@ SIGNATURES = {
     "tide_read_block": (C.c_int32, [_vp, C.c_int64, _vp]),
     "tide_tier_get_stats": (C.c_int32, [_vp, _P(tide_tier_stats)]),
     "tide_tier_spheres": (C.c_int32, [_vp, _P(C.c_float), C.c_int64]),
+    "tide_tier_resident": (C.c_int32, [_vp, _P(C.c_int32), C.c_int64, _P(C.c_int32)]),
     "tide_timer_clear": (C.c_int32, []),
     "tide_mlp_param_count": (C.c_int64, [_pi32, C.c_int32]),
     "tide_mlp_ws_bytes": (C.c_size_t, [_P(tide_mlp), C.c_int32]),

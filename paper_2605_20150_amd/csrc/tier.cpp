@@ -287,6 +287,7 @@ struct tide_residency {
   int64_t host_cap = 0;
   bool host_pool = false;
   bool no_tide = false, no_overlap = false;   // ablation switches
+  bool cold_restart = false, bounded = false;  // the paper's default placement and budget
   double lambda = 0.75, gamma = 0.9, kappa = 1.32;
   size_t pbytes = 0, sbytes = 0, rec = 0;
   // caller memory
@@ -383,8 +384,26 @@ struct tide_residency {
     TIDE_HIP(hipMemcpyAsync(dst, src, n, h2d ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost, s));
     return TIDE_OK;
   }
+  tide_status zero(void* dst, size_t n, hipStream_t s) {
+    if (host_pool) {
+      std::memset(dst, 0, n);
+      return TIDE_OK;
+    }
+    TIDE_HIP(hipMemsetAsync(dst, 0, n, s));
+    return TIDE_OK;
+  }
+  // A cold-restart block moves its parameters only; its moments and steps
+  // start from zero on the GPU.
   tide_status h2d_block(int32_t slot, const char* buf, hipStream_t s) {
     tide_status r;
+    if (cold_restart) {
+      if ((r = copy(slot_ptr(0, slot), buf, pbytes, true, s)) != TIDE_OK) return r;
+      for (int a = 1; a < 3; ++a)
+        if ((r = zero(slot_ptr(a, slot), pbytes, s)) != TIDE_OK) return r;
+      if ((r = zero(slot_ptr(3, slot), sbytes, s)) != TIDE_OK) return r;
+      st.h2d_bytes += (int64_t)pbytes;
+      return TIDE_OK;
+    }
     for (int a = 0; a < 3; ++a)
       if ((r = copy(slot_ptr(a, slot), buf + a * pbytes, pbytes, true, s)) != TIDE_OK) return r;
     if ((r = copy(slot_ptr(3, slot), buf + 3 * pbytes, sbytes, true, s)) != TIDE_OK) return r;
@@ -393,8 +412,13 @@ struct tide_residency {
   }
   tide_status d2h_block(int32_t slot, char* buf, hipStream_t s) {
     tide_status r;
-    for (int a = 0; a < 3; ++a)
+    const int arrays = cold_restart ? 1 : 3;
+    for (int a = 0; a < arrays; ++a)
       if ((r = copy(buf + a * pbytes, slot_ptr(a, slot), pbytes, false, s)) != TIDE_OK) return r;
+    if (cold_restart) {
+      st.d2h_bytes += (int64_t)pbytes;
+      return TIDE_OK;
+    }
     if ((r = copy(buf + 3 * pbytes, slot_ptr(3, slot), sbytes, false, s)) != TIDE_OK) return r;
     st.d2h_bytes += (int64_t)rec;
     return TIDE_OK;
@@ -647,6 +671,8 @@ tide_status tide_residency_create(const tide_store_cfg* cfg, tide_pool* pool, fl
   r->host_pool = (cfg->flags & TIDE_TIER_HOST_POOL) != 0;
   r->no_tide = (cfg->flags & TIDE_TIER_NO_TIDE) != 0;
   r->no_overlap = (cfg->flags & TIDE_TIER_NO_OVERLAP) != 0;
+  r->cold_restart = (cfg->flags & TIDE_TIER_COLD_RESTART) != 0;
+  r->bounded = (cfg->flags & TIDE_TIER_BOUNDED) != 0;
   r->lambda = cfg->lambda_;
   r->gamma = cfg->gamma;
   r->kappa = cfg->kappa;
@@ -805,7 +831,8 @@ tide_status tide_cull_blocks(const tide_residency* res, const tide_camera* cams,
 tide_status tide_ensure_resident(tide_residency* res, const int32_t* K, int32_t n, void* compute_stream,
                                  double* stall_s) {
   TIDE_CHECK_ARG(res && (K || n == 0) && n >= 0, "null argument");
-  TIDE_CHECK_ARG(n <= res->pool->n_slots, "K_t (%d blocks) exceeds the pool's %d slots", n, res->pool->n_slots);
+  TIDE_CHECK_ARG(res->bounded || n <= res->pool->n_slots, "K_t (%d blocks) exceeds the pool's %d slots", n,
+                 res->pool->n_slots);
   hipStream_t cs = (hipStream_t)compute_stream;
   const double t0 = now_s();
   std::unique_lock<std::mutex> lk(res->mu);
@@ -825,7 +852,15 @@ tide_status tide_ensure_resident(tide_residency* res, const int32_t* K, int32_t 
     res->cv.wait(lk, [&] { return !res->pending_contains(k) || res->io_error != TIDE_OK; });
     if (res->io_error != TIDE_OK) return res->io_failed();
   }
-  // blocks of K_t that are not resident at all: synchronous fetch
+  // blocks of K_t that are not resident at all: synchronous fetch (or, under
+  // a binding budget, left out of this render)
+  if (res->bounded) {
+    std::vector<int32_t> kept;
+    for (int32_t k : need)
+      if (res->slot_of[k] >= 0) kept.push_back(k);
+    res->st.skipped += (int64_t)(need.size() - kept.size());
+    need.swap(kept);
+  }
   for (int32_t k : need) {
     if (res->slot_of[k] >= 0) continue;
     int32_t slot = res->free_slot();
@@ -1204,6 +1239,18 @@ tide_status tide_tier_get_stats(const tide_residency* res, tide_tier_stats* out)
 tide_status tide_tier_spheres(const tide_residency* res, float* out, int64_t n_blocks) {
   TIDE_CHECK_ARG(res && out && n_blocks == res->K, "bad arguments");
   std::memcpy(out, res->h_spheres.data(), 16 * res->K);
+  return TIDE_OK;
+}
+
+tide_status tide_tier_resident(const tide_residency* res, int32_t* out, int64_t cap, int32_t* n) {
+  TIDE_CHECK_ARG(res && n && (out || cap == 0) && cap >= 0, "bad arguments");
+  std::lock_guard<std::mutex> g(const_cast<tide_residency*>(res)->mu);
+  *n = (int32_t)res->R.size();
+  if ((int64_t)res->R.size() > cap) {
+    set_error("resident set of %zu blocks exceeds cap %lld", res->R.size(), (long long)cap);
+    return TIDE_ECAPACITY;
+  }
+  std::copy(res->R.begin(), res->R.end(), out);
   return TIDE_OK;
 }
 

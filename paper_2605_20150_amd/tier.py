@@ -25,9 +25,12 @@ def _ptr(a):
 class Tier:
     def __init__(self, directory: str, n_rows: int, pool: Pool, capacity: int, host_cache_blocks: int,
                  io_threads: int = 4, lam: float = 0.75, gamma: float = 0.9, kappa: float = 1.32,
-                 host_pool: bool = False, odirect: bool = False, no_tide: bool = False, no_overlap: bool = False):
+                 host_pool: bool = False, odirect: bool = False, no_tide: bool = False, no_overlap: bool = False,
+                 cold_restart: bool = False, bounded: bool = False):
         """no_tide / no_overlap: the paper's ablations (full retransmission of
-        K_{t+1}; transfers serialised with compute)."""
+        K_{t+1}; transfers serialised with compute).  cold_restart / bounded:
+        its default optimizer placement (moments only while resident) and a
+        binding budget (render R_t and K_t's intersection)."""
         self.lib = L.load()
         self.pool = pool
         self.B = pool.block_rows
@@ -46,7 +49,9 @@ class Tier:
         cfg.host_cache_blocks = int(host_cache_blocks)
         cfg.io_threads = int(io_threads)
         cfg.flags = ((L.TIDE_TIER_HOST_POOL if host_pool else 0) | (L.TIDE_TIER_ODIRECT if odirect else 0) |
-                     (L.TIDE_TIER_NO_TIDE if no_tide else 0) | (L.TIDE_TIER_NO_OVERLAP if no_overlap else 0))
+                     (L.TIDE_TIER_NO_TIDE if no_tide else 0) | (L.TIDE_TIER_NO_OVERLAP if no_overlap else 0) |
+                     (L.TIDE_TIER_COLD_RESTART if cold_restart else 0) | (L.TIDE_TIER_BOUNDED if bounded else 0))
+        self.bounded = bool(bounded)
         cfg.lambda_, cfg.gamma, cfg.kappa = float(lam), float(gamma), float(kappa)
         self.cfg = cfg
         h = C.c_void_p()
@@ -132,6 +137,13 @@ class Tier:
         out = np.zeros((self.K, 4), dtype=np.float32)
         L.check(self.lib.tide_tier_spheres(self.h, out.ctypes.data_as(C.POINTER(C.c_float)), self.K))
         return out
+
+    def resident(self) -> list[int]:
+        """R as the tier's host tables hold it (ascending block ids)."""
+        out = np.zeros(max(1, self.K), dtype=np.int32)
+        n = C.c_int32(0)
+        L.check(self.lib.tide_tier_resident(self.h, _ptr(out), self.K, C.byref(n)))
+        return out[:n.value].tolist()
 
     def resident_slots(self) -> dict:
         """block -> slot, read from the pool's slot table."""

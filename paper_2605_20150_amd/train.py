@@ -52,7 +52,7 @@ class OutOfCoreTrainer:
     def __init__(self, theta, block_rows: int, directory: str, capacity: int, spare_slots: int,
                  host_cache_blocks: int, device="cuda", kappa=1.32, io_threads=4, predictor=None,
                  n_rows: int | None = None, odirect: bool = False, no_tide: bool = False,
-                 no_overlap: bool = False):
+                 no_overlap: bool = False, cold_restart: bool = False, bounded: bool = False):
         """theta: the [N][59] table to lay out in a new store, or None to
         reopen the store already in ``directory`` (n_rows rows, from its
         persisted Index)."""
@@ -61,7 +61,8 @@ class OutOfCoreTrainer:
         self.B = block_rows
         self.pool = Pool.empty(capacity + spare_slots, block_rows, device)
         self.tier = Tier(directory, self.N, self.pool, capacity, host_cache_blocks, io_threads=io_threads,
-                         kappa=kappa, odirect=odirect, no_tide=no_tide, no_overlap=no_overlap)
+                         kappa=kappa, odirect=odirect, no_tide=no_tide, no_overlap=no_overlap,
+                         cold_restart=cold_restart, bounded=bounded)
         if theta is not None:
             for k in range(self.tier.K):
                 rows = theta[k * block_rows:(k + 1) * block_rows]
@@ -74,15 +75,21 @@ class OutOfCoreTrainer:
         self.side = torch.cuda.Stream(device=device)
         self.predictor = predictor
         self.stall = 0.0
-        self.k_sets = []
+        self.k_sets = []        # K_t per iteration
+        self.r_sets = []        # R_t per iteration (after ensure_resident)
 
     def iterate(self, cams, target, next_cams=None):
         t = self.tier
         cs = torch.cuda.current_stream().cuda_stream
         t.sync_bounds()
-        K = sorted(set(int(x) for s in t.cull(cams) for x in s))
+        per_cam = t.cull(cams)
+        K = sorted(set(int(x) for s in per_cam for x in s))
         self.k_sets.append(K)
+        if t.bounded and not self.r_sets:
+            # under a binding budget the first batch comes in by a delta from the empty set
+            t.stream_delta(per_cam, self.side.cuda_stream)
         self.stall += t.ensure_resident(K, cs)
+        self.r_sets.append(t.resident())
         hinting = self.predictor is not None and next_cams is not None
         if hinting:
             self.predictor.launch(list(cams) + list(next_cams))   # its own stream: overlaps the compute

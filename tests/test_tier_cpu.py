@@ -299,3 +299,76 @@ def test_host_cache_pinned_by_the_iteration_in_flight_is_an_error(tmp_path):
     with pytest.raises(RuntimeError, match="too small"):
         t.stream_delta([[5, 6, 7, 8, 9]])
     t.close()
+
+
+def test_cold_restart_moves_parameters_only_and_zeroes_the_moments(tmp_path):
+    """Sec. 3.5's default placement: a block that leaves and comes back keeps
+    its trained parameters and restarts m, v and its steps from zero; only
+    parameters cross PCIe."""
+    th = scene()
+    t, pool = build(tmp_path, th, n_slots=4, capacity=4, cache=6, cold_restart=True)
+    pbytes = 59 * B * 4
+    t.ensure_resident([0, 1])
+    s = t.resident_slots()
+    for k in (0, 1):
+        pool.params[s[k]] += 0.5
+        pool.exp_avg[s[k]] += 1.0
+        pool.exp_avg_sq[s[k]] += 2.0
+        pool.step[s[k]] += 3
+        t.dirty[k] = 1
+    trained = {k: pool.params[s[k]].numpy().copy() for k in (0, 1)}
+    t.end_iteration()
+    t.stream_delta([[2, 3, 4, 5]])          # 0 and 1 leave
+    t.sync_bounds()
+    t.ensure_resident([2, 3, 4, 5])
+    assert 0 not in t.resident() and 1 not in t.resident()
+    t.end_iteration()
+    t.stream_delta([[0, 1]])                # and come back
+    t.sync_bounds()
+    t.ensure_resident([0, 1])
+    s = t.resident_slots()
+    for k in (0, 1):
+        assert np.array_equal(pool.params[s[k]].numpy(), trained[k])
+        assert not pool.exp_avg[s[k]].any() and not pool.exp_avg_sq[s[k]].any() and not pool.step[s[k]].any()
+    st = t.stats()
+    assert st["h2d_bytes"] == pbytes * (st["blocks_in"] + st["sync_fetches"])
+    assert st["d2h_bytes"] % pbytes == 0 and st["d2h_bytes"] > 0
+    t.close()
+
+
+def test_bounded_budget_follows_alg1_and_renders_the_resident_part(tmp_path):
+    """A budget C below |K_{t+1}|: the camera-balanced Top-C decisions match
+    the oracle, the render order holds K_t's resident blocks only, nothing is
+    fetched outside the deltas, and the skipped blocks are counted."""
+    th = scene()
+    C_ = 5
+    t, pool = build(tmp_path, th, n_slots=C_, capacity=C_, cache=8, bounded=True)
+    rng = np.random.default_rng(46)
+    sets = []
+    for i in range(25):
+        sets.append([sorted(set(((i // 2 + j * 3 + rng.integers(0, 5, size=3)) % t.K).tolist())) for j in range(2)])
+    age = np.full(t.K, 1e9)
+    R, Kprev = [], []
+    skipped = 0
+    for i, cams in enumerate(sets):
+        Kt = sorted(set(x for c in cams for x in c))
+        Rn, sp_ref, sm_ref, age, _ = oracle.alg1(R, Kprev, cams, age, 0.75, 0.9, C_)
+        if i == 0:
+            sp, sm = t.stream_delta(cams)
+        assert sorted(sp.tolist()) == sp_ref and sorted(sm.tolist()) == sm_ref, i
+        t.ensure_resident(Kt)
+        R = t.resident()
+        assert R == Rn.tolist() and len(R) <= C_, i
+        rendered = [k for k in Kt if k in set(R)]
+        order = pool.order[:pool.n_order].numpy().tolist()
+        slots = t.resident_slots()
+        assert order == [slots[k] for k in rendered], i
+        skipped += len(Kt) - len(rendered)
+        t.end_iteration()
+        if i + 1 < len(sets):
+            sp, sm = t.stream_delta(sets[i + 1])
+        t.sync_bounds()
+        Kprev = [k for k in Kt if k in set(R)]
+    st = t.stats()
+    assert st["sync_fetches"] == 0 and st["skipped"] == skipped and skipped > 0
+    t.close()
