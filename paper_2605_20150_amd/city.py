@@ -110,12 +110,66 @@ def targets_for(batches, seed: int, height: int, width: int, device="cuda"):
     return out
 
 
+def churn_stats(r_sets, k_sets) -> dict:
+    """Residency churn of a run (the paper's churn table, App. B), from R_t
+    and K_t per iteration:
+      eviction rate      mean over t of |R_t minus R_{t+1}| / |R_t|;
+      re-admission rate  mean over t of the blocks of R_{t+1} minus R_t that
+                         had been resident before, over |R_{t+1}|;
+      cold-restarted updates / updates   an update is a block rendered at t
+                         (in K_t and R_t); it is cold-restarted when it is the
+                         first update of a residency interval other than the
+                         block's first;
+      mean resident streak   mean length of the maximal runs of consecutive
+                         iterations a block stays resident (runs cut by the
+                         walk's end included)."""
+    T = len(r_sets)
+    Rs = [set(r) for r in r_sets]
+    ev, re = [], []
+    seen = set(Rs[0]) if T else set()
+    for t in range(T - 1):
+        if Rs[t]:
+            ev.append(len(Rs[t] - Rs[t + 1]) / len(Rs[t]))
+        new = Rs[t + 1] - Rs[t]
+        if Rs[t + 1]:
+            re.append(len(new & seen) / len(Rs[t + 1]))
+        seen |= Rs[t + 1]
+    updates = cold = 0
+    interval_updated = {}       # block -> updated in its current interval
+    intervals = {}              # block -> residency intervals begun so far
+    streaks, open_run = [], {}
+    for t in range(T):
+        for k in Rs[t]:
+            if t == 0 or k not in Rs[t - 1]:
+                intervals[k] = intervals.get(k, 0) + 1
+                interval_updated[k] = False
+                open_run[k] = 0
+            open_run[k] += 1
+        if t > 0:
+            for k in Rs[t - 1] - Rs[t]:
+                streaks.append(open_run.pop(k))
+        for k in set(k_sets[t]) & Rs[t]:
+            updates += 1
+            if not interval_updated[k]:
+                interval_updated[k] = True
+                cold += intervals[k] > 1
+    streaks.extend(open_run.values())
+    return dict(eviction_rate=round(float(np.mean(ev)) if ev else 0.0, 4),
+                readmission_rate=round(float(np.mean(re)) if re else 0.0, 4),
+                cold_restarted_update_ratio=round(cold / max(1, updates), 4),
+                mean_resident_streak=round(float(np.mean(streaks)) if streaks else 0.0, 2),
+                block_updates=updates)
+
+
 def run(directory: str, N: int, B: int, batches, targets, capacity: int, spare: int, host_cache: int,
-        predictor=None, io_threads: int = 8, no_tide: bool = False, no_overlap: bool = False, log=print):
+        predictor=None, io_threads: int = 8, no_tide: bool = False, no_overlap: bool = False,
+        cold_restart: bool = False, bounded: bool = False, log=print):
     """One training run over the walk from the persisted base store
-    (no_tide / no_overlap: the tier's ablation switches)."""
+    (no_tide / no_overlap: the tier's ablation switches; cold_restart /
+    bounded: the paper's default optimizer placement and a binding budget)."""
     tr = OutOfCoreTrainer(None, B, directory, capacity, spare, host_cache, n_rows=N, odirect=True,
-                          io_threads=io_threads, predictor=predictor, no_tide=no_tide, no_overlap=no_overlap)
+                          io_threads=io_threads, predictor=predictor, no_tide=no_tide, no_overlap=no_overlap,
+                          cold_restart=cold_restart, bounded=bounded)
     T = len(batches) - 1
     weights = None
     digests, losses, stalls, kset = [], [], [], []
@@ -149,7 +203,10 @@ def run(directory: str, N: int, B: int, batches, targets, capacity: int, spare: 
                blocks_in=st["blocks_in"], blocks_out=st["blocks_out"], readmissions=st["readmissions"],
                sync_fetches=st["sync_fetches"], host_hits=st["host_hits"], host_misses=st["host_misses"],
                host_hit_rate=round(st["host_hits"] / max(1, st["host_hits"] + st["host_misses"]), 4),
-               prefetch_issued=st["prefetch_issued"], prefetch_used=st["prefetch_used"])
+               prefetch_issued=st["prefetch_issued"], prefetch_used=st["prefetch_used"],
+               skipped_blocks=st["skipped"],
+               rendered_fraction=round(1.0 - st["skipped"] / max(1, sum(len(k) for k in tr.k_sets)), 4),
+               churn=churn_stats(tr.r_sets, tr.k_sets))
     return res, [int(d.item()) for d in digests], [float(l) for l in losses]
 
 

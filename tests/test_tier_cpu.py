@@ -372,3 +372,19 @@ def test_bounded_budget_follows_alg1_and_renders_the_resident_part(tmp_path):
     st = t.stats()
     assert st["sync_fetches"] == 0 and st["skipped"] == skipped and skipped > 0
     t.close()
+
+
+def test_churn_statistics_on_a_hand_counted_walk():
+    """Block 1 leaves at t = 2 and comes back at t = 3: eviction rates
+    0, 1/2, 0; re-admission rates 0, 0, 1/2; seven block updates of which the
+    first after the return is cold-restarted; streaks 4 (block 0), 2 and 1
+    (block 1)."""
+    from paper_2605_20150_amd.city import churn_stats
+    r = [[0, 1], [0, 1], [0], [0, 1]]
+    c = churn_stats(r, r)
+    assert c["eviction_rate"] == round(0.5 / 3, 4) and c["readmission_rate"] == round(0.5 / 3, 4)
+    assert c["block_updates"] == 7 and c["cold_restarted_update_ratio"] == round(1 / 7, 4)
+    assert c["mean_resident_streak"] == round(7 / 3, 2)
+    # a block resident but outside K_t is not updated; first admissions are not restarts
+    c = churn_stats([[0, 1], [0, 2]], [[0], [0, 2]])
+    assert c["block_updates"] == 3 and c["cold_restarted_update_ratio"] == 0.0
