@@ -357,6 +357,22 @@ tide_status tide_residency_destroy(tide_residency* res);
  * Block k of the layout is then rows perm[kB .. (k+1)B). */
 tide_status tide_morton_order(const float* xyz, int64_t n, int64_t stride, int64_t* perm);
 
+/* Training-view order (Sec. 3.5 and App. A: a clustered travelling-salesperson
+ * order of the camera poses, so that consecutive batches share blocks).
+ * perm [n] receives a permutation of the n cameras:
+ *   d(i, j) = |p_i - p_j| + dir_weight |f_i - f_j| (p = -R^T t the centre,
+ *   f = R's third row the viewing direction, dir_weight in metres);
+ *   ceil(n / cluster_size) clusters of the centres (farthest-point seeds
+ *   from camera 0, Lloyd iterations until stable, at most 100);
+ *   the non-empty clusters along an open path over their centroids from
+ *   camera 0's cluster (nearest neighbour, then 2-opt);
+ *   inside each, an open path with d entered at the camera nearest the
+ *   previous cluster's last (camera 0 first), nearest neighbour then 2-opt.
+ * Ties go to the lower index; a 2-opt move must gain more than 1e-9.
+ * Deterministic; host only. */
+tide_status tide_view_order(const tide_camera* cams, int64_t n, int32_t cluster_size, double dir_weight,
+                            int32_t* perm);
+
 /* Layout build (Sec. 3.3, 4.1): writes block k's record to the base segment
  * with zero moments and steps.  params: host f32 [59][rows of block k].
  * Computes the block's sphere: c_k = mean of the member means (fixed),

@@ -4,7 +4,8 @@ Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
 import this package.  The product library never loads it and shares no code
 with it.  This module is ctypes glue: it marshals numpy arrays into the C++
 oracle (``raster_oracle.cpp``, ``tier_oracle.cpp``, ``mlp_oracle.cpp``) and
-holds none of the arithmetic itself.
+holds none of the arithmetic itself.  ``ordering.py`` is the one oracle
+written in Python: the training-view order.
 """
 from __future__ import annotations
 

@@ -150,6 +150,7 @@ SIGNATURES = {
     "tide_pose_features": (C.c_int32, [_P(tide_camera), C.c_int32, C.c_double, _P(C.c_float)]),
     "tide_cull_bits": (C.c_int32, [_P(C.c_float), C.c_int64, _P(tide_camera), C.c_int32, _P(C.c_uint32), C.c_int64]),
     "tide_morton_order": (C.c_int32, [_P(C.c_float), C.c_int64, C.c_int64, _P(C.c_int64)]),
+    "tide_view_order": (C.c_int32, [_P(tide_camera), C.c_int64, C.c_int32, C.c_double, _P(C.c_int32)]),
     "tide_block_sphere": (C.c_int32, [_P(C.c_float), C.c_int64, C.c_int64, C.c_double, _P(C.c_float)]),
 }
 

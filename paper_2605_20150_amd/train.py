@@ -111,3 +111,16 @@ class OutOfCoreTrainer:
             rows = min(self.B, self.N - k * self.B)
             out[k * self.B:k * self.B + rows] = r["params"][:, :rows].T
         return out
+
+
+def view_order(cams, cluster_size: int = 16, dir_weight: float = 10.0) -> np.ndarray:
+    """Clustered travelling-salesperson order of the training views (Sec. 3.5,
+    App. A), from the library: a permutation of range(len(cams))."""
+    import ctypes as C
+    from . import _lib as L
+    n = len(cams)
+    perm = np.zeros(max(1, n), dtype=np.int32)
+    arr = L.camera_array(cams) if n else None
+    L.check(L.load().tide_view_order(arr, n, int(cluster_size), float(dir_weight),
+                                     perm.ctypes.data_as(C.POINTER(C.c_int32))))
+    return perm[:n].copy()
