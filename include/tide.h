@@ -357,6 +357,18 @@ tide_status tide_residency_destroy(tide_residency* res);
  * Block k of the layout is then rows perm[kB .. (k+1)B). */
 tide_status tide_morton_order(const float* xyz, int64_t n, int64_t stride, int64_t* perm);
 
+/* Out-of-core layout build (Sec. 3.3, 4.1) of a new store: table_path holds
+ * the N rows of the tier as f32 [N][59], row-major (N and B from the tier's
+ * configuration).  Pass 1 reads the centres' bounding box; pass 2 sorts runs
+ * of run_rows rows by (Morton code, row), with tide_morton_order's
+ * quantisation, into files under tmp_dir; pass 3 merges the runs and writes
+ * every block through tide_store_put_block, then tide_store_finalize.  The
+ * block contents equal those of tide_morton_order's permutation.  Host
+ * memory is about 490 B per run row; at most 512 runs; the run files are
+ * removed on return.  TIDE_EINVAL if the file size is not N * 236 B or a
+ * centre is not finite; TIDE_EIO on a read or write error. */
+tide_status tide_layout_build(tide_residency* res, const char* table_path, const char* tmp_dir, int64_t run_rows);
+
 /* Training-view order (Sec. 3.5 and App. A: a clustered travelling-salesperson
  * order of the camera poses, so that consecutive batches share blocks).
  * perm [n] receives a permutation of the n cameras:
@@ -426,6 +438,15 @@ tide_status tide_prefetch_hint(tide_residency* res, const int32_t* blocks, int32
  * block, flush of every dirty host entry to a patch segment, fsync, then the
  * Index is persisted atomically. Blocks until done. */
 tide_status tide_checkpoint(tide_residency* res);
+
+/* Compaction (Sec. 3.4, off the training path): a checkpoint, then the
+ * newest version of every block is rewritten in block order into a new base
+ * segment that replaces the old by rename; the Index is persisted pointing
+ * there (versions kept) and the patch segments are deleted.  Crash-safe at
+ * every step (the old Index stays valid until the new one is in place).
+ * Called between iterations (after tide_residency_sync_bounds); blocks until
+ * done. */
+tide_status tide_store_compact(tide_residency* res);
 
 /* Reads block k's newest record (host, rec_bytes) through Index: from the
  * GPU if resident (blocking copy), else the host cache, else the SSD. */

@@ -151,6 +151,8 @@ SIGNATURES = {
     "tide_cull_bits": (C.c_int32, [_P(C.c_float), C.c_int64, _P(tide_camera), C.c_int32, _P(C.c_uint32), C.c_int64]),
     "tide_morton_order": (C.c_int32, [_P(C.c_float), C.c_int64, C.c_int64, _P(C.c_int64)]),
     "tide_view_order": (C.c_int32, [_P(tide_camera), C.c_int64, C.c_int32, C.c_double, _P(C.c_int32)]),
+    "tide_layout_build": (C.c_int32, [_vp, C.c_char_p, C.c_char_p, C.c_int64]),
+    "tide_store_compact": (C.c_int32, [_vp]),
     "tide_block_sphere": (C.c_int32, [_P(C.c_float), C.c_int64, C.c_int64, C.c_double, _P(C.c_float)]),
 }
 

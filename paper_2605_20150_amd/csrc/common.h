@@ -17,6 +17,8 @@ void set_error(const char* fmt, ...);
 tide_status hip_fail(hipError_t e, const char* what);
 // Records the events armed for `kernel` (tide_timer_arm) on `st`.
 void timer_mark(const char* kernel, hipStream_t st, bool begin);
+// N (rows) and B (rows per block) of a tier.
+void residency_shape(const tide_residency* res, int64_t* n_rows, int32_t* block_rows);
 
 #define TIDE_CHECK_ARG(cond, ...)          \
   do {                                     \

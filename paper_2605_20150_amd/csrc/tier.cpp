@@ -221,6 +221,63 @@ class LogStore {
     return new_patch();   // later appends never touch the segments the index refers to
   }
 
+  // Compaction (Sec. 3.4; off the training path): the current version of
+  // every block is rewritten in block order into a new base segment, which
+  // replaces base.seg by rename; then the Index (every entry in the new base,
+  // versions kept) is persisted and the patch segments are deleted.  The
+  // caller has persisted every newest version first (a checkpoint), so a
+  // crash between the rename and the new Index leaves the old Index reading
+  // the same versions: its base entries name records the rename did not
+  // change, its patch entries patches that still exist.
+  tide_status compact() {
+    const std::string tmp = dir + "/base.compact";
+    ::unlink(tmp.c_str());
+    int fd = ::open(tmp.c_str(), O_RDWR | O_CREAT | O_TRUNC | (odirect ? O_DIRECT : 0), 0644);
+    if (fd < 0) return fail("cannot create the compacted base");
+    void* raw = nullptr;
+    if (posix_memalign(&raw, 4096, rec) != 0) {
+      ::close(fd);
+      return fail("out of host memory for compaction");
+    }
+    std::unique_ptr<char, void (*)(void*)> buf((char*)raw, std::free);
+    for (int64_t k = 0; k < K; ++k) {
+      tide_status r = read(k, buf.get());
+      if (r != TIDE_OK) {
+        ::close(fd);
+        return r;
+      }
+      size_t put = 0;
+      while (put < rec) {
+        const ssize_t w = ::pwrite(fd, buf.get() + put, rec - put, (off_t)(k * (int64_t)rec + put));
+        if (w <= 0) {
+          ::close(fd);
+          return fail("compacted base write failed");
+        }
+        put += (size_t)w;
+      }
+    }
+    const bool synced = ::fsync(fd) == 0;
+    ::close(fd);
+    if (!synced || ::rename(tmp.c_str(), seg_name(0).c_str()) != 0) return fail("compacted base commit failed");
+    int dfd = ::open(dir.c_str(), O_RDONLY);
+    if (dfd >= 0) { ::fsync(dfd); ::close(dfd); }
+    const int old_nseg = (int)fds.size();
+    for (int f : fds)
+      if (f >= 0) ::close(f);
+    fds.clear();
+    const int base = open_seg(0, false);
+    if (base < 0) return fail("cannot reopen the compacted base");
+    fds.push_back(base);
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      for (int64_t k = 0; k < K; ++k) index[k] = IndexEntry{0, 0, (int64_t)(k * rec), (int64_t)rec, index[k].version};
+    }
+    tide_status r = persist();
+    if (r != TIDE_OK) return r;
+    for (int id = 1; id < old_nseg; ++id) ::unlink(seg_name(id).c_str());
+    return new_patch();
+  }
+
   static tide_status fail(const char* what) {
     set_error("%s (%s)", what, std::strerror(errno));
     return TIDE_EIO;
@@ -1191,6 +1248,22 @@ tide_status tide_checkpoint(tide_residency* res) {
   return write_sphere_file(res);
 }
 
+tide_status tide_store_compact(tide_residency* res) {
+  TIDE_CHECK_ARG(res, "null argument");
+  tide_status r = tide_checkpoint(res);
+  if (r != TIDE_OK) return r;
+  std::unique_lock<std::mutex> lk(res->mu);
+  // no read or write-back may touch the segments meanwhile
+  res->cv.wait(lk, [&] {
+    if (res->io_error != TIDE_OK) return true;
+    for (const auto& e : res->ent)
+      if (e.loading || e.flushing || e.dirty) return false;
+    return true;
+  });
+  if (res->io_error != TIDE_OK) return res->io_failed();
+  return res->store.compact();
+}
+
 tide_status tide_read_block(tide_residency* res, int64_t block, void* dst) {
   TIDE_CHECK_ARG(res && dst && block >= 0 && block < res->K, "bad arguments");
   std::unique_lock<std::mutex> lk(res->mu);
@@ -1255,3 +1328,8 @@ tide_status tide_tier_resident(const tide_residency* res, int32_t* out, int64_t 
 }
 
 }  // extern "C"
+
+void tide::residency_shape(const tide_residency* res, int64_t* n_rows, int32_t* block_rows) {
+  *n_rows = res->N;
+  *block_rows = res->B;
+}

@@ -119,6 +119,15 @@ class Tier:
     def checkpoint(self):
         L.check(self.lib.tide_checkpoint(self.h))
 
+    def compact(self):
+        """Merge the patch segments into a new base segment (checkpoint first)."""
+        L.check(self.lib.tide_store_compact(self.h))
+
+    def layout_build(self, table_path: str, tmp_dir: str, run_rows: int):
+        """Out-of-core Morton layout of a new store from an f32 [N][59] table
+        file; the store is finalized on return."""
+        L.check(self.lib.tide_layout_build(self.h, table_path.encode(), tmp_dir.encode(), int(run_rows)))
+
     # ------------------------------------------------------------ inspection
     def read_block(self, k: int) -> dict:
         buf = np.zeros(self.rec_bytes, dtype=np.uint8)

@@ -388,3 +388,92 @@ def test_churn_statistics_on_a_hand_counted_walk():
     # a block resident but outside K_t is not updated; first admissions are not restarts
     c = churn_stats([[0, 1], [0, 2]], [[0], [0, 2]])
     assert c["block_updates"] == 3 and c["cold_restarted_update_ratio"] == 0.0
+
+
+def _table(tmp_path, n=3001, seed=47):
+    th = synth.dense_scene(n, seed, extent=3.0, logscale_mu=-3.0).astype(np.float32)
+    th[100:110, :3] = th[5, :3]             # equal centres: ties keep row order
+    path = tmp_path / "table.f32"
+    th.tofile(path)
+    return th, str(path)
+
+
+@pytest.mark.parametrize("run_rows", [3001, 700, 64])
+def test_out_of_core_layout_equals_the_oracle_morton_blocks(tmp_path, run_rows):
+    """Sec. 3.3's layout from a table file through sorted runs on disk and a
+    k-way merge: every block holds the rows of the oracle's stable Morton
+    order (one run, several, many; a ragged last block), the spheres are the
+    oracle's, the run files are gone and the store reopens."""
+    th, path = _table(tmp_path)
+    N = th.shape[0]
+    t = Tier(str(tmp_path / "store"), N, Pool.empty(4, B, "cpu"), 4, 4, host_pool=True, kappa=1.32)
+    t.layout_build(path, str(tmp_path), run_rows)
+    ref = th[oracle.morton_order(th[:, :3])]
+    assert t.K == 12
+    for k in range(t.K):
+        rows = ref[k * B:(k + 1) * B]
+        assert np.array_equal(t.read_block(k)["params"][:, :len(rows)], rows.T), k
+    sp = oracle.block_spheres(ref.astype(np.float64), B, 1.32)
+    got = t.host_spheres()
+    assert np.allclose(got[:, :3], sp[:, :3], rtol=1e-6, atol=1e-6) and (got[:, 3] >= sp[:, 3]).all()
+    assert not [p for p in os.listdir(tmp_path) if p.startswith("tide_run_")]
+    t.close()
+    t2 = Tier(str(tmp_path / "store"), N, Pool.empty(4, B, "cpu"), 4, 4, host_pool=True)
+    t2.open()
+    assert np.array_equal(t2.read_block(11)["params"][:, :N - 11 * B], ref[11 * B:].T)
+    t2.close()
+
+
+def test_out_of_core_layout_rejects_bad_inputs(tmp_path):
+    th, path = _table(tmp_path)
+    t = Tier(str(tmp_path / "s1"), th.shape[0] + 1, Pool.empty(4, B, "cpu"), 4, 4, host_pool=True)
+    with pytest.raises(RuntimeError, match="expected"):
+        t.layout_build(path, str(tmp_path), 700)       # file holds one row fewer than N
+    t.close()
+    t = Tier(str(tmp_path / "s2"), th.shape[0], Pool.empty(4, B, "cpu"), 4, 4, host_pool=True)
+    with pytest.raises(RuntimeError, match="runs"):
+        t.layout_build(path, str(tmp_path), 5)         # 601 runs: more than 512 open files
+    t.close()
+
+
+def test_compaction_merges_the_patches_and_keeps_the_newest_versions(tmp_path):
+    """Sec. 3.4's optional compaction: after write-backs spread blocks over
+    patch segments, compaction leaves one base segment holding every block's
+    newest version; training continues (new patches) and a reopened store
+    reads the newest versions."""
+    th = scene()
+    t, pool = build(tmp_path, th, n_slots=4, capacity=4, cache=4)
+    rng = np.random.default_rng(48)
+    truth = {k: t.read_block(k)["params"].copy() for k in range(t.K)}
+
+    def train(iters):
+        for _ in range(iters):
+            Kt = sorted(rng.choice(t.K, 2, replace=False).tolist())
+            t.ensure_resident(Kt)
+            slots = t.resident_slots()
+            for k in Kt:
+                assert np.array_equal(pool.params[slots[k]].numpy(), truth[k])
+                pool.params[slots[k]] += 0.25
+                t.dirty[k] = 1
+                truth[k] = pool.params[slots[k]].numpy().copy()
+            t.end_iteration()
+            t.stream_delta([sorted(rng.choice(t.K, 2, replace=False).tolist())])
+            t.sync_bounds()
+
+    d = tmp_path / "store"
+    train(25)
+    t.checkpoint()
+    assert sum(os.path.getsize(d / p) for p in os.listdir(d) if p.startswith("patch_")) > 0
+    t.compact()
+    assert sorted(p for p in os.listdir(d) if p.endswith(".seg")) == ["base.seg", "patch_000001.seg"]
+    assert os.path.getsize(d / "patch_000001.seg") == 0
+    for k in range(t.K):
+        assert np.array_equal(t.read_block(k)["params"], truth[k]), k
+    train(10)
+    t.checkpoint()
+    t.close()
+    t2 = Tier(str(d), th.shape[0], Pool.empty(4, B, "cpu"), 4, 4, host_pool=True)
+    t2.open()
+    for k in range(t2.K):
+        assert np.array_equal(t2.read_block(k)["params"], truth[k]), k
+    t2.close()
