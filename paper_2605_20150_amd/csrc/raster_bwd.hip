@@ -100,16 +100,31 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
       // accumulated as moments of dp over dy and finished once per lane:
       // d/dA = dx^2 S0, d/dB = dx S1, d/dC = S2 (times -1/2, -1, -1/2 below),
       // d/du = A dx S0 + B S1, d/dv = B dx S0 + C S1.
-      T S0 = 0, S1 = 0, S2 = 0, a_o = 0, a_r = 0, a_g = 0, a_b = 0;
+      // G first: an entry no pixel of the tile takes (pass and before the
+      // pixel's last contributor) leaves every pixel's state and the entry's
+      // partial at zero, so the wave skips the rest.
+      T Gq[4];
+      bool okq[4];
       bool hit = false;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
+        T araw, alpha;
+        const bool pass = entry_alpha<T>(adx2, bdx, Ch, op, fyp[q] - v, Gq[q], araw, alpha);
+        okq[q] = pass && pos < lst[q];
+        hit = hit || okq[q];
+      }
+      const bool any_hit = __ballot(hit) != 0;
+      if (lane == 0) s_hit[k] = any_hit ? 1u : 0u;
+      if (!any_hit) continue;
+      T S0 = 0, S1 = 0, S2 = 0, a_o = 0, a_r = 0, a_g = 0, a_b = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
         const T dy = fyp[q] - v;
-        T G, araw, alpha;
-        const bool pass = entry_alpha<T>(adx2, bdx, Ch, op, dy, G, araw, alpha);
-        const bool ok = pass && pos < lst[q];
+        const T G = Gq[q];
+        const T araw = op * G;
+        const T alpha = araw < (T)0.99 ? araw : (T)0.99;
+        const bool ok = okq[q];
         const bool okg = ok && araw < (T)0.99;   // alpha clamped at 0.99: no input dependence
-        hit = hit || ok;
         const T a_ok = ok ? alpha : (T)0;
         const T G_ok = okg ? G : (T)0;
         const T r_ok = okg ? araw : (T)0;
@@ -128,9 +143,6 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
       T a_u = s_A[k] * dx * S0 + B * S1;
       T a_v = Bdx * S0 + C * S1;
       T a_A = dx2 * S0, a_B = dx * S1, a_C = S2;
-      const bool any_hit = __ballot(hit) != 0;
-      if (lane == 0) s_hit[k] = any_hit ? 1u : 0u;
-      if (!any_hit) continue;
       a_u = row_sum_to_15(a_u); a_v = row_sum_to_15(a_v); a_A = row_sum_to_15(a_A);
       a_B = row_sum_to_15(a_B); a_C = row_sum_to_15(a_C); a_o = row_sum_to_15(a_o);
       a_r = row_sum_to_15(a_r); a_g = row_sum_to_15(a_g); a_b = row_sum_to_15(a_b);
