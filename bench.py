@@ -290,9 +290,10 @@ def order_main(args):
     one pass in batches of 4, in the order the walks captured them, in a
     shuffled order and in the library's clustered travelling-salesperson
     order.  Every view keeps its own target, so the three runs optimise the
-    same objective; only the schedule differs.  Blocks of 16384 Gaussians
-    and a host cache that holds the whole store keep the shuffled run's
-    traffic within a few minutes."""
+    same objective; only the schedule differs.  The capacity is the smallest
+    all three orders can run with.  Blocks of 16384 Gaussians and a host
+    cache that holds the whole store keep the shuffled run within a few
+    minutes."""
     import shutil
 
     import numpy as np
@@ -324,7 +325,9 @@ def order_main(args):
         batches[name] = (b + [b[0]], [torch.cat([per_view[i] for i in o[4 * t:4 * t + 4]]) for t in range(n // 4)]
                          + [torch.cat([per_view[i] for i in o[0:4]])])
         sizes[name] = [len(P.bits_to_ids(P.cull_bits(spheres, x, words), K)) for x in b]
-    capacity = 2 * max(max(v) for v in sizes.values()) + 8
+    # the smallest capacity every order can run with: the shuffled order
+    # then churns while the ordered ones keep their working sets
+    capacity = max(max(v) for v in sizes.values()) + 8
     log(f"order city: {n_blocks} blocks of {B} over {extent:.0f} m, {n} views, capacity {capacity}, host cache "
         f"{n_blocks} blocks; |K_t| per order: " + ", ".join(f"{k} {np.mean(v):.0f}" for k, v in sizes.items()))
     runs = {}

@@ -205,6 +205,28 @@ def test_empty_and_degenerate_inputs():
     assert (fr.image[0, 1] == 0.5).all() and (fr.last == 0).all() and (fr.t_final == 1).all()
 
 
+def test_empty_render_order():
+    """No block in the render order (n_order = 0: a binding budget that keeps
+    none of K_t): the image is the background, nothing is active, and the
+    backward and Adam change nothing."""
+    say("case: render order of zero blocks")
+    theta, cams, tgt = synth.tiny_workload()
+    rast = Rasterizer("cuda")
+    pool = Pool.from_dense(torch.tensor(theta, device="cuda"), 4096)
+    before = pool.params.clone()
+    pool.n_order = 0
+    proj, bins, fr = rast.forward(pool, cams, (0.25, 0.5, 0.75))
+    assert bins.n_vis == 0 and bins.n_inst == 0
+    assert (fr.image[0, 0] == 0.25).all() and (fr.image[0, 2] == 0.75).all() and (fr.t_final == 1).all()
+    target = torch.zeros_like(fr.image)
+    loss, dimg = rast.loss(fr.image, target)
+    g = rast.backward(pool, cams, proj, bins, fr, dimg)
+    rast.adam(pool, proj, g, adam_cfg(LR59))
+    torch.cuda.synchronize()
+    assert int(proj.n_active.item()) == 0
+    assert torch.equal(pool.params, before)
+
+
 # ---------------------------------------------------------------- loss
 def test_loss_matches_oracle():
     say("case: loss on 2 views of 70x53")

@@ -14,8 +14,8 @@ import pytest
 import torch
 
 from paper_2605_20150_amd import synth
-from paper_2605_20150_amd.raster import Pool, Rasterizer
-from paper_2605_20150_amd.train import OutOfCoreTrainer, ResidentTrainer, image_digest
+from paper_2605_20150_amd.raster import LR59, Pool, Rasterizer, adam_cfg
+from paper_2605_20150_amd.train import OutOfCoreTrainer, ResidentTrainer, image_digest, step
 
 pytestmark = pytest.mark.gpu
 
@@ -47,12 +47,27 @@ def walk(n_iters, V=4):
     return [cams[V * t:V * t + V] for t in range(n_iters + 1)]
 
 
-def test_out_of_core_equals_all_resident(tmp_path):
+def walk_back(n_iters, V=4):
+    """Forward along the strip for half the iterations, then back (still
+    looking ahead): blocks left behind come back into view."""
+    out = []
+    for t in range(n_iters + 1):
+        s = t if t <= n_iters // 2 else n_iters - t
+        out.append([synth.look_at((-20 + 10.0 * s + 2.0 * v, 0.0, 20.0), (10 + 10.0 * s + 2.0 * v, 0.0, 0.0),
+                                  (0, 0, 1), 320, 180, synth.focal_for_hfov(320, 60), z_far=60.0)
+                    for v in range(V)])
+    return out
+
+
+@pytest.mark.parametrize("flags", [{}, {"no_tide": True}, {"no_overlap": True}])
+def test_out_of_core_equals_all_resident(tmp_path, flags):
+    """Also with the ablation switches: they change the schedule, not the
+    result (Sec. 4.4)."""
     theta = strip_scene()
     B = 4096
     T = 36
     batches = walk(T)
-    say(f"case: {theta.shape[0]} Gaussians in {(theta.shape[0] + B - 1) // B} blocks, {T} iterations")
+    say(f"case: {theta.shape[0]} Gaussians in {(theta.shape[0] + B - 1) // B} blocks, {T} iterations, {flags}")
     # targets from perturbed parameters, rendered by the GPU
     rast = Rasterizer("cuda")
     tpool = Pool.from_dense(torch.tensor(synth.perturbed(theta, 0.05, 51), device="cuda"), B)
@@ -61,7 +76,8 @@ def test_out_of_core_equals_all_resident(tmp_path):
         _, _, fr = rast.forward(tpool, batches[t])
         targets.append(fr.image.clone())
     A = ResidentTrainer(theta, B)
-    O = OutOfCoreTrainer(theta, B, str(tmp_path / "store"), capacity=12, spare_slots=4, host_cache_blocks=8)
+    O = OutOfCoreTrainer(theta, B, str(tmp_path / "store"), capacity=12, spare_slots=4, host_cache_blocks=8,
+                         **flags)
     for t in range(T):
         fa, la = A.iterate(batches[t], targets[t])
         fo, lo = O.iterate(batches[t], targets[t], batches[t + 1])
@@ -111,4 +127,50 @@ def test_predictor_hints_leave_results_identical(tmp_path):
     say(f"tier stats: {st}")
     assert np.array_equal(A.params(), O.params())
     assert st["prefetch_issued"] > 0 and O.predictor.hinted > 0
+    O.tier.close()
+
+
+def test_paper_default_placement_equals_its_resident_emulation(tmp_path):
+    """The paper's default operating point (Sec. 3.5): a budget C below
+    |K_t| and Adam moments that live only while a block is resident.  An
+    all-resident pool reproduces it when it renders R_t and K_t's
+    intersection (the tier's own R_t and K_t) and zeroes the moments and
+    steps of every block admitted since the previous iteration: images,
+    losses and parameters must then be identical."""
+    theta = strip_scene()
+    B = 4096
+    T = 30
+    batches = walk_back(T)
+    rast = Rasterizer("cuda")
+    tpool = Pool.from_dense(torch.tensor(synth.perturbed(theta, 0.05, 51), device="cuda"), B)
+    targets = []
+    for t in range(T):
+        _, _, fr = rast.forward(tpool, batches[t])
+        targets.append(fr.image.clone())
+    O = OutOfCoreTrainer(theta, B, str(tmp_path / "store"), capacity=5, spare_slots=3, host_cache_blocks=8,
+                         cold_restart=True, bounded=True)
+    pool = Pool.from_dense(torch.tensor(theta, device="cuda"), B)   # block k in slot k
+    cfg = adam_cfg(LR59)
+    grad = torch.empty((59, pool.n_pidx), dtype=torch.float32, device="cuda")
+    prev = set()
+    for t in range(T):
+        fo, lo = O.iterate(batches[t], targets[t], batches[t + 1])
+        R = set(O.r_sets[t])
+        for k in sorted(R - prev):
+            pool.exp_avg[k].zero_()
+            pool.exp_avg_sq[k].zero_()
+            pool.step[k].zero_()
+        rend = sorted(set(O.k_sets[t]) & R)
+        pool.order[:len(rend)] = torch.tensor(rend, dtype=torch.int32, device="cuda")
+        pool.n_order = len(rend)
+        fa, la = step(rast, pool, batches[t], targets[t], cfg, grad)
+        torch.cuda.synchronize()
+        assert image_digest(fa.image) == image_digest(fo.image), f"iteration {t}"
+        assert float(la) == float(lo), f"iteration {t}"
+        prev = R
+    st = O.tier.stats()
+    say(f"tier stats: {st}")
+    assert st["skipped"] > 0 and st["readmissions"] > 0 and st["sync_fetches"] == 0
+    dense = pool.dense(theta.shape[0]).cpu().numpy()
+    assert np.array_equal(dense, O.params())
     O.tier.close()
