@@ -49,6 +49,17 @@ class Buffers:
         return b
 
 
+def _dptr(t: torch.Tensor) -> int:
+    """Device address of t's first element.  An empty view of an allocated
+    buffer (n_pidx = 0: nothing in the render order) reports 0 from
+    data_ptr(); the library still wants a valid address, so take the
+    buffer's."""
+    p = t.data_ptr()
+    if p == 0 and t.numel() == 0:
+        p = t.untyped_storage().data_ptr() + t.storage_offset() * t.element_size()
+    return p
+
+
 class Pool:
     """Resident parameter pool, block-SoA [n_slots][59][block_rows]."""
 
@@ -130,13 +141,13 @@ class Proj:
 
     def c(self) -> L.tide_proj:
         p = L.tide_proj()
-        p.rec = self.rec.data_ptr()
-        p.depth = self.depth.data_ptr()
-        p.rect = self.rect.data_ptr()
-        p.tiles_touched = self.tiles_touched.data_ptr()
-        p.active = self.active.data_ptr()
-        p.act_idx = self.act_idx.data_ptr()
-        p.n_active = self.n_active.data_ptr()
+        p.rec = _dptr(self.rec)
+        p.depth = _dptr(self.depth)
+        p.rect = _dptr(self.rect)
+        p.tiles_touched = _dptr(self.tiles_touched)
+        p.active = _dptr(self.active)
+        p.act_idx = _dptr(self.act_idx)
+        p.n_active = _dptr(self.n_active)
         p.n_pidx = self.n_pidx
         p.n_cams = self.n_cams
         p.dtype = self.dtype
