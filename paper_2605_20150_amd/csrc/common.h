@@ -75,6 +75,7 @@ struct Mth<float> {
   __device__ static float sqrt(float x) { return sqrtf(x); }
   __device__ static float rcp(float x) { return __frcp_rn(x); }
   __device__ static float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
+  __device__ static float log(float x) { return __logf(x); }
   __device__ static float ceil(float x) { return ceilf(x); }
   __device__ static float floor(float x) { return floorf(x); }
 };
@@ -85,6 +86,7 @@ struct Mth<double> {
   __device__ static double sqrt(double x) { return ::sqrt(x); }
   __device__ static double rcp(double x) { return 1.0 / x; }
   __device__ static double rcp_fast(double x) { return 1.0 / x; }
+  __device__ static double log(double x) { return ::log(x); }
   __device__ static double ceil(double x) { return ::ceil(x); }
   __device__ static double floor(double x) { return ::floor(x); }
 };

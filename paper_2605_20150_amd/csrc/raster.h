@@ -118,6 +118,31 @@ __device__ __forceinline__ bool entry_alpha(T adx2, T bdx, T Ch, T op, T dy, T& 
   return power <= (T)0 && alpha >= (T)(1.0 / 255.0);
 }
 
+// Tile-level test of one list entry, conservative: false only when no pixel
+// centre of tile (tx, ty) can take the entry, i.e. when opacity * G < 1/255
+// at every centre, G = exp(-Q/2), Q = A dx^2 + 2 B dx dy + C dy^2 (the conic
+// is positive definite).  The minimum of Q over the continuous box of the
+// tile's pixel centres bounds it over the centres: 0 if the mean is inside,
+// else the least of the four edge minima (on an edge, Q is a 1-D quadratic
+// minimised at the clamped stationary point).  A slack of 1e-3 (relative and
+// absolute) covers the rounding of this test and of the per-pixel one.
+template <typename T>
+__device__ __forceinline__ bool tile_may_take(T u, T v, T A, T B, T C, T op, int tx, int ty) {
+  const T xa = (T)(kTile * tx) + (T)0.5 - u, xb = xa + (T)(kTile - 1);
+  const T ya = (T)(kTile * ty) + (T)0.5 - v, yb = ya + (T)(kTile - 1);
+  T qmin = 0;
+  if (!(xa <= (T)0 && xb >= (T)0 && ya <= (T)0 && yb >= (T)0)) {
+    auto q = [&](T dx, T dy) { return A * dx * dx + (T)2 * B * dx * dy + C * dy * dy; };
+    auto cl = [](T x, T lo, T hi) { return x < lo ? lo : (x > hi ? hi : x); };
+    const T e0 = q(xa, cl(-B * xa / C, ya, yb)), e1 = q(xb, cl(-B * xb / C, ya, yb));
+    const T e2 = q(cl(-B * ya / A, xa, xb), ya), e3 = q(cl(-B * yb / A, xa, xb), yb);
+    qmin = e0 < e1 ? e0 : e1;
+    qmin = qmin < e2 ? qmin : e2;
+    qmin = qmin < e3 ? qmin : e3;
+  }
+  return (T)0.5 * qmin * (T)(1.0 - 1e-3) <= Mth<T>::log((T)255 * op) + (T)1e-3;
+}
+
 // Wave64 sum with DPP row shifts and row broadcasts; the total lands in
 // lane 63 (other lanes hold partial sums).
 template <int CTRL, int ROWS, bool BC>

@@ -72,7 +72,7 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
   __shared__ T s_u[64], s_v[64], s_Ah[64], s_Bh[64], s_Ch[64], s_A[64], s_B[64], s_C[64], s_o[64], s_r[64],
       s_g[64], s_b[64];
   __shared__ T s_part[64][4][kG2];
-  __shared__ uint32_t s_hit[64];
+  __shared__ uint32_t s_hit[64], s_take[64];
   const T ks = (T)Ex<T>::k;
   const int row = lane >> 4;
   for (int32_t hi = (int32_t)maxl; hi > 0; hi -= 64) {
@@ -86,9 +86,14 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
       s_A[lane] = q[2]; s_B[lane] = q[3]; s_C[lane] = q[4];
       s_Ah[lane] = (T)-0.5 * ks * q[2]; s_Bh[lane] = -ks * q[3]; s_Ch[lane] = (T)-0.5 * ks * q[4];
       s_o[lane] = q[5]; s_r[lane] = q[6]; s_g[lane] = q[7]; s_b[lane] = q[8];
+      s_take[lane] = tile_may_take<T>(q[0], q[1], q[2], q[3], q[4], q[5], tx, ty) ? 1u : 0u;
     }
     __syncthreads();
     for (int k = n - 1; k >= 0; --k) {
+      if (!s_take[k]) {   // no pixel centre of the tile takes the entry (forward's test)
+        if (lane == 0) s_hit[k] = 0u;
+        continue;
+      }
       const uint32_t pos = (uint32_t)(lo + k);
       const T v = s_v[k], Ch = s_Ch[k], op = s_o[k];
       const T B = s_B[k], C = s_C[k];
@@ -100,9 +105,9 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
       // accumulated as moments of dp over dy and finished once per lane:
       // d/dA = dx^2 S0, d/dB = dx S1, d/dC = S2 (times -1/2, -1, -1/2 below),
       // d/du = A dx S0 + B S1, d/dv = B dx S0 + C S1.
-      // G first: an entry no pixel of the tile takes (pass and before the
-      // pixel's last contributor) leaves every pixel's state and the entry's
-      // partial at zero, so the wave skips the rest.
+      // G first: an entry no pixel takes (pass and before the pixel's last
+      // contributor) leaves every pixel's state and the entry's partial at
+      // zero, so the wave skips the rest.
       T Gq[4];
       bool okq[4];
       bool hit = false;

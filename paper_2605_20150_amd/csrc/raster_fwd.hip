@@ -409,10 +409,15 @@ __global__ void __launch_bounds__(64) k_render_fwd(const uint32_t* __restrict__ 
     lst[q] = 0;
   }
   unsigned long long nvis = 0;   // wave-uniform: live pixels summed over entries
+  // live pixels of the wave; every entry reached counts them as visits
+  uint32_t nlive = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) nlive += (uint32_t)__popcll(__ballot(Tr[q] > 0));
   const uint32_t start = ranges[2 * g], end = ranges[2 * g + 1];
   __shared__ T s_u[64], s_v[64], s_A[64], s_B[64], s_C[64], s_o[64], s_r[64], s_g[64], s_b[64];
+  __shared__ uint32_t s_take[64];
   const T ks = (T)Ex<T>::k;
-  bool any = __ballot(Tr[0] > 0 || Tr[1] > 0 || Tr[2] > 0 || Tr[3] > 0) != 0;
+  bool any = nlive != 0;
   for (uint32_t b0 = start; b0 < end && any; b0 += 64) {
     const uint32_t j = b0 + lane;
     if (j < end) {
@@ -420,19 +425,24 @@ __global__ void __launch_bounds__(64) k_render_fwd(const uint32_t* __restrict__ 
       s_u[lane] = q[0]; s_v[lane] = q[1];
       s_A[lane] = (T)-0.5 * ks * q[2]; s_B[lane] = -ks * q[3]; s_C[lane] = (T)-0.5 * ks * q[4];
       s_o[lane] = q[5]; s_r[lane] = q[6]; s_g[lane] = q[7]; s_b[lane] = q[8];
+      // entries whose footprint misses every pixel centre of the tile at
+      // alpha >= 1/255 (about 40 % of the aerial scene's instances) are
+      // passed over without any per-pixel work
+      s_take[lane] = tile_may_take<T>(q[0], q[1], q[2], q[3], q[4], q[5], tx, ty) ? 1u : 0u;
     }
     __syncthreads();
     const int nb = (int)(end - b0 < 64 ? end - b0 : 64);
     for (int k = 0; k < nb; ++k) {
+      nvis += nlive;
+      if (!s_take[k]) continue;
       const T v = s_v[k], Ch = s_C[k], op = s_o[k];
       const T cr = s_r[k], cg = s_g[k], cb = s_b[k];
       const T dx = fxp - s_u[k];
       const T adx2 = s_A[k] * dx * dx, bdx = s_B[k] * dx;
       const uint32_t idx = b0 - start + (uint32_t)k + 1;
-      // Alphas first: when no live pixel of the tile takes the entry (about
-      // 40 % of the instances of the aerial scene: their tile meets the
-      // footprint's square but not its alpha >= 1/255 ellipse), the update
-      // below would change nothing, and the wave skips it.
+      // Alphas first: when no live pixel takes the entry (the tile test is
+      // conservative, and pixels stop), the update below would change
+      // nothing, and the wave skips it.
       T al[4];
       bool ps[4];
       bool take_any = false;
@@ -440,12 +450,9 @@ __global__ void __launch_bounds__(64) k_render_fwd(const uint32_t* __restrict__ 
       for (int q = 0; q < 4; ++q) {
         T G, araw;
         ps[q] = entry_alpha<T>(adx2, bdx, Ch, op, fyp[q] - v, G, araw, al[q]);
-        const bool live = Tr[q] > 0;
-        nvis += (unsigned long long)__popcll(__ballot(live));
-        take_any = take_any || (ps[q] && live);
+        take_any = take_any || (ps[q] && Tr[q] > 0);
       }
       if (__ballot(take_any) == 0) continue;
-      bool live_any = false;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const T alpha = al[q];
@@ -460,9 +467,11 @@ __global__ void __launch_bounds__(64) k_render_fwd(const uint32_t* __restrict__ 
         C0[q] += cr * w; C1[q] += cg * w; C2[q] += cb * w;
         Tr[q] = take ? tn : (stop ? -Tr[q] : Tr[q]);
         lst[q] = take ? idx : lst[q];
-        live_any = live_any || (live && !stop);
       }
-      if (__ballot(live_any) == 0) { any = false; break; }
+      nlive = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) nlive += (uint32_t)__popcll(__ballot(Tr[q] > 0));
+      if (nlive == 0) { any = false; break; }
     }
     __syncthreads();
   }
