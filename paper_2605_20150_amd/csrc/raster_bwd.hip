@@ -15,8 +15,9 @@ constexpr int kG2 = 9;  // du, dv, dA, dB, dC, dopacity, dr, dg, db
 // normalised colour behind the entry (r_{i-1} = alpha_i c_i + (1-alpha_i) r_i,
 // starting from the background).  The per-pixel update is branch-free; the
 // four pixels of a lane are summed in registers, each row of 16 lanes is
-// reduced with DPP and the four row sums are parked in LDS; once a batch of
-// 64 entries is done, lane k adds entry k's four row sums (fixed order) and
+// reduced with DPP, rows are added in pairs (0 + 1, 2 + 3) and the two pair
+// sums are parked in LDS (small enough for four waves per SIMD); once a
+// batch of 64 entries is done, lane k adds entry k's two pair sums and
 // stores its partial.  Entries no pixel reaches get zero partials.
 template <typename T>
 __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ order,
@@ -71,10 +72,9 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
   }
   __shared__ T s_u[64], s_v[64], s_Ah[64], s_Bh[64], s_Ch[64], s_A[64], s_B[64], s_C[64], s_o[64], s_r[64],
       s_g[64], s_b[64];
-  __shared__ T s_part[64][4][kG2];
+  __shared__ T s_part[64][2][kG2];   // per entry, the sums of rows 0-1 and 2-3
   __shared__ uint32_t s_hit[64], s_take[64];
   const T ks = (T)Ex<T>::k;
-  const int row = lane >> 4;
   for (int32_t hi = (int32_t)maxl; hi > 0; hi -= 64) {
     const int32_t lo = hi - 64 > 0 ? hi - 64 : 0;
     const int32_t n = hi - lo;
@@ -151,8 +151,11 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
       a_u = row_sum_to_15(a_u); a_v = row_sum_to_15(a_v); a_A = row_sum_to_15(a_A);
       a_B = row_sum_to_15(a_B); a_C = row_sum_to_15(a_C); a_o = row_sum_to_15(a_o);
       a_r = row_sum_to_15(a_r); a_g = row_sum_to_15(a_g); a_b = row_sum_to_15(a_b);
-      if ((lane & 15) == 15) {
-        T* S = s_part[k][row];
+      a_u = pair_rows(a_u); a_v = pair_rows(a_v); a_A = pair_rows(a_A); a_B = pair_rows(a_B);
+      a_C = pair_rows(a_C); a_o = pair_rows(a_o); a_r = pair_rows(a_r); a_g = pair_rows(a_g);
+      a_b = pair_rows(a_b);
+      if ((lane & 31) == 31) {
+        T* S = s_part[k][lane >> 5];
         S[0] = a_u; S[1] = a_v; S[2] = a_A; S[3] = a_B; S[4] = a_C;
         S[5] = a_o; S[6] = a_r; S[7] = a_g; S[8] = a_b;
       }
@@ -164,7 +167,7 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
         T r[kG2];
 #pragma unroll
         for (int m = 0; m < kG2; ++m)
-          r[m] = ((s_part[lane][0][m] + s_part[lane][1][m]) + s_part[lane][2][m]) + s_part[lane][3][m];
+          r[m] = s_part[lane][0][m] + s_part[lane][1][m];
         // dpower/dA = -dx^2/2, dpower/dB = -dx dy, dpower/dC = -dy^2/2
         P[0] = r[0]; P[1] = r[1]; P[2] = (T)-0.5 * r[2]; P[3] = -r[3]; P[4] = (T)-0.5 * r[4];
         P[5] = r[5]; P[6] = r[6]; P[7] = r[7]; P[8] = r[8];
