@@ -480,8 +480,9 @@ def main():
         rast.backward(pool, cb, proj, bins, fr, dimg, grad=grad)
         rast.adam(pool, proj, grad, cfg, spheres, dirty)
         if stats is not None:
-            stats.append((bins.n_vis, bins.n_inst, proj.n_active.clone(), fr.visits, fr.last.sum(dtype=torch.int64),
-                          (proj.tiles_touched.view(V, -1) > 0).any(0).sum(), loss))
+            # counters the kernels keep themselves: no extra reductions in the
+            # timed region (the Gaussians kept by some camera are the active set)
+            stats.append((bins.n_vis, bins.n_inst, proj.n_active.clone(), fr.visits, loss))
 
     # per-kernel HIP events armed on the launch stream; created (and
     # materialised by one record) before the timed region
@@ -514,9 +515,9 @@ def main():
     n_vis = np.mean([s[0] for s in stats])
     n_inst = np.mean([s[1] for s in stats])
     n_active = np.mean([int(s[2].item()) for s in stats])
-    fwd_visits = np.mean([int(s[3].sum().item()) for s in stats])
-    bwd_visits = np.mean([int(s[4].item()) for s in stats])
-    n_kept = np.mean([int(s[5].item()) for s in stats])
+    fwd_visits = np.mean([int(s[3][0].sum().item()) for s in stats])
+    bwd_visits = np.mean([int(s[3][1].sum().item()) for s in stats])
+    n_kept = n_active
     pixels = V * 1920 * 1080
     iters = args.steps / wall
 

@@ -154,7 +154,9 @@ typedef struct {
   const uint32_t* inst_rec;    /* [n_inst] record index of emission index e */
   const uint32_t* ranges;      /* [n_cams*n_tiles][2] sorted-instance [start, end) */
   const uint32_t* tile_order;  /* [n_cams*n_tiles] global tile ids by descending list length
-                                  (ties in tile order): the compositing launch order */
+                                  on a log scale, 16 steps per octave of length + 1 (lengths
+                                  >= 2^16 together; ties in tile order): the compositing
+                                  launch order */
   int64_t n_vis;
   int64_t n_inst;
   int32_t n_cams;
@@ -183,9 +185,10 @@ tide_status tide_bin_sort(const tide_proj* proj, int32_t tiles_x, int32_t tiles_
  *   t_final device dtype [n_cams][H][W]
  *   last    device u32 [n_cams][H][W]: 1 + position (in the tile list) of
  *           the last contributing entry, 0 if none
- *   visits  device u64 [n_cams]: entries evaluated, summed over pixels
- *           (the entry that stops a pixel is counted); accumulated, so
- *           zero it first.
+ *   visits  device u64 [2][n_cams]: row 0 the entries evaluated, summed
+ *           over pixels (the entry that stops a pixel is counted); row 1
+ *           the entries the backward walks, summed over pixels (the sum of
+ *           last); accumulated, so zero them first.
  * bg: host float[3]. All cameras share W = width, H = height. */
 typedef struct {
   void* image;

@@ -54,15 +54,18 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint32_t* 
                                                                 const uint32_t* gofs, int64_t nb,
                                                                 uint32_t* keys_out, uint32_t* vals_out) {
   const int64_t n = dev_count(n_max, d_n);
-  if ((int64_t)blockIdx.x * kSortTile >= n) return;
+  const int64_t b0 = (int64_t)blockIdx.x * kSortTile;
+  if (b0 >= n) return;
+  const int m = (int)(n - b0 < kSortTile ? n - b0 : kSortTile);   // elements of this block
   __shared__ uint32_t wcnt[kSortWaves][256];
-  __shared__ uint32_t gbase[256];
+  __shared__ uint32_t gbase[256], lstart[256], wsum[kSortWaves];
+  __shared__ uint32_t skey[kSortTile], sval[kSortTile];
   for (int k = threadIdx.x; k < kSortWaves * 256; k += kSortThreads) (&wcnt[0][0])[k] = 0;
   gbase[threadIdx.x] = gofs[(int64_t)threadIdx.x * nb + blockIdx.x];
   __syncthreads();
   const int w = threadIdx.x / kWave, lane = __lane_id();
   const uint64_t lt = lanemask_lt();
-  const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)w * (kWave * kSortRounds);
+  const int64_t base = b0 + (int64_t)w * (kWave * kSortRounds);
   uint32_t key[kSortRounds], val[kSortRounds], rank[kSortRounds];
 #pragma unroll
   for (int r = 0; r < kSortRounds; ++r) {
@@ -75,8 +78,8 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint32_t* 
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
       const bool bit = (d >> b) & 1u;
-      const uint64_t m = __ballot(bit);
-      peers &= bit ? m : ~m;
+      const uint64_t mk = __ballot(bit);
+      peers &= bit ? mk : ~mk;
     }
     uint32_t r0 = 0;
     if (ok) r0 = wcnt[w][d];
@@ -85,26 +88,43 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint32_t* 
     if (ok && (peers & lt) == 0) wcnt[w][d] = r0 + (uint32_t)__popcll(peers);
   }
   __syncthreads();
-  {
-    const int d = threadIdx.x;
-    uint32_t run = 0;
+  // per digit: the waves' offsets within the digit, and the digit's start in
+  // the block (exclusive scan of the block's digit counts)
+  const int d = threadIdx.x;
+  uint32_t cnt = 0;
 #pragma unroll
-    for (int q = 0; q < kSortWaves; ++q) {
-      const uint32_t c = wcnt[q][d];
-      wcnt[q][d] = run;
-      run += c;
-    }
+  for (int q = 0; q < kSortWaves; ++q) {
+    const uint32_t c = wcnt[q][d];
+    wcnt[q][d] = cnt;
+    cnt += c;
   }
+  const uint32_t inc = wave_incl_scan(cnt);
+  if (lane == kWave - 1) wsum[w] = inc;
   __syncthreads();
+  uint32_t pre = 0;
+  for (int q = 0; q < w; ++q) pre += wsum[q];
+  lstart[d] = pre + inc - cnt;
+  __syncthreads();
+  // the block's elements in (digit, rank) order in LDS ...
 #pragma unroll
   for (int r = 0; r < kSortRounds; ++r) {
     const int64_t i = base + (int64_t)r * kWave + lane;
     if (i < n) {
-      const uint32_t d = (key[r] >> shift) & 255u;
-      const uint32_t pos = gbase[d] + wcnt[w][d] + rank[r];
-      keys_out[pos] = key[r];
-      vals_out[pos] = val[r];
+      const uint32_t dd = (key[r] >> shift) & 255u;
+      const uint32_t j = lstart[dd] + wcnt[w][dd] + rank[r];
+      skey[j] = key[r];
+      sval[j] = val[r];
     }
+  }
+  __syncthreads();
+  // ... written out in that order: runs of one digit land on consecutive
+  // addresses
+  for (int j = threadIdx.x; j < m; j += kSortThreads) {
+    const uint32_t k = skey[j];
+    const uint32_t dd = (k >> shift) & 255u;
+    const uint32_t pos = gbase[dd] + (uint32_t)j - lstart[dd];
+    keys_out[pos] = k;
+    vals_out[pos] = sval[j];
   }
 }
 

@@ -327,11 +327,18 @@ __global__ void k_ranges(const uint32_t* __restrict__ key, int64_t n, uint32_t* 
 // Launch order of the compositing kernels: tiles by descending list length
 // (ties in tile order), so that the longest lists start first and the tail
 // of the launch is made of short ones.  Key = 2^24 - 1 - min(length, 2^24 - 1).
+// Launch-order key of a tile: its list length on a log scale with 16 steps
+// per octave (the leading bit's position and the next four bits of len + 1),
+// longest first; lengths of 2^16 and more share the first bucket.  One 8-bit
+// radix pass orders them; ties keep tile order.
 __global__ void k_tile_keys(const uint32_t* __restrict__ ranges, int64_t n, uint32_t* __restrict__ key) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
-  const uint32_t len = ranges[2 * g + 1] - ranges[2 * g];
-  key[g] = 0xffffffu - (len < 0xffffffu ? len : 0xffffffu);
+  const uint32_t x = ranges[2 * g + 1] - ranges[2 * g] + 1u;
+  const uint32_t e = 31u - (uint32_t)__clz(x);
+  const uint32_t f = e >= 4u ? (x >> (e - 4u)) & 15u : (x << (4u - e)) & 15u;
+  const uint32_t b = 16u * e + f;
+  key[g] = 255u - (b < 255u ? b : 255u);
 }
 
 struct BinLayout {
@@ -476,11 +483,13 @@ __global__ void __launch_bounds__(64) k_render_fwd(const uint32_t* __restrict__ 
     __syncthreads();
   }
   const int64_t HW = (int64_t)H * W;
+  unsigned long long nback = 0;   // entries the backward walks for this lane's pixels
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int py = py0 + 4 * q;
     if (px < W && py < H) {
       const int64_t p = (int64_t)py * W + px;
+      nback += lst[q];
       const T tf = Tr[q] < 0 ? -Tr[q] : Tr[q];
       image[((int64_t)c * 3 + 0) * HW + p] = C0[q] + tf * bg0;
       image[((int64_t)c * 3 + 1) * HW + p] = C1[q] + tf * bg1;
@@ -490,6 +499,8 @@ __global__ void __launch_bounds__(64) k_render_fwd(const uint32_t* __restrict__ 
     }
   }
   if (lane == 0 && nvis) atomicAdd(&visits[c], nvis);
+  nback = wave_sum(nback);
+  if (lane == 0 && nback) atomicAdd(&visits[(int)(gridDim.x / (uint32_t)nt) + c], nback);
 }
 
 }  // namespace tide
@@ -596,7 +607,7 @@ extern "C" tide_status tide_bin_sort(const tide_proj* proj, int32_t tiles_x, int
   hipLaunchKernelGGL(k_tile_keys, dim3((uint32_t)ceil_div(ntt, 256)), dim3(256), 0, st, L.ranges, ntt, L.oka);
   TIDE_LAUNCH_CHECK("k_tile_keys");
   uint32_t *ok, *order;
-  radix_sort_pairs(L.oka, L.ova, L.okb, L.ovb, ntt, 24, true, L.hist, L.partial, &L.totals[3], st, &ok, &order);
+  radix_sort_pairs(L.oka, L.ova, L.okb, L.ovb, ntt, 8, true, L.hist, L.partial, &L.totals[3], st, &ok, &order);
   out->tile_order = order;
   out->vis_rec = vrec;
   out->inst_off = L.inst_off;

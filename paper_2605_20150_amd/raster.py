@@ -159,9 +159,17 @@ class Frame:
     image: torch.Tensor
     t_final: torch.Tensor
     last: torch.Tensor
-    visits: torch.Tensor
+    visits: torch.Tensor      # [2][V]: forward visits, backward visits per view
     width: int
     height: int
+
+    @property
+    def visits_fwd(self) -> torch.Tensor:
+        return self.visits[0]
+
+    @property
+    def visits_bwd(self) -> torch.Tensor:
+        return self.visits[1]
 
     def c(self) -> L.tide_frame:
         f = L.tide_frame()
@@ -234,14 +242,18 @@ class Rasterizer:
             return bins
         raise L.TideError(L.TIDE_ECAPACITY, "bin_sort capacity retries exhausted")
 
-    def render(self, proj: Proj, bins: L.tide_bins, width: int, height: int, bg=(0.0, 0.0, 0.0)) -> Frame:
-        V = proj.n_cams
-        dt = torch.float32 if proj.dtype == L.TIDE_F32 else torch.float64
+    def new_frame(self, V: int, width: int, height: int, dtype) -> Frame:
         dev = self.device
-        fr = Frame(image=torch.empty((V, 3, height, width), dtype=dt, device=dev),
-                   t_final=torch.empty((V, height, width), dtype=dt, device=dev),
-                   last=torch.empty((V, height, width), dtype=torch.int32, device=dev),
-                   visits=torch.zeros((V,), dtype=torch.int64, device=dev), width=width, height=height)
+        return Frame(image=torch.empty((V, 3, height, width), dtype=dtype, device=dev),
+                     t_final=torch.empty((V, height, width), dtype=dtype, device=dev),
+                     last=torch.empty((V, height, width), dtype=torch.int32, device=dev),
+                     visits=torch.zeros((2, V), dtype=torch.int64, device=dev), width=width, height=height)
+
+    def render(self, proj: Proj, bins: L.tide_bins, width: int, height: int, bg=(0.0, 0.0, 0.0),
+               fr: Frame | None = None) -> Frame:
+        if fr is None:
+            fr = self.new_frame(proj.n_cams, width, height, torch.float32 if proj.dtype == L.TIDE_F32
+                                else torch.float64)
         bgc = (C.c_float * 3)(*[float(x) for x in bg])
         fc = fr.c()
         pc = proj.c()
@@ -252,8 +264,11 @@ class Rasterizer:
         W, H = int(cams[0].width), int(cams[0].height)
         cam_arr = L.camera_array(cams)
         proj = self.preprocess(pool, cams, cam_arr)
+        # the frame is made before the binning, whose count read-back leaves
+        # the GPU idle until the next launch
+        fr = self.new_frame(len(cams), W, H, pool.params.dtype)
         bins = self.bin_sort(proj, (W + TILE - 1) // TILE, (H + TILE - 1) // TILE)
-        fr = self.render(proj, bins, W, H, bg)
+        self.render(proj, bins, W, H, bg, fr)
         return proj, bins, fr
 
     # ----------------------------------------------------------------- loss

@@ -91,7 +91,9 @@ def test_tiny_scene_image_matches_oracle():
     assert err <= 1e-4
     last = fr.last.cpu().numpy()
     assert np.array_equal(last[~tie], ref["last"][~tie])
-    assert int(fr.visits.sum()) == int(ref["visits"].sum()) or tie.any()
+    assert int(fr.visits_fwd.sum()) == int(ref["visits"].sum()) or tie.any()
+    # the backward walks every entry up to each pixel's last contributor
+    assert np.array_equal(fr.visits_bwd.cpu().numpy(), last.reshape(last.shape[0], -1).sum(1))
     assert np.abs(fr.t_final.double().cpu().numpy() - ref["t_final"])[~tie].max() <= 1e-5
 
 
@@ -151,11 +153,17 @@ def test_binning_is_bit_exact_on_oracle_inputs():
     assert np.array_equal(g_ranges, ranges)
     g_list = inst_rec[inst_e] % proj.n_pidx
     assert np.array_equal(g_list, gid)
-    # the launch order is a permutation of the tiles, longest lists first
+    # the launch order is a permutation of the tiles, longest lists first on
+    # a log scale of 16 steps per octave of len + 1 (ties in tile order)
     order = b["tile_order"].cpu().numpy().astype(np.int64)
-    lens = ranges[:, 1] - ranges[:, 0]
+    lens = (ranges[:, 1] - ranges[:, 0]).astype(np.int64)
     assert sorted(order.tolist()) == list(range(len(lens)))
-    assert np.array_equal(order, np.argsort(-lens, kind="stable"))
+    x = lens + 1
+    e = np.floor(np.log2(x)).astype(np.int64)
+    frac = np.floor((x / 2.0 ** e - 1.0) * 16).astype(np.int64)
+    bucket = np.minimum(255, 16 * e + frac)
+    assert np.array_equal(order, np.argsort(-bucket, kind="stable"))
+    assert (np.diff(lens[order].astype(float)) <= 0).mean() > 0.5
     say(f"instances {bins.n_inst}, visible pairs {bins.n_vis}: lists identical")
 
 
@@ -407,4 +415,5 @@ def test_aerial_full_size_view_matches_oracle():
     # contribution at the 1/255 alpha floor (or by T below 1e-4): <= 1e-2
     assert err.max() <= 1e-2
     vis_ref = int(ref["visits"].sum())
-    say(f"visits gpu {int(fr.visits[0])} oracle {vis_ref}")
+    say(f"visits gpu {int(fr.visits_fwd[0])} oracle {vis_ref}")
+    assert int(fr.visits_bwd[0]) == int(fr.last[0].sum(dtype=torch.int64))

@@ -77,8 +77,9 @@ def test_street_50m_rates_crop_gradient_and_finite_differences():
     torch.cuda.synchronize()
     lib.tide_timer_clear()
     ms = {k: a.elapsed_time(b) for k, (a, b) in ev.items()}
-    fv = int(fr.visits.sum())
-    bv = int(fr.last.sum(dtype=torch.int64))
+    fv = int(fr.visits_fwd.sum())
+    bv = int(fr.visits_bwd.sum())
+    assert bv == int(fr.last.sum(dtype=torch.int64))
     pixels = 4 * 900 * 1600
     say(f"visible pairs {bins.n_vis}, instances {bins.n_inst}; forward {ms['render_fwd']:.3f} ms, "
         f"{fv / ms['render_fwd'] / 1e9:.3f} T visits/s, "
