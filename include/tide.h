@@ -157,6 +157,8 @@ typedef struct {
                                   on a log scale, 16 steps per octave of length + 1 (lengths
                                   >= 2^16 together; ties in tile order): the compositing
                                   launch order */
+  unsigned long long* tile_visits;  /* [2][n_cams*n_tiles] scratch in ws: per-tile visit
+                                  counts that tide_render_fwd writes and sums per view */
   int64_t n_vis;
   int64_t n_inst;
   int32_t n_cams;

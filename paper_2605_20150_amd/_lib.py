@@ -51,7 +51,8 @@ class tide_proj(C.Structure):
 
 class tide_bins(C.Structure):
     _fields_ = [("vis_rec", C.c_void_p), ("inst_off", C.c_void_p), ("inst_e", C.c_void_p),
-                ("inst_rec", C.c_void_p), ("ranges", C.c_void_p), ("tile_order", C.c_void_p), ("n_vis", C.c_int64), ("n_inst", C.c_int64),
+                ("inst_rec", C.c_void_p), ("ranges", C.c_void_p), ("tile_order", C.c_void_p),
+                ("tile_visits", C.c_void_p), ("n_vis", C.c_int64), ("n_inst", C.c_int64),
                 ("n_cams", C.c_int32), ("tiles_x", C.c_int32), ("tiles_y", C.c_int32), ("n_pidx", C.c_int64),
                 ("ws_required", C.c_size_t)]
 

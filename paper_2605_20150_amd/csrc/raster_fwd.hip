@@ -344,6 +344,7 @@ __global__ void k_tile_keys(const uint32_t* __restrict__ ranges, int64_t n, uint
 struct BinLayout {
   uint32_t *vis_off, *ka, *va, *kb, *vb, *inst_off, *tka, *tva, *tkb, *tvb, *inst_rec, *ranges, *hist;
   uint32_t *oka, *ova, *okb, *ovb;   // tile launch-order sort
+  unsigned long long* tvis;          // per-tile visit counts of the compositing
   unsigned long long *partial, *totals;
   size_t bytes;
 };
@@ -369,6 +370,7 @@ static BinLayout bin_layout(void* ws, int n_cams, int64_t n_pidx, int64_t n_tile
   L.ova = cv.take<uint32_t>(ntt);
   L.okb = cv.take<uint32_t>(ntt);
   L.ovb = cv.take<uint32_t>(ntt);
+  L.tvis = cv.take<unsigned long long>(2 * ntt);
   int64_t big = nv > cap ? nv : cap;
   big = big > ntt ? big : ntt;
   const size_t nh = radix_hist_count(big);
@@ -395,7 +397,7 @@ __global__ void __launch_bounds__(64) k_render_fwd(const uint32_t* __restrict__ 
                                                    int32_t Tx, int32_t Ty, int32_t W, int32_t H, T bg0, T bg1,
                                                    T bg2, T* __restrict__ image, T* __restrict__ tfin,
                                                    uint32_t* __restrict__ last_out,
-                                                   unsigned long long* __restrict__ visits) {
+                                                   unsigned long long* __restrict__ tile_visits) {
   const int nt = Tx * Ty;
   const int g = (int)order[blockIdx.x];
   const int c = g / nt, t = g - c * nt;
@@ -498,9 +500,29 @@ __global__ void __launch_bounds__(64) k_render_fwd(const uint32_t* __restrict__ 
       last_out[(int64_t)c * HW + p] = lst[q];
     }
   }
-  if (lane == 0 && nvis) atomicAdd(&visits[c], nvis);
+  // per-tile counts, summed per view by k_sum_visits (no same-address
+  // atomics: those cross the XCDs' separate L2s)
   nback = wave_sum(nback);
-  if (lane == 0 && nback) atomicAdd(&visits[(int)(gridDim.x / (uint32_t)nt) + c], nback);
+  if (lane == 0) {
+    tile_visits[g] = nvis;
+    tile_visits[gridDim.x + g] = nback;
+  }
+}
+
+// visits[r][c] += sum over camera c's tiles of tile_visits[r][c * nt + t],
+// in tile order (one workgroup per (row, camera)).
+__global__ void __launch_bounds__(256) k_sum_visits(const unsigned long long* __restrict__ tile_visits,
+                                                    int64_t nt, int32_t n_cams,
+                                                    unsigned long long* __restrict__ visits) {
+  const int rc = blockIdx.x;   // r * n_cams + c
+  const unsigned long long* p = tile_visits + (int64_t)rc * nt;
+  unsigned long long s = 0;
+  for (int64_t t = threadIdx.x; t < nt; t += 256) s += p[t];
+  s = wave_sum(s);
+  __shared__ unsigned long long ws[4];
+  if (__lane_id() == 0) ws[threadIdx.x / kWave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) visits[rc] += ws[0] + ws[1] + ws[2] + ws[3];
 }
 
 }  // namespace tide
@@ -609,6 +631,7 @@ extern "C" tide_status tide_bin_sort(const tide_proj* proj, int32_t tiles_x, int
   uint32_t *ok, *order;
   radix_sort_pairs(L.oka, L.ova, L.okb, L.ovb, ntt, 8, true, L.hist, L.partial, &L.totals[3], st, &ok, &order);
   out->tile_order = order;
+  out->tile_visits = L.tvis;
   out->vis_rec = vrec;
   out->inst_off = L.inst_off;
   out->inst_e = te;
@@ -627,7 +650,7 @@ extern "C" tide_status tide_render_fwd(const tide_proj* proj, const tide_bins* b
                                        tide_frame* fr, void* stream) {
   tide_status s;
   if ((s = check_proj(proj)) != TIDE_OK) return s;
-  TIDE_CHECK_ARG(bins && fr && bg, "null argument");
+  TIDE_CHECK_ARG(bins && fr && bg && bins->tile_visits, "null argument");
   TIDE_CHECK_ARG(fr->image && fr->t_final && fr->last && fr->visits, "frame has a null pointer");
   TIDE_CHECK_ARG(bins->n_cams == proj->n_cams && bins->n_pidx == proj->n_pidx, "bins do not match proj");
   TIDE_CHECK_ARG(fr->width > 0 && fr->height > 0 && (fr->width + kTile - 1) / kTile == bins->tiles_x &&
@@ -638,12 +661,15 @@ extern "C" tide_status tide_render_fwd(const tide_proj* proj, const tide_bins* b
   if (proj->dtype == TIDE_F32)
     TIDE_TIMED("render_fwd", st, hipLaunchKernelGGL(k_render_fwd<float>, dim3(grid), dim3(64), 0, st, bins->tile_order, bins->ranges, bins->inst_e, bins->inst_rec,
                        (const float*)proj->rec, bins->tiles_x, bins->tiles_y, fr->width, fr->height, bg[0], bg[1],
-                       bg[2], (float*)fr->image, (float*)fr->t_final, fr->last, fr->visits));
+                       bg[2], (float*)fr->image, (float*)fr->t_final, fr->last, bins->tile_visits));
   else
     TIDE_TIMED("render_fwd", st, hipLaunchKernelGGL(k_render_fwd<double>, dim3(grid), dim3(64), 0, st, bins->tile_order, bins->ranges, bins->inst_e,
                        bins->inst_rec, (const double*)proj->rec, bins->tiles_x, bins->tiles_y, fr->width,
                        fr->height, (double)bg[0], (double)bg[1], (double)bg[2], (double*)fr->image,
-                       (double*)fr->t_final, fr->last, fr->visits));
+                       (double*)fr->t_final, fr->last, bins->tile_visits));
   TIDE_LAUNCH_CHECK("k_render_fwd");
+  hipLaunchKernelGGL(k_sum_visits, dim3((uint32_t)(2 * bins->n_cams)), dim3(256), 0, st, bins->tile_visits,
+                     (int64_t)bins->tiles_x * bins->tiles_y, bins->n_cams, fr->visits);
+  TIDE_LAUNCH_CHECK("k_sum_visits");
   return TIDE_OK;
 }
