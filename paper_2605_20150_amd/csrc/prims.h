@@ -72,11 +72,32 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(In in, int64_t n_m
 __global__ void __launch_bounds__(1024) k_scan_partials(unsigned long long* partial, int64_t nb,
                                                         unsigned long long* total);
 
-template <typename In>
+// kSums: partial holds the blocks' sums (not yet scanned); each block adds
+// up its predecessors' itself and block 0 writes the total (one launch
+// fewer; used when there are at most 1024 blocks).
+template <typename In, bool kSums>
 __global__ void __launch_bounds__(kScanThreads) k_scan_down(In in, int64_t n_max, const unsigned long long* d_n,
                                                             const unsigned long long* partial,
-                                                            uint32_t* out) {
+                                                            uint32_t* out, int64_t nb,
+                                                            unsigned long long* total) {
   const int64_t n = dev_count(n_max, d_n);
+  __shared__ unsigned long long bpre[kScanThreads / kWave + 1];
+  if (kSums) {
+    // predecessors' sums (and, in block 0, all the sums for the total)
+    const int64_t upto = blockIdx.x == 0 ? nb : (int64_t)blockIdx.x;
+    unsigned long long a = 0;
+    for (int64_t q = threadIdx.x; q < upto; q += kScanThreads) a += partial[q];
+    a = wave_sum(a);
+    if (__lane_id() == 0) bpre[threadIdx.x / kWave] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long t = 0;
+      for (int q = 0; q < kScanThreads / kWave; ++q) t += bpre[q];
+      if (blockIdx.x == 0) *total = t;
+      bpre[kScanThreads / kWave] = blockIdx.x == 0 ? 0ull : t;
+    }
+    __syncthreads();
+  }
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   uint32_t v[kScanItems];
   uint32_t s = 0;
@@ -93,7 +114,8 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_down(In in, int64_t n_max
   __syncthreads();
   uint32_t wpre = 0;
   for (int q = 0; q < w; ++q) wpre += wtot[q];
-  uint32_t run = (uint32_t)partial[blockIdx.x] + wpre + inc - s;
+  const unsigned long long bp = kSums ? bpre[kScanThreads / kWave] : partial[blockIdx.x];
+  uint32_t run = (uint32_t)bp + wpre + inc - s;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     if (base + k < n) out[base + k] = run;
@@ -108,9 +130,14 @@ inline void scan_exclusive(In in, int64_t n, uint32_t* out, unsigned long long* 
                            unsigned long long* total, hipStream_t st, const unsigned long long* d_n = nullptr) {
   const int64_t nb = ceil_div(n > 0 ? n : 1, kScanTile);
   hipLaunchKernelGGL(k_scan_reduce<In>, dim3((uint32_t)nb), dim3(kScanThreads), 0, st, in, n, d_n, partial);
+  if (nb <= 1024) {
+    hipLaunchKernelGGL((k_scan_down<In, true>), dim3((uint32_t)nb), dim3(kScanThreads), 0, st, in, n, d_n,
+                       (const unsigned long long*)partial, out, nb, total);
+    return;
+  }
   hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, partial, nb, total);
-  hipLaunchKernelGGL(k_scan_down<In>, dim3((uint32_t)nb), dim3(kScanThreads), 0, st, in, n, d_n,
-                     (const unsigned long long*)partial, out);
+  hipLaunchKernelGGL((k_scan_down<In, false>), dim3((uint32_t)nb), dim3(kScanThreads), 0, st, in, n, d_n,
+                     (const unsigned long long*)partial, out, nb, total);
 }
 
 inline size_t scan_partial_count(int64_t n) { return (size_t)ceil_div(n > 0 ? n : 1, kScanTile); }
