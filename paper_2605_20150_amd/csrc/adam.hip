@@ -56,45 +56,6 @@ __global__ void __launch_bounds__(256) k_adam_cols(T* __restrict__ params, T* __
   params[o] -= K.lr[j] * (m * (T)bc.x) / (Mth<T>::sqrt(v) * (T)bc.y + K.eps);
 }
 
-// The same update with four consecutive rows of one column per thread
-// (single precision, block_rows a multiple of 4): 16-byte loads and stores of
-// p, m and v, and nothing touched where none of the four rows is active.
-// Inactive rows among the four are written back with the values just read.
-__global__ void __launch_bounds__(256) k_adam_cols4(float* __restrict__ params, float* __restrict__ m1,
-                                                    float* __restrict__ m2, const int32_t* __restrict__ order,
-                                                    int32_t B, int64_t n_pidx, const uint32_t* __restrict__ active,
-                                                    const uint32_t* __restrict__ act_idx,
-                                                    const float* __restrict__ grad, int64_t ld, AdamK<float> K,
-                                                    const float2* __restrict__ bias) {
-  const int64_t i0 = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
-  const int j = blockIdx.y;
-  if (i0 >= n_pidx) return;
-  const uint4 a = *reinterpret_cast<const uint4*>(active + i0);
-  if (!(a.x | a.y | a.z | a.w)) return;
-  const int64_t k = i0 / B;
-  const int32_t row = (int32_t)(i0 - k * B);
-  const int64_t o = ((int64_t)order[k] * kD + j) * B + row;
-  float4 P = *reinterpret_cast<const float4*>(params + o);
-  float4 M = *reinterpret_cast<const float4*>(m1 + o);
-  float4 V = *reinterpret_cast<const float4*>(m2 + o);
-  const float lr = K.lr[j];
-  auto upd = [&](uint32_t act, int64_t i, float& p, float& m, float& v) {
-    if (!act) return;
-    const float g = grad[(int64_t)act_idx[i] + (int64_t)j * ld];
-    const float2 bc = bias[i];
-    m = K.b1 * m + (1.f - K.b1) * g;
-    v = K.b2 * v + (1.f - K.b2) * g * g;
-    p -= lr * (m * bc.x) / (Mth<float>::sqrt(v) * bc.y + K.eps);
-  };
-  upd(a.x, i0, P.x, M.x, V.x);
-  upd(a.y, i0 + 1, P.y, M.y, V.y);
-  upd(a.z, i0 + 2, P.z, M.z, V.z);
-  upd(a.w, i0 + 3, P.w, M.w, V.w);
-  *reinterpret_cast<float4*>(m1 + o) = M;
-  *reinterpret_cast<float4*>(m2 + o) = V;
-  *reinterpret_cast<float4*>(params + o) = P;
-}
-
 // One workgroup covers up to kBoundRows consecutive rows of one block: the
 // rows are reduced in registers and LDS, then a single atomic max per
 // workgroup raises the block radius.
@@ -180,18 +141,10 @@ extern "C" tide_status tide_adam_sparse(tide_pool* pool, const tide_proj* proj, 
     AdamK<float> K;
     for (int j = 0; j < kD; ++j) K.lr[j] = cfg->lr[j];
     K.b1 = cfg->beta1; K.b2 = cfg->beta2; K.eps = cfg->eps; K.kappa = cfg->kappa;
-    const bool vec4 = pool->block_rows % 4 == 0 && aligned16(pool->params) && aligned16(pool->exp_avg) &&
-                      aligned16(pool->exp_avg_sq) && aligned16(proj->active);
-    if (vec4)
-      TIDE_TIMED("adam", st, hipLaunchKernelGGL(k_adam_cols4, dim3((uint32_t)ceil_div(n, 1024), kD), dim3(256), 0,
-                                                st, (float*)pool->params, (float*)pool->exp_avg,
-                                                (float*)pool->exp_avg_sq, pool->order, pool->block_rows, n,
-                                                proj->active, proj->act_idx, (const float*)grad, grad_ld, K, bias));
-    else
-      TIDE_TIMED("adam", st, hipLaunchKernelGGL(k_adam_cols<float>, dim3(gx, kD), dim3(256), 0, st,
-                                                (float*)pool->params, (float*)pool->exp_avg,
-                                                (float*)pool->exp_avg_sq, pool->order, pool->block_rows, n,
-                                                proj->active, proj->act_idx, (const float*)grad, grad_ld, K, bias));
+    TIDE_TIMED("adam", st, hipLaunchKernelGGL(k_adam_cols<float>, dim3(gx, kD), dim3(256), 0, st,
+                                              (float*)pool->params, (float*)pool->exp_avg, (float*)pool->exp_avg_sq,
+                                              pool->order, pool->block_rows, n, proj->active, proj->act_idx,
+                                              (const float*)grad, grad_ld, K, bias));
     if (spheres || dirty)
       hipLaunchKernelGGL(k_adam_bounds<float>, dim3(gb), dim3(256), 0, st, (const float*)pool->params, pool->order,
                          pool->slot_block, pool->block_rows, n, proj->active, cfg->kappa, spheres, dirty);
