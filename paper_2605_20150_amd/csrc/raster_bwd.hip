@@ -199,7 +199,6 @@ __global__ void __launch_bounds__(64) k_reduce_pairs(const uint32_t* __restrict_
   const int np = (int)(n_vis - s0 < kWave ? n_vis - s0 : kWave);
   __shared__ uint32_t s_off[kWave + 1];
   __shared__ T s_acc[kWave][kG2];
-  __shared__ T s_in[kWave * kG2];   // the chunk's 64 partials, loaded as 9 coalesced rows
   if (lane <= np) s_off[lane] = inst_off[s0 + lane];
   if (lane == 0 && np == kWave) s_off[kWave] = inst_off[s0 + kWave];
 #pragma unroll
@@ -216,19 +215,10 @@ __global__ void __launch_bounds__(64) k_reduce_pairs(const uint32_t* __restrict_
       else hi = mid;
     }
     const int p = valid ? lo : -1;
-    // the chunk's partials are contiguous: load them as 9 runs of 64
-    // consecutive values, then read each lane's 9 from LDS (stride 9 is
-    // free of bank conflicts)
-    const int64_t c0 = (int64_t)base * kG2, c1 = (int64_t)e1 * kG2;
-#pragma unroll
-    for (int m = 0; m < kG2; ++m) {
-      const int64_t q = c0 + m * kWave + lane;
-      s_in[m * kWave + lane] = q < c1 ? partial[q] : (T)0;
-    }
-    __syncthreads();
     T v[kG2];
+    const T* P = partial + (int64_t)(valid ? e : e0) * kG2;
 #pragma unroll
-    for (int m = 0; m < kG2; ++m) v[m] = valid ? s_in[lane * kG2 + m] : (T)0;
+    for (int m = 0; m < kG2; ++m) v[m] = valid ? P[m] : (T)0;
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) {
       const int pn = __shfl_up(p, off, kWave);
