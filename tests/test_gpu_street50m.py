@@ -170,4 +170,5 @@ def test_street_50m_rates_crop_gradient_and_finite_differences():
         worst = max(worst, err / (abs(fd) + 1e-12))
         assert err <= 1e-4 * abs(fd) + 1e-6, (i, j, gsel[a, j], fd)
         done += 1
-    say(f"64 FP64 samples within 1e-4 relative (worst {worst:.2e}); {replaced} replaced for a decision flip")
+    say(f"64 FP64 samples within 1e-4 |fd| + 1e-6 (largest relative error {worst:.2e}, at a small |fd|); "
+        f"{replaced} replaced for a decision flip")
