@@ -197,6 +197,46 @@ def test_dense_scene_end_to_end_matches_oracle():
     assert err.max() <= 1e-4
 
 
+def long_list_case():
+    """70 000 wide, faint Gaussians in front of a 70x45 camera (5 x 3 tiles,
+    the last column and row ragged): every footprint covers the whole image,
+    so every tile's list is longer than 2^16 entries; opacities sit around
+    the 1/255 floor (about a quarter below it), so pixels walk a few thousand
+    entries, 64 at a time, before T < 1e-4."""
+    n = 70000
+    th = synth.dense_scene(n, 31, extent=1.0, logscale_mu=0.2, logscale_sigma=0.2)
+    rng = np.random.Generator(np.random.PCG64(32))
+    th[:, 10] = rng.normal(-5.2, 0.5, size=n).astype(np.float32)
+    cams = [synth.look_at((0.0, 0.0, -3.0), (0, 0, 0), (0, -1, 0), 70, 45, 60.0)]
+    return th, cams
+
+
+def test_lists_longer_than_two_to_the_sixteen():
+    say("case: 70000 Gaussians covering a 70x45 image (lists > 65536 entries), forward and backward")
+    th, cams = long_list_case()
+    cm = synth.cams_array(cams)
+    th64 = th.astype(np.float64)
+    ref = oracle.render(th64, cm)
+    rast, pool, proj, bins, fr = gpu_forward(th, cams, block_rows=4096)
+    b = bins_views(rast, bins)
+    lens = (b["ranges"][:, 1] - b["ranges"][:, 0]).cpu().numpy()
+    say(f"list lengths {int(lens.min())}..{int(lens.max())}, last up to {int(fr.last.max())}")
+    assert lens.min() > 65536
+    tie = near_tie_pixels(ref)
+    err = np.abs(fr.image.double().cpu().numpy() - ref["image"]).max(axis=1)
+    say(f"near-tie pixels {int(tie.sum())} of {tie.size}; image max-abs error {err[~tie].max():.3e}")
+    assert err[~tie].max() <= 1e-4
+    assert int(fr.visits_bwd.sum()) == int(fr.last.sum(dtype=torch.int64))
+    W = np.random.Generator(np.random.PCG64(33)).normal(size=ref["image"].shape)
+    g_ref = oracle.backward(th64, cm, W)
+    g = rast.backward(pool, cams, proj, bins, fr, torch.tensor(W, dtype=torch.float32, device="cuda"))
+    gd = dense_grad(proj, g, th.shape[0]).double().cpu().numpy()
+    tie_rows = (ref["pair_margin"] < NEAR_TIE).any(axis=0)
+    say(f"near-tie rows {int(tie_rows.sum())} of {th.shape[0]}")
+    assert (~tie_rows).sum() > 0.5 * th.shape[0]
+    assert_grad_close(gd[~tie_rows], g_ref[~tie_rows])
+
+
 def test_empty_and_degenerate_inputs():
     say("case: all Gaussians behind the camera; zero opacity")
     theta, cams, _ = synth.tiny_workload()
