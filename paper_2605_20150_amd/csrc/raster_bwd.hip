@@ -264,41 +264,22 @@ __global__ void __launch_bounds__(128) k_adjoint(const T* __restrict__ params, c
   const T mu0 = P[0], mu1 = P[B], mu2 = P[2 * (int64_t)B];
   const T s0 = Mth<T>::exp(P[3 * (int64_t)B]), s1 = Mth<T>::exp(P[4 * (int64_t)B]),
           s2 = Mth<T>::exp(P[5 * (int64_t)B]);
-  const T qw0 = P[6 * (int64_t)B], qx0 = P[7 * (int64_t)B], qy0 = P[8 * (int64_t)B], qz0 = P[9 * (int64_t)B];
-  const T qn = Mth<T>::sqrt(qw0 * qw0 + qx0 * qx0 + qy0 * qy0 + qz0 * qz0);
-  const T iq = (T)1 / qn;
-  const T qw = qw0 * iq, qx = qx0 * iq, qy = qy0 * iq, qz = qz0 * iq;
+  // Pass 1 over the cameras: colour (SH and the viewing direction) and
+  // opacity.  The 48 SH sums are stored before pass 2, so the two passes'
+  // registers need not be live together (320 -> 249 VGPRs: two waves per
+  // SIMD instead of one).
   const T op = (T)1 / ((T)1 + Mth<T>::exp(-P[10 * (int64_t)B]));
-  const T Rq[9] = {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy),
-                   2 * (qx * qy + qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qw * qx),
-                   2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)};
-  const T sv[3] = {s0, s1, s2};
-  T M[9];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) M[3 * a + b] = Rq[3 * a + b] * sv[b];
-  T Sg[9];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) Sg[3 * a + b] = M[3 * a] * M[3 * b] + M[3 * a + 1] * M[3 * b + 1] + M[3 * a + 2] * M[3 * b + 2];
-
   T gsh[48];
 #pragma unroll
   for (int m = 0; m < 48; ++m) gsh[m] = 0;
   T dmu0 = 0, dmu1 = 0, dmu2 = 0, dlogit = 0;
-  T dSig[9];
-#pragma unroll
-  for (int m = 0; m < 9; ++m) dSig[m] = 0;
-
 #pragma unroll 1
   for (int c = 0; c < cs.n; ++c) {
     const int64_t o = (int64_t)c * n_pidx + i;
     if (tt[o] == 0) continue;
     const DevCam<T>& cm = cs.c[c];
     const T* G2 = g2d + o * kG2;
-    const T gu = G2[0], gv = G2[1], gA = G2[2], gB = G2[3], gC = G2[4], gop = G2[5];
+    const T gop = G2[5];
     const T gcol[3] = {G2[6], G2[7], G2[8]};
     // ---- colour
     T dx = mu0 - cm.pos[0], dy = mu1 - cm.pos[1], dz = mu2 - cm.pos[2];
@@ -351,8 +332,44 @@ __global__ void __launch_bounds__(128) k_adjoint(const T* __restrict__ params, c
       dmu1 += (gy - dd * y) * il;
       dmu2 += (gz - dd * z) * il;
     }
-    // ---- opacity
     dlogit += gop * op * ((T)1 - op);
+  }
+  const int64_t a = act_idx[i];
+  T* G = grad + a;
+  G[10 * ld] = dlogit;
+#pragma unroll
+  for (int m = 0; m < 48; ++m) G[(int64_t)(11 + m) * ld] = gsh[m];
+
+  // Pass 2: geometry (mean through the projection, covariance)
+  const T qw0 = P[6 * (int64_t)B], qx0 = P[7 * (int64_t)B], qy0 = P[8 * (int64_t)B], qz0 = P[9 * (int64_t)B];
+  const T qn = Mth<T>::sqrt(qw0 * qw0 + qx0 * qx0 + qy0 * qy0 + qz0 * qz0);
+  const T iq = (T)1 / qn;
+  const T qw = qw0 * iq, qx = qx0 * iq, qy = qy0 * iq, qz = qz0 * iq;
+  const T Rq[9] = {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy),
+                   2 * (qx * qy + qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qw * qx),
+                   2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)};
+  const T sv[3] = {s0, s1, s2};
+  T M[9];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) M[3 * a + b] = Rq[3 * a + b] * sv[b];
+  T Sg[9];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) Sg[3 * a + b] = M[3 * a] * M[3 * b] + M[3 * a + 1] * M[3 * b + 1] + M[3 * a + 2] * M[3 * b + 2];
+
+  T dSig[9];
+#pragma unroll
+  for (int m = 0; m < 9; ++m) dSig[m] = 0;
+#pragma unroll 1
+  for (int c = 0; c < cs.n; ++c) {
+    const int64_t o = (int64_t)c * n_pidx + i;
+    if (tt[o] == 0) continue;
+    const DevCam<T>& cm = cs.c[c];
+    const T* G2 = g2d + o * kG2;
+    const T gu = G2[0], gv = G2[1], gA = G2[2], gB = G2[3], gC = G2[4];
     // ---- geometry: recompute p, J, T, Sigma', conic
     const T px = cm.R[0] * mu0 + cm.R[1] * mu1 + cm.R[2] * mu2 + cm.t[0];
     const T py = cm.R[3] * mu0 + cm.R[4] * mu1 + cm.R[5] * mu2 + cm.t[1];
@@ -443,17 +460,12 @@ __global__ void __launch_bounds__(128) k_adjoint(const T* __restrict__ params, c
   dq[2] = 2 * (-2 * y * g9[0] + x * g9[1] + w * g9[2] + x * g9[3] + z * g9[5] - w * g9[6] + z * g9[7] - 2 * y * g9[8]);
   dq[3] = 2 * (-2 * z * g9[0] - w * g9[1] + x * g9[2] + w * g9[3] - 2 * z * g9[4] + y * g9[5] + x * g9[6] + y * g9[7]);
   const T dqq = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
-  const int64_t a = act_idx[i];
-  T* G = grad + a;
   G[0] = dmu0; G[ld] = dmu1; G[2 * ld] = dmu2;
   G[3 * ld] = gls[0]; G[4 * ld] = gls[1]; G[5 * ld] = gls[2];
   G[6 * ld] = (dq[0] - dqq * w) * iq;
   G[7 * ld] = (dq[1] - dqq * x) * iq;
   G[8 * ld] = (dq[2] - dqq * y) * iq;
   G[9 * ld] = (dq[3] - dqq * z) * iq;
-  G[10 * ld] = dlogit;
-#pragma unroll
-  for (int m = 0; m < 48; ++m) G[(int64_t)(11 + m) * ld] = gsh[m];
 }
 
 template <typename T>
