@@ -50,14 +50,18 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-blobs", type=int, default=200)
     ap.add_argument("--per-blob", type=int, default=5000)
-    ap.add_argument("--workload", choices=["aerial", "city", "city-ablation", "city-budget", "city-order"],
+    ap.add_argument("--workload", choices=["aerial", "city", "city-ablation", "city-budget", "city-order",
+                                           "layout"],
                     default="aerial",
                     help="aerial: resident training (default); city: out-of-core street city, exact-only "
                          "streaming against predictor-hinted streaming; city-ablation: the same city "
                          "without differential streaming, without overlap and without the Morton layout; "
                          "city-budget: a binding block budget with persisted and with cold-restarted moments; "
                          "city-order: one pass over a fixed street view set in capture, shuffled and clustered "
-                         "travelling-salesperson order")
+                         "travelling-salesperson order; layout: the out-of-core Morton layout build of a "
+                         "street city from a table file")
+    ap.add_argument("--layout-blocks", type=int, default=477, help="blocks of 65536 for --workload layout")
+    ap.add_argument("--layout-run-rows", type=int, default=1 << 22, help="rows per sorted run")
     ap.add_argument("--budget-blocks", type=int, default=160, help="C for --workload city-budget")
     ap.add_argument("--budget-zfar", type=float, default=1000.0, help="z_far for --workload city-budget")
     ap.add_argument("--city-blocks", type=int, default=954, help="blocks of 65536 Gaussians (954 = 1 km^2)")
@@ -362,6 +366,56 @@ def order_main(args):
     print(json.dumps(out), flush=True)
 
 
+def layout_main(args):
+    """The layout build of Sec. 3.3 and 4.1 out of core: a street city's
+    table (generation order) on disk, sorted runs of --layout-run-rows rows,
+    a k-way merge into the base segment with the block spheres.  Checks two
+    blocks against the in-memory Morton order of the same centres."""
+    import shutil
+
+    import numpy as np
+
+    from paper_2605_20150_amd import city as CT
+    from paper_2605_20150_amd import predictor as P
+    from paper_2605_20150_amd.raster import Pool
+    from paper_2605_20150_amd.tier import Tier
+
+    B = 65536
+    n_blocks = args.layout_blocks
+    extent = 1000.0 * (n_blocks / 954.0) ** 0.5
+    root = args.city_dir
+    shutil.rmtree(root, ignore_errors=True)
+    os.makedirs(root)
+    table = os.path.join(root, "table.f32")
+    N, _, t_table = CT.write_table(table, n_blocks, B, 30, extent, log=log)
+    log(f"layout: table of {N} rows ({N * 236 / 1e9:.1f} GB) written in {t_table:.1f} s")
+    tier = Tier(os.path.join(root, "store"), N, Pool.empty(1, B, "cpu"), 1, 4, io_threads=1, host_pool=True,
+                odirect=True)
+    t0 = time.perf_counter()
+    tier.layout_build(table, root, args.layout_run_rows)
+    t_build = time.perf_counter() - t0
+    log(f"layout: built in {t_build:.1f} s")
+    # the same order in memory, for two blocks
+    th = np.memmap(table, dtype=np.float32, mode="r", shape=(N, 59))
+    perm = P.morton_order(np.ascontiguousarray(th[:, :3]))
+    same = all(np.array_equal(tier.read_block(k)["params"], th[perm[k * B:(k + 1) * B]].T) for k in (0, n_blocks - 1))
+    tier.close()
+    del th
+    shutil.rmtree(root, ignore_errors=True)
+    rate = N / t_build
+    out = {
+        "metric": METRIC, "value": round(rate / 1e6, 3), "unit": "M Gaussians/s laid out", "n_gpus": 1, "steps": 1,
+        "warmup": 0, "ms_per_step": round(1e3 * t_build, 1), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"out-of-core Morton layout build, street city of {N} Gaussians ({n_blocks} blocks "
+                               f"x {B}), runs of {args.layout_run_rows} rows, O_DIRECT base segment",
+                   "gaussians": N, "blocks": n_blocks, "run_rows": args.layout_run_rows, "parallelism": "host"},
+        "table_write_s": round(t_table, 1), "build_s": round(t_build, 1),
+        "blocks_match_in_memory_order": bool(same),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def city_main(args):
     """Out-of-core street city: the same held-out walk trained from the same
     store with exact-culling-only streaming and with the predictor's hints."""
@@ -440,6 +494,8 @@ def main():
         return budget_main(args)
     if args.workload == "city-order":
         return order_main(args)
+    if args.workload == "layout":
+        return layout_main(args)
     import numpy as np
     import torch
 

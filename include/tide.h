@@ -391,7 +391,9 @@ tide_status tide_view_order(const tide_camera* cams, int64_t n, int32_t cluster_
                             int32_t* perm);
 
 /* Layout build (Sec. 3.3, 4.1): writes block k's record to the base segment
- * with zero moments and steps.  params: host f32 [59][rows of block k].
+ * with zero moments and steps (only the parameters are written; the new
+ * segment's moments and steps are holes that read as zeros).  params: host
+ * f32 [59][rows of block k].
  * Computes the block's sphere: c_k = mean of the member means (fixed),
  * r_k = max |mu_i - c_k| + 3 kappa max exp(log-scale_i). */
 tide_status tide_store_put_block(tide_residency* res, int64_t block, const float* params);

@@ -67,6 +67,23 @@ def build_store(directory: str, n_blocks: int, B: int, seed: int, extent: float,
     return N, city, spheres, time.perf_counter() - t0
 
 
+def write_table(path: str, n_blocks: int, B: int, seed: int, extent: float, log=print):
+    """Writes the city's n_blocks * B Gaussians in generation order (no
+    layout) as an f32 [N][59] table file, B rows at a time; returns
+    (N, City, seconds).  The input of the out-of-core layout build."""
+    t0 = time.perf_counter()
+    N = n_blocks * B
+    mu, city = synth.city_means(N, seed, extent)
+    with open(path, "wb") as f:
+        for k in range(n_blocks):
+            blk = synth.block_attributes(seed, k, B)
+            blk[:, 0:3] = mu[k * B:(k + 1) * B]
+            f.write(np.ascontiguousarray(blk, dtype=np.float32).tobytes())
+            if k % 100 == 99:
+                log(f"table: {k + 1}/{n_blocks} chunks written, {time.perf_counter() - t0:.1f} s")
+    return N, city, time.perf_counter() - t0
+
+
 def walk_batches(city, seed: int, n_iters: int, z_far: float, width: int, height: int):
     cams = synth.street_walk(city, 4 * n_iters, seed, width=width, height=height, z_far=z_far)
     return [cams[4 * t:4 * t + 4] for t in range(n_iters)]

@@ -279,6 +279,7 @@ extern "C" tide_status tide_layout_build(tide_residency* res, const char* table_
       cleanup();
       return io_fail("short read of the run", names[r]);
     }
+  std::vector<float> rm((size_t)block_rows * kCols59);    // the block's rows, row-major
   std::vector<float> blk((size_t)block_rows * kCols59);   // [59][rows of the block]
   int64_t done = 0, block = 0;
   while (done < n_rows) {
@@ -291,14 +292,18 @@ extern "C" tide_status tide_layout_build(tide_residency* res, const char* table_
       }
       const int32_t r = heap.top().second;
       heap.pop();
-      float p[kCols59];
-      std::memcpy(p, cur[r] + 16, kRowBytes);
-      for (int j = 0; j < kCols59; ++j) blk[(size_t)j * rows_k + i] = p[j];
+      std::memcpy(&rm[(size_t)i * kCols59], cur[r] + 16, kRowBytes);
       if (!push(r)) {
         cleanup();
         return io_fail("short read of the run", names[r]);
       }
       ++done;
+    }
+    // row-major -> column-major in 64-row tiles (cache-friendly)
+    for (int64_t i0 = 0; i0 < rows_k; i0 += 64) {
+      const int64_t i1 = std::min<int64_t>(rows_k, i0 + 64);
+      for (int j = 0; j < kCols59; ++j)
+        for (int64_t i = i0; i < i1; ++i) blk[(size_t)j * rows_k + i] = rm[(size_t)i * kCols59 + j];
     }
     const tide_status st = tide_store_put_block(res, block, blk.data());
     if (st != TIDE_OK) {

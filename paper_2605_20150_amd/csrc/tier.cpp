@@ -82,7 +82,8 @@ class LogStore {
     ::mkdir(dir.c_str(), 0755);
     int fd = open_seg(0, true);
     if (fd < 0) return fail("cannot create the base segment");
-    if (::ftruncate(fd, (off_t)(rec * K)) != 0) return fail("cannot size the base segment");
+    // emptied first: records are written as parameters over holes (zeros)
+    if (::ftruncate(fd, 0) != 0 || ::ftruncate(fd, (off_t)(rec * K)) != 0) return fail("cannot size the base segment");
     fds.assign(1, fd);
     index.resize(K);
     for (int64_t k = 0; k < K; ++k) index[k] = IndexEntry{0, 0, (int64_t)(k * rec), (int64_t)rec, 0};
@@ -115,14 +116,21 @@ class LogStore {
     return buf.get();
   }
 
-  tide_status write_base(int64_t k, const void* src) {
-    if (odirect) {
+  // Writes the first n bytes of block k's base record (the rest of the
+  // record stays as it is: a hole, i.e. zeros, in a new base segment).
+  tide_status write_base(int64_t k, const void* src, size_t n) {
+    if (odirect && (reinterpret_cast<uintptr_t>(src) & 4095u) != 0) {
       char* b = bounce();
       if (!b) return fail("out of host memory for a direct-I/O buffer");
-      std::memcpy(b, src, rec);
+      std::memcpy(b, src, n);
       src = b;
     }
-    if (::pwrite(fds[0], src, rec, (off_t)(k * rec)) != (ssize_t)rec) return fail("base write failed");
+    size_t put = 0;
+    while (put < n) {
+      const ssize_t w = ::pwrite(fds[0], (const char*)src + put, n - put, (off_t)(k * rec + put));
+      if (w <= 0) return fail("base write failed");
+      put += (size_t)w;
+    }
     return TIDE_OK;
   }
 
@@ -400,8 +408,10 @@ struct tide_residency {
   bool compute_recorded = false, bounds_pending = false;
   tide_tier_stats st{};
 
+  char* put_buf = nullptr;   // layout-build staging record (4 KiB aligned, reused)
   ~tide_residency() {
     delete io;
+    std::free(put_buf);
     for (auto& e : ent) free_host(e.buf);
     free_host((char*)h_spheres_stage);
     free_host((char*)h_dirty_stage);
@@ -804,18 +814,23 @@ tide_status tide_store_put_block(tide_residency* res, int64_t block, const float
     if (c != TIDE_OK) return c;
   }
   const int64_t rows = std::min<int64_t>(res->B, res->N - block * (int64_t)res->B);
-  std::vector<char> buf(res->rec, 0);
-  float* P = (float*)buf.data();
-  for (int j = 0; j < kCols; ++j) std::memcpy(P + (size_t)j * res->B, params + (size_t)j * rows, rows * sizeof(float));
-  block_sphere(P, res->B, rows, res->kappa, &res->h_spheres[4 * block]);
-  if (res->store.odirect) {
-    char* al = res->alloc_host(res->rec);
-    std::memcpy(al, buf.data(), res->rec);
-    const tide_status r = res->store.write_base(block, al);
-    res->free_host(al);
-    return r;
+  // one 4 KiB-aligned record reused across blocks (written directly with
+  // O_DIRECT); moments and steps stay zero, the column tails are cleared
+  if (!res->put_buf) {
+    void* raw = nullptr;
+    if (posix_memalign(&raw, 4096, res->rec) != 0) return LogStore::fail("out of host memory for the layout build");
+    res->put_buf = (char*)raw;
+    std::memset(res->put_buf, 0, res->rec);
   }
-  return res->store.write_base(block, buf.data());
+  float* P = (float*)res->put_buf;
+  for (int j = 0; j < kCols; ++j) {
+    std::memcpy(P + (size_t)j * res->B, params + (size_t)j * rows, rows * sizeof(float));
+    if (rows < res->B) std::memset(P + (size_t)j * res->B + rows, 0, (size_t)(res->B - rows) * sizeof(float));
+  }
+  block_sphere(P, res->B, rows, res->kappa, &res->h_spheres[4 * block]);
+  // zero moments and steps are the new base segment's holes: only the
+  // parameters are written (a third of the record)
+  return res->store.write_base(block, res->put_buf, res->pbytes);
 }
 
 static tide_status upload_spheres(tide_residency* res) {
