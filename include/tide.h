@@ -172,9 +172,13 @@ typedef struct {
 size_t tide_bin_sort_ws_bytes(int32_t n_cams, int64_t n_pidx, int32_t tiles_x, int32_t tiles_y,
                               int64_t n_inst_cap);
 
-/* Blocks once: it reads the visible-pair and instance counts back to the
- * host.  On TIDE_ECAPACITY, out->ws_required holds the size to retry with
- * (the projection records are unchanged and may be reused). */
+/* Blocks once, until the visible-pair and instance counts have reached the
+ * host; the rest of the binning is queued before that wait (sized by the
+ * workspace's instance capacity, reading the counts on the device), so the
+ * GPU keeps working meanwhile.  The counts go through a pinned host slot
+ * allocated on the first call, one per device, which concurrent calls on a
+ * device take in turn.  On TIDE_ECAPACITY, out->ws_required holds the size
+ * to retry with (the projection records are unchanged and may be reused). */
 tide_status tide_bin_sort(const tide_proj* proj, int32_t tiles_x, int32_t tiles_y, void* ws,
                           size_t ws_bytes, tide_bins* out, void* stream);
 

@@ -33,11 +33,6 @@ struct NonzeroIn {
   const uint32_t* a;
   __device__ uint32_t operator()(int64_t i) const { return a[i] != 0u ? 1u : 0u; }
 };
-struct GatherIn {  // a[idx[i]]
-  const uint32_t* a;
-  const uint32_t* idx;
-  __device__ uint32_t operator()(int64_t i) const { return a[idx[i]]; }
-};
 
 // Element counts: n_max bounds the launch; when d_n is given the kernels
 // read the actual count from device memory (n = min(n_max, *d_n)), which
@@ -150,7 +145,8 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint32_t* 
                                                                 const uint32_t* vals_in, int64_t n_max,
                                                                 const unsigned long long* d_n, int shift,
                                                                 const uint32_t* gofs, int64_t nb,
-                                                                uint32_t* keys_out, uint32_t* vals_out);
+                                                                uint32_t* keys_out, uint32_t* vals_out,
+                                                                const uint32_t* gather_src, uint32_t* gather_out);
 
 inline size_t radix_hist_count(int64_t n) { return 256 * (size_t)ceil_div(n > 0 ? n : 1, kSortTile); }
 
@@ -159,10 +155,13 @@ inline size_t radix_hist_count(int64_t n) { return 256 * (size_t)ceil_div(n > 0 
 // the input indices and va is only used as storage.  Buffers (ka, va) and
 // (kb, vb) ping-pong; the sorted result pointers are returned through
 // *keys_res / *vals_res.  hist needs radix_hist_count(n) u32, partial
-// scan_partial_count(radix_hist_count(n)) u64, total one u64.
+// scan_partial_count(radix_hist_count(n)) u64, total one u64.  With
+// gather_src, the last pass also writes gather_out[j] = gather_src[value j]
+// for every sorted position j.
 void radix_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int64_t n, int bits,
                       bool identity_vals, uint32_t* hist, unsigned long long* partial,
                       unsigned long long* total, hipStream_t st, uint32_t** keys_res,
-                      uint32_t** vals_res, const unsigned long long* d_n = nullptr);
+                      uint32_t** vals_res, const unsigned long long* d_n = nullptr,
+                      const uint32_t* gather_src = nullptr, uint32_t* gather_out = nullptr);
 
 }  // namespace tide

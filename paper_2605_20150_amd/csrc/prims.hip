@@ -52,7 +52,8 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint32_t* 
                                                                 const uint32_t* vals_in, int64_t n_max,
                                                                 const unsigned long long* d_n, int shift,
                                                                 const uint32_t* gofs, int64_t nb,
-                                                                uint32_t* keys_out, uint32_t* vals_out) {
+                                                                uint32_t* keys_out, uint32_t* vals_out,
+                                                                const uint32_t* gather_src, uint32_t* gather_out) {
   const int64_t n = dev_count(n_max, d_n);
   const int64_t b0 = (int64_t)blockIdx.x * kSortTile;
   if (b0 >= n) return;
@@ -123,15 +124,18 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint32_t* 
     const uint32_t k = skey[j];
     const uint32_t dd = (k >> shift) & 255u;
     const uint32_t pos = gbase[dd] + (uint32_t)j - lstart[dd];
+    const uint32_t v = sval[j];
     keys_out[pos] = k;
-    vals_out[pos] = sval[j];
+    vals_out[pos] = v;
+    if (gather_src) gather_out[pos] = gather_src[v];
   }
 }
 
 void radix_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int64_t n, int bits,
                       bool identity_vals, uint32_t* hist, unsigned long long* partial,
                       unsigned long long* total, hipStream_t st, uint32_t** keys_res,
-                      uint32_t** vals_res, const unsigned long long* d_n) {
+                      uint32_t** vals_res, const unsigned long long* d_n, const uint32_t* gather_src,
+                      uint32_t* gather_out) {
   uint32_t *ki = ka, *vi = va, *ko = kb, *vo = vb;
   bool ident = identity_vals;
   const int64_t nb = ceil_div(n > 0 ? n : 1, kSortTile);
@@ -139,8 +143,10 @@ void radix_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, in
     for (int shift = 0; shift < bits; shift += 8) {
       hipLaunchKernelGGL(k_radix_hist, dim3((uint32_t)nb), dim3(kSortThreads), 0, st, ki, n, d_n, shift, hist, nb);
       scan_exclusive(ArrayIn{hist}, 256 * nb, hist, partial, total, st);
+      const bool last = shift + 8 >= bits;
       TIDE_TIMED("radix_scatter", st, hipLaunchKernelGGL(k_radix_scatter, dim3((uint32_t)nb), dim3(kSortThreads), 0, st, ki,
-                         ident ? nullptr : vi, n, d_n, shift, hist, nb, ko, vo));
+                         ident ? nullptr : vi, n, d_n, shift, hist, nb, ko, vo, last ? gather_src : nullptr,
+                         last ? gather_out : nullptr));
       ident = false;
       uint32_t* t = ki; ki = ko; ko = t;
       t = vi; vi = vo; vo = t;

@@ -3,6 +3,7 @@
 // depth/tile radix sort, and front-to-back compositing.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "prims.h"
 #include "raster.h"
@@ -263,46 +264,53 @@ __global__ void k_compact_vis(const uint32_t* __restrict__ tt, const float* __re
 }
 
 // Instances of the depth-ordered visible pairs, each pair's tiles in
-// row-major order.  One wave64 workgroup per 64 consecutive pairs walks their
+// row-major order.  A wave64 workgroup takes 64 consecutive pairs at a time
+// (grid-stride over the pair count read on the device) and walks their
 // contiguous instance range [inst_off[s0], inst_off[s0 + 64]) 64 at a time
 // (coalesced writes); a lane finds its pair by binary search over the 64
 // offsets and its tile from the pair's rectangle.  Balanced whatever the
-// footprint sizes.
+// footprint sizes.  Instances at or past cap are not written (the call then
+// reports the count it needs).
 __global__ void __launch_bounds__(64) k_emit(const uint32_t* __restrict__ vis_rec,
                                              const uint32_t* __restrict__ inst_off,
-                                             const uint32_t* __restrict__ rect, int64_t n_vis, int64_t n_pidx,
-                                             int32_t Tx, int32_t Ty, uint32_t* __restrict__ tkey,
+                                             const uint32_t* __restrict__ rect, int64_t nv_max,
+                                             const unsigned long long* __restrict__ d_nvis, int64_t cap,
+                                             int64_t n_pidx, int32_t Tx, int32_t Ty, uint32_t* __restrict__ tkey,
                                              uint32_t* __restrict__ inst_rec) {
   const int lane = threadIdx.x;
-  const int64_t s0 = (int64_t)blockIdx.x * kWave;
-  const int np = (int)(n_vis - s0 < kWave ? n_vis - s0 : kWave);
+  const int64_t n_vis = dev_count(nv_max, d_nvis);
   __shared__ uint32_t s_off[kWave + 1];
   __shared__ uint32_t s_rec[kWave], s_base[kWave], s_x0[kWave], s_w[kWave];
-  if (lane <= np) s_off[lane] = inst_off[s0 + lane];
-  if (lane == 0 && np == kWave) s_off[kWave] = inst_off[s0 + kWave];
-  if (lane < np) {
-    const uint32_t r = vis_rec[s0 + lane];
-    const uint32_t c = (uint32_t)(r / (uint64_t)n_pidx);
-    const uint32_t a = rect[2 * (int64_t)r], b = rect[2 * (int64_t)r + 1];
-    const uint32_t x0 = a & 0xffff, y0 = a >> 16, x1 = b & 0xffff;
-    s_rec[lane] = r;
-    s_x0[lane] = x0;
-    s_w[lane] = x1 - x0;
-    s_base[lane] = c * (uint32_t)(Tx * Ty) + y0 * (uint32_t)Tx;   // key of the rectangle's first row, column 0
-  }
-  __syncthreads();
-  const uint32_t e0 = s_off[0], e1 = s_off[np];
-  for (uint32_t e = e0 + (uint32_t)lane; e < e1; e += kWave) {
-    int lo = 0, hi = np;   // s_off[lo] <= e < s_off[hi]
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (s_off[mid] <= e) lo = mid;
-      else hi = mid;
+  for (int64_t s0 = (int64_t)blockIdx.x * kWave; s0 < n_vis; s0 += (int64_t)gridDim.x * kWave) {
+    const int np = (int)(n_vis - s0 < kWave ? n_vis - s0 : kWave);
+    if (lane <= np) s_off[lane] = inst_off[s0 + lane];
+    if (lane == 0 && np == kWave) s_off[kWave] = inst_off[s0 + kWave];
+    if (lane < np) {
+      const uint32_t r = vis_rec[s0 + lane];
+      const uint32_t c = (uint32_t)(r / (uint64_t)n_pidx);
+      const uint32_t a = rect[2 * (int64_t)r], b = rect[2 * (int64_t)r + 1];
+      const uint32_t x0 = a & 0xffff, y0 = a >> 16, x1 = b & 0xffff;
+      s_rec[lane] = r;
+      s_x0[lane] = x0;
+      s_w[lane] = x1 - x0;
+      s_base[lane] = c * (uint32_t)(Tx * Ty) + y0 * (uint32_t)Tx;   // key of the rectangle's first row, column 0
     }
-    const uint32_t k = e - s_off[lo], w = s_w[lo];
-    const uint32_t row = k / w, col = k - row * w;
-    tkey[e] = s_base[lo] + row * (uint32_t)Tx + s_x0[lo] + col;
-    inst_rec[e] = s_rec[lo];
+    __syncthreads();
+    const uint32_t e0 = s_off[0];
+    const uint32_t e1 = (int64_t)s_off[np] < cap ? s_off[np] : (uint32_t)cap;
+    for (uint32_t e = e0 + (uint32_t)lane; e < e1; e += kWave) {
+      int lo = 0, hi = np;   // s_off[lo] <= e < s_off[hi]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (s_off[mid] <= e) lo = mid;
+        else hi = mid;
+      }
+      const uint32_t k = e - s_off[lo], w = s_w[lo];
+      const uint32_t row = k / w, col = k - row * w;
+      tkey[e] = s_base[lo] + row * (uint32_t)Tx + s_x0[lo] + col;
+      inst_rec[e] = s_rec[lo];
+    }
+    __syncthreads();
   }
 }
 
@@ -316,18 +324,21 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
   if (i < n) p[i] = v;
 }
 
-__global__ void k_ranges(const uint32_t* __restrict__ key, int64_t n, uint32_t* __restrict__ ranges) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  const uint32_t k = key[j];
-  if (j == 0 || key[j - 1] != k) ranges[2 * (int64_t)k] = (uint32_t)j;
-  if (j == n - 1 || key[j + 1] != k) ranges[2 * (int64_t)k + 1] = (uint32_t)(j + 1);
+// Per-tile [start, end) of the tile-sorted keys; the count is read on the
+// device (grid-stride).
+__global__ void k_ranges(const uint32_t* __restrict__ key, int64_t n_max, const unsigned long long* __restrict__ d_n,
+                         uint32_t* __restrict__ ranges) {
+  const int64_t n = dev_count(n_max, d_n);
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t k = key[j];
+    if (j == 0 || key[j - 1] != k) ranges[2 * (int64_t)k] = (uint32_t)j;
+    if (j == n - 1 || key[j + 1] != k) ranges[2 * (int64_t)k + 1] = (uint32_t)(j + 1);
+  }
 }
 
 // Launch order of the compositing kernels: tiles by descending list length
 // (ties in tile order), so that the longest lists start first and the tail
-// of the launch is made of short ones.  Key = 2^24 - 1 - min(length, 2^24 - 1).
-// Launch-order key of a tile: its list length on a log scale with 16 steps
+// of the launch is made of short ones.  Launch-order key of a tile: its list length on a log scale with 16 steps
 // per octave (the leading bit's position and the next four bits of len + 1),
 // longest first; lengths of 2^16 and more share the first bucket.  One 8-bit
 // radix pass orders them; ties keep tile order.
@@ -547,6 +558,22 @@ extern "C" tide_status tide_preprocess(const tide_pool* pool, const tide_camera*
                                  : preprocess_t<double>(pool, cams, n_cams, out, ws, st);
 }
 
+// Pinned host slot for the binning's counts and the event that marks their
+// arrival, one per device; calls on one device take turns on it.  Allocated
+// on first use and kept for the life of the process.
+struct CountSlot {
+  std::mutex mu;
+  unsigned long long* host = nullptr;
+  hipEvent_t ev = nullptr;
+};
+
+static CountSlot& count_slot() {
+  static CountSlot slots[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  return slots[dev];
+}
+
 extern "C" size_t tide_bin_sort_ws_bytes(int32_t n_cams, int64_t n_pidx, int32_t tiles_x, int32_t tiles_y,
                                          int64_t n_inst_cap) {
   return bin_layout(nullptr, n_cams, n_pidx, (int64_t)tiles_x * tiles_y, n_inst_cap).bytes;
@@ -585,51 +612,70 @@ extern "C" tide_status tide_bin_sort(const tide_proj* proj, int32_t tiles_x, int
   // 2. stable sort of the visible pairs by depth; grids are sized by the
   //    upper bound and the kernels read the visible count from the device
   uint32_t *vk, *vrec;
+  //    the last pass also gathers each pair's tile count into depth order
+  //    (into vis_off, free once the compaction has run)
   radix_sort_pairs(L.ka, L.va, L.kb, L.vb, nv, 32, false, L.hist, L.partial, &L.totals[1], st, &vk, &vrec,
-                   &L.totals[0]);
-  // 3. instance offsets in depth order, and the one host read of the counts
-  scan_exclusive(GatherIn{proj->tiles_touched, vrec}, nv, L.inst_off, L.partial, &L.totals[2], st, &L.totals[0]);
+                   &L.totals[0], proj->tiles_touched, L.vis_off);
+  // 3. instance offsets in depth order
+  scan_exclusive(ArrayIn{L.vis_off}, nv, L.inst_off, L.partial, &L.totals[2], st, &L.totals[0]);
   hipLaunchKernelGGL(k_set_end, dim3(1), dim3(1), 0, st, L.inst_off, &L.totals[0], &L.totals[2]);
   TIDE_LAUNCH_CHECK("instance scan");
-  unsigned long long h_tot[3] = {0, 0, 0};
-  TIDE_HIP(hipMemcpyAsync(h_tot, L.totals, 24, hipMemcpyDeviceToHost, st));
-  TIDE_HIP(hipStreamSynchronize(st));
-  const int64_t n_vis = (int64_t)h_tot[0];
-  const int64_t n_inst = (int64_t)h_tot[2];
+  // 4. the counts travel to the host while the rest of the binning is queued
+  //    behind them: those kernels are sized by the instance capacity and read
+  //    the counts on the device, so the GPU does not wait for the host
+  CountSlot& slot = count_slot();
+  std::lock_guard<std::mutex> lk(slot.mu);
+  if (!slot.host) {
+    TIDE_HIP(hipHostMalloc((void**)&slot.host, 4 * sizeof(unsigned long long), hipHostMallocDefault));
+    TIDE_HIP(hipEventCreateWithFlags(&slot.ev, hipEventDisableTiming));
+  }
+  TIDE_HIP(hipMemcpyAsync(slot.host, L.totals, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+  TIDE_HIP(hipEventRecord(slot.ev, st));
+  // 5. emit instances in depth order, keyed by global tile id
+  {
+    const int64_t chunks = ceil_div(nv > 0 ? nv : 1, kWave);
+    TIDE_TIMED("emit", st, hipLaunchKernelGGL(k_emit, dim3((uint32_t)(chunks < 32768 ? chunks : 32768)), dim3(kWave), 0,
+                                              st, vrec, L.inst_off, proj->rect, nv, &L.totals[0], cap, N, tiles_x,
+                                              tiles_y, L.tka, L.inst_rec));
+  }
+  TIDE_LAUNCH_CHECK("k_emit");
+  // 6. stable sort by tile; values are emission indices
+  int bits = 0;
+  while ((1ll << bits) < (int64_t)V * nt) ++bits;
+  bits = bits < 8 ? 8 : bits;
+  uint32_t *tk, *te;
+  radix_sort_pairs(L.tka, L.tva, L.tkb, L.tvb, cap, bits, true, L.hist, L.partial, &L.totals[3], st, &tk, &te,
+                   &L.totals[2]);
+  // 7. per-tile ranges
+  const int64_t nr = 2 * (int64_t)V * nt;
+  hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)ceil_div(nr, 256)), dim3(256), 0, st, L.ranges, nr, 0u);
+  if (cap > 0) {
+    const int64_t nb = ceil_div(cap, 256);
+    hipLaunchKernelGGL(k_ranges, dim3((uint32_t)(nb < 65536 ? nb : 65536)), dim3(256), 0, st, tk, cap, &L.totals[2],
+                       L.ranges);
+  }
+  TIDE_LAUNCH_CHECK("k_ranges");
+  // 8. launch order of the tiles: longest lists first
+  const int64_t ntt = (int64_t)V * nt;
+  hipLaunchKernelGGL(k_tile_keys, dim3((uint32_t)ceil_div(ntt, 256)), dim3(256), 0, st, L.ranges, ntt, L.oka);
+  TIDE_LAUNCH_CHECK("k_tile_keys");
+  uint32_t *ok, *order;
+  radix_sort_pairs(L.oka, L.ova, L.okb, L.ovb, ntt, 8, true, L.hist, L.partial, &L.totals[3], st, &ok, &order);
+  // 9. the counts, once they are on the host
+  TIDE_HIP(hipEventSynchronize(slot.ev));
+  const int64_t n_vis = (int64_t)slot.host[0];
+  const int64_t n_inst = (int64_t)slot.host[2];
+  out->n_vis = n_vis;
+  out->n_inst = n_inst;
   if (n_inst >= (int64_t)UINT32_MAX) {
     set_error("instance count %lld exceeds 32-bit indexing", (long long)n_inst);
     return TIDE_EINVAL;
   }
   if (n_inst > cap) {
     out->ws_required = tide_bin_sort_ws_bytes(V, N, tiles_x, tiles_y, n_inst + n_inst / 8 + 1024);
-    out->n_vis = n_vis;
-    out->n_inst = n_inst;
     set_error("bin_sort needs %lld instances, workspace holds %lld", (long long)n_inst, (long long)cap);
     return TIDE_ECAPACITY;
   }
-  // 4. emit instances in depth order, keyed by global tile id
-  if (n_vis > 0)
-    TIDE_TIMED("emit", st, hipLaunchKernelGGL(k_emit, dim3((uint32_t)ceil_div(n_vis, kWave)), dim3(kWave), 0, st, vrec,
-                                              L.inst_off, proj->rect, n_vis, N, tiles_x, tiles_y, L.tka, L.inst_rec));
-  TIDE_LAUNCH_CHECK("k_emit");
-  // 5. stable sort by tile; values are emission indices
-  int bits = 0;
-  while ((1ll << bits) < (int64_t)V * nt) ++bits;
-  bits = bits < 8 ? 8 : bits;
-  uint32_t *tk, *te;
-  radix_sort_pairs(L.tka, L.tva, L.tkb, L.tvb, n_inst, bits, true, L.hist, L.partial, &L.totals[3], st, &tk, &te);
-  // 6. per-tile ranges
-  const int64_t nr = 2 * (int64_t)V * nt;
-  hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)ceil_div(nr, 256)), dim3(256), 0, st, L.ranges, nr, 0u);
-  if (n_inst > 0)
-    hipLaunchKernelGGL(k_ranges, dim3((uint32_t)ceil_div(n_inst, 256)), dim3(256), 0, st, tk, n_inst, L.ranges);
-  TIDE_LAUNCH_CHECK("k_ranges");
-  // 7. launch order of the tiles: longest lists first
-  const int64_t ntt = (int64_t)V * nt;
-  hipLaunchKernelGGL(k_tile_keys, dim3((uint32_t)ceil_div(ntt, 256)), dim3(256), 0, st, L.ranges, ntt, L.oka);
-  TIDE_LAUNCH_CHECK("k_tile_keys");
-  uint32_t *ok, *order;
-  radix_sort_pairs(L.oka, L.ova, L.okb, L.ovb, ntt, 8, true, L.hist, L.partial, &L.totals[3], st, &ok, &order);
   out->tile_order = order;
   out->tile_visits = L.tvis;
   out->vis_rec = vrec;
@@ -637,8 +683,6 @@ extern "C" tide_status tide_bin_sort(const tide_proj* proj, int32_t tiles_x, int
   out->inst_e = te;
   out->inst_rec = L.inst_rec;
   out->ranges = L.ranges;
-  out->n_vis = n_vis;
-  out->n_inst = n_inst;
   out->n_cams = V;
   out->tiles_x = tiles_x;
   out->tiles_y = tiles_y;

@@ -264,8 +264,8 @@ class Rasterizer:
         W, H = int(cams[0].width), int(cams[0].height)
         cam_arr = L.camera_array(cams)
         proj = self.preprocess(pool, cams, cam_arr)
-        # the frame is made before the binning, whose count read-back leaves
-        # the GPU idle until the next launch
+        # the frame is made before the binning, which returns only once its
+        # counts have reached the host
         fr = self.new_frame(len(cams), W, H, pool.params.dtype)
         bins = self.bin_sort(proj, (W + TILE - 1) // TILE, (H + TILE - 1) // TILE)
         self.render(proj, bins, W, H, bg, fr)

@@ -167,6 +167,28 @@ def test_binning_is_bit_exact_on_oracle_inputs():
     say(f"instances {bins.n_inst}, visible pairs {bins.n_vis}: lists identical")
 
 
+def test_bin_sort_capacity_retry_gives_the_same_lists():
+    """A workspace too small for the instances: the first call, whose emit and
+    tile sort are queued before the counts reach the host, writes within its
+    capacity and reports the size it needs; the retry's lists and image equal
+    those of a call that fitted at once."""
+    say("case: dense scene, bin_sort with an instance capacity below the count, then the retry")
+    th, cams = dense_case()
+    ref_rast, pool, _, ref_bins, ref_fr = gpu_forward(th, cams, block_rows=1024)
+    small = Rasterizer("cuda")
+    small.inst_cap = 5000
+    _, bins, fr = small.forward(pool, cams)
+    torch.cuda.synchronize()
+    assert ref_bins.n_inst > 5000 and small.inst_cap > 5000
+    a, b = bins_views(ref_rast, ref_bins), bins_views(small, bins)
+    assert bins.n_inst == ref_bins.n_inst and bins.n_vis == ref_bins.n_vis
+    for k in ("ranges", "tile_order", "vis_rec", "inst_off"):
+        assert torch.equal(a[k], b[k]), k
+    assert torch.equal(a["inst_rec"][a["inst_e"].long()], b["inst_rec"][b["inst_e"].long()])
+    assert torch.equal(fr.image, ref_fr.image)
+    say(f"instances {bins.n_inst}: retry from capacity 5000 identical")
+
+
 def test_compositing_matches_oracle_on_oracle_records():
     say("case: dense scene, stage-isolated compositing on oracle records")
     th, cams = dense_case()
