@@ -1,8 +1,8 @@
 // Photometric loss 0.8 L1 + 0.2 (1 - SSIM) and its gradient.  SSIM windows
 // are separable 11-tap Gaussians (sigma 1.5, zero padding).
 //
-// One wave sweeps a strip of 64 columns (one per lane) down kRows output
-// rows.  Each input row is staged in LDS with a 5-column halo on both sides;
+// One wave sweeps a strip of 64 columns (one per lane) down a strip of
+// output rows.  Each input row is staged in LDS with a 5-column halo on both sides;
 // a lane's horizontal 11-tap sums go into a register ring holding the last 11
 // rows, and the vertical sum over the ring gives the output row 5 rows above
 // the newest input row.  LDS carries only the horizontal exchange (two values
@@ -15,9 +15,16 @@
 namespace tide {
 
 constexpr int kHalo = 5, kTaps = 2 * kHalo + 1;
-constexpr int kTurns = 5;                          // ring turns per wave
-constexpr int kRows = kTaps * kTurns - 2 * kHalo;  // 45 output rows per wave
-constexpr int kSpan = kWave + 2 * kHalo;           // 74 staged columns
+constexpr int kSpan = kWave + 2 * kHalo;   // 74 staged columns
+// Ring turns per wave and the output rows they give (11 turns - 10 halo
+// rows).  Set for 1080-row frames: the forward's 11 strips of 100 rows are
+// 3960 waves, one round at its four waves per SIMD; the backward (68 VGPRs)
+// does best with 14 strips of 78 rows (measured: 100 rows 204 us against
+// 45 rows 213 us for the forward, 78 rows 164 us against 181 us for the
+// backward, 4 x 3 x 1080 x 1920).
+constexpr int kTurnsFwd = 10, kTurnsBwd = 8;
+constexpr int rows_of(int turns) { return kTaps * turns - 2 * kHalo; }
+constexpr int kRowsFwd = rows_of(kTurnsFwd), kRowsBwd = rows_of(kTurnsBwd);
 
 template <typename T>
 struct Win {
@@ -42,7 +49,7 @@ __global__ void __launch_bounds__(kWave) k_ssim_fwd(const T* __restrict__ X, con
   const int ca = c - kHalo;                     // column staged in slot lane
   const int cb = c + kWave - kHalo;             // column staged in slot 64 + lane (lane < 10)
   const bool ina = ca >= 0 && ca < W, inb = lane < 2 * kHalo && cb < W, inc = c < W;
-  const int r0 = blockIdx.y * kRows;
+  const int r0 = blockIdx.y * kRowsFwd;
   T xa, ya, xb, yb;   // the next input row
   auto fetch = [&](int ir) {
     const bool rin = ir >= 0 && ir < H;
@@ -56,7 +63,7 @@ __global__ void __launch_bounds__(kWave) k_ssim_fwd(const T* __restrict__ X, con
   T ring[kTaps][5];
   const T C1 = (T)1e-4, C2 = (T)9e-4;
   double l1 = 0, ss = 0;
-  for (int turn = 0; turn < kTurns; ++turn) {
+  for (int turn = 0; turn < kTurnsFwd; ++turn) {
 #pragma unroll
     for (int j = 0; j < kTaps; ++j) {
       const int n = turn * kTaps + j;   // input rows staged before this one
@@ -68,7 +75,7 @@ __global__ void __launch_bounds__(kWave) k_ssim_fwd(const T* __restrict__ X, con
         sx[q][kWave + lane] = xb;
         sy[q][kWave + lane] = yb;
       }
-      if (n + 1 < kTaps * kTurns) fetch(ir + 1);
+      if (n + 1 < kTaps * kTurnsFwd) fetch(ir + 1);
       __syncthreads();
       T a = 0, b = 0, aa = 0, bb = 0, ab = 0, xc = 0, yc = 0;
 #pragma unroll
@@ -80,7 +87,7 @@ __global__ void __launch_bounds__(kWave) k_ssim_fwd(const T* __restrict__ X, con
       }
       ring[j][0] = a; ring[j][1] = b; ring[j][2] = aa; ring[j][3] = bb; ring[j][4] = ab;
       // this input row is an output row of the wave: its L1 term
-      if (n >= kHalo && n < kHalo + kRows && ir < H && inc) l1 += (double)(xc > yc ? xc - yc : yc - xc);
+      if (n >= kHalo && n < kHalo + kRowsFwd && ir < H && inc) l1 += (double)(xc > yc ? xc - yc : yc - xc);
       if (n >= 2 * kHalo) {
         // ring slot (j + 1 + t) mod 11 holds input row ir - 10 + t
         T mx = 0, my = 0, mxx = 0, myy = 0, mxy = 0;
@@ -131,7 +138,7 @@ __global__ void __launch_bounds__(kWave) k_ssim_bwd(const T* __restrict__ X, con
   const int c = blockIdx.x * kWave + lane;
   const int ca = c - kHalo, cb = c + kWave - kHalo;
   const bool ina = ca >= 0 && ca < W, inb = lane < 2 * kHalo && cb < W, inc = c < W;
-  const int r0 = blockIdx.y * kRows;
+  const int r0 = blockIdx.y * kRowsBwd;
   T da[3], db[3], xo, yo;   // the next input row of the maps; x, y of the next output row
   auto fetch = [&](int ir) {
     const bool rin = ir >= 0 && ir < H;
@@ -148,7 +155,7 @@ __global__ void __launch_bounds__(kWave) k_ssim_bwd(const T* __restrict__ X, con
   };
   fetch(r0 - kHalo);
   T ring[kTaps][3];
-  for (int turn = 0; turn < kTurns; ++turn) {
+  for (int turn = 0; turn < kTurnsBwd; ++turn) {
 #pragma unroll
     for (int j = 0; j < kTaps; ++j) {
       const int n = turn * kTaps + j;
@@ -160,7 +167,7 @@ __global__ void __launch_bounds__(kWave) k_ssim_bwd(const T* __restrict__ X, con
         if (lane < 2 * kHalo) sd[q][m][kWave + lane] = db[m];
       }
       const T xv = xo, yv = yo;
-      if (n + 1 < kTaps * kTurns) fetch(ir + 1);
+      if (n + 1 < kTaps * kTurnsBwd) fetch(ir + 1);
       __syncthreads();
       T a = 0, b = 0, e = 0;
 #pragma unroll
@@ -219,7 +226,7 @@ using namespace tide;
 extern "C" size_t tide_loss_ws_bytes(int32_t n_views, int32_t height, int32_t width, int32_t dtype) {
   const size_t es = dtype == TIDE_F64 ? 8 : 4;
   const size_t planes = (size_t)n_views * 3;
-  const size_t nblk = planes * ceil_div(width, kWave) * ceil_div(height, kRows);
+  const size_t nblk = planes * ceil_div(width, kWave) * ceil_div(height, kRowsFwd);
   return align_up(3 * planes * (size_t)height * width * es) + align_up(2 * nblk * sizeof(double)) + 256;
 }
 
@@ -236,7 +243,8 @@ extern "C" tide_status tide_loss(const void* image, const void* target, int32_t 
     return TIDE_ECAPACITY;
   }
   hipStream_t st = (hipStream_t)stream;
-  const dim3 grid((uint32_t)ceil_div(width, kWave), (uint32_t)ceil_div(height, kRows), (uint32_t)(n_views * 3));
+  const dim3 grid((uint32_t)ceil_div(width, kWave), (uint32_t)ceil_div(height, kRowsFwd), (uint32_t)(n_views * 3));
+  const dim3 gridb((uint32_t)ceil_div(width, kWave), (uint32_t)ceil_div(height, kRowsBwd), (uint32_t)(n_views * 3));
   const int64_t nblk = (int64_t)grid.x * grid.y * grid.z;
   const double n_all = 3.0 * height * width * n_views;
   Carver cv(ws);
@@ -246,7 +254,7 @@ extern "C" tide_status tide_loss(const void* image, const void* target, int32_t 
     const Win<float> w = make_window<float>();
     TIDE_TIMED("loss_fwd", st, hipLaunchKernelGGL(k_ssim_fwd<float>, grid, dim3(kWave), 0, st, (const float*)image, (const float*)target, height,
                        width, w, dm, part));
-    TIDE_TIMED("loss_bwd", st, hipLaunchKernelGGL(k_ssim_bwd<float>, grid, dim3(kWave), 0, st, (const float*)image, (const float*)target, dm,
+    TIDE_TIMED("loss_bwd", st, hipLaunchKernelGGL(k_ssim_bwd<float>, gridb, dim3(kWave), 0, st, (const float*)image, (const float*)target, dm,
                        height, width, w, (float)(1.0 / n_all), (float*)d_dimage));
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(1024), 0, st, part, nblk, 1.0 / n_all, d_loss);
   } else {
@@ -255,7 +263,7 @@ extern "C" tide_status tide_loss(const void* image, const void* target, int32_t 
     const Win<double> w = make_window<double>();
     TIDE_TIMED("loss_fwd", st, hipLaunchKernelGGL(k_ssim_fwd<double>, grid, dim3(kWave), 0, st, (const double*)image, (const double*)target,
                        height, width, w, dm, part));
-    TIDE_TIMED("loss_bwd", st, hipLaunchKernelGGL(k_ssim_bwd<double>, grid, dim3(kWave), 0, st, (const double*)image, (const double*)target, dm,
+    TIDE_TIMED("loss_bwd", st, hipLaunchKernelGGL(k_ssim_bwd<double>, gridb, dim3(kWave), 0, st, (const double*)image, (const double*)target, dm,
                        height, width, w, 1.0 / n_all, (double*)d_dimage));
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(1024), 0, st, part, nblk, 1.0 / n_all, d_loss);
   }

@@ -34,6 +34,19 @@ struct NonzeroIn {
   __device__ uint32_t operator()(int64_t i) const { return a[i] != 0u ? 1u : 0u; }
 };
 
+// Output sinks: element i with exclusive prefix `off` and value v.
+struct OffsetsOut {   // out[i] = off
+  uint32_t* out;
+  __device__ void operator()(int64_t i, uint32_t off, uint32_t) const { out[i] = off; }
+};
+
+// Extras written by whichever block holds the total: a u32 copy of it, and
+// end[n] = total (the closing offset of an offsets array).
+struct ScanTail {
+  uint32_t* total32;
+  uint32_t* end;
+};
+
 // Element counts: n_max bounds the launch; when d_n is given the kernels
 // read the actual count from device memory (n = min(n_max, *d_n)), which
 // lets a pipeline size its grids without a host round trip.
@@ -63,18 +76,25 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(In in, int64_t n_m
   }
 }
 
-// One workgroup scans partial[0..nb) in place (exclusive) and writes the total.
+// One workgroup scans partial[0..nb) in place (exclusive) and writes the
+// total and the tail (n as for dev_count).
 __global__ void __launch_bounds__(1024) k_scan_partials(unsigned long long* partial, int64_t nb,
-                                                        unsigned long long* total);
+                                                        unsigned long long* total, ScanTail tail, int64_t n_max,
+                                                        const unsigned long long* d_n);
+
+__device__ inline void write_tail(const ScanTail& tail, unsigned long long t, int64_t n) {
+  if (tail.total32) *tail.total32 = (uint32_t)t;
+  if (tail.end) tail.end[n] = (uint32_t)t;
+}
 
 // kSums: partial holds the blocks' sums (not yet scanned); each block adds
 // up its predecessors' itself and block 0 writes the total (one launch
 // fewer; used when there are at most 1024 blocks).
-template <typename In, bool kSums>
+template <typename In, bool kSums, typename Out>
 __global__ void __launch_bounds__(kScanThreads) k_scan_down(In in, int64_t n_max, const unsigned long long* d_n,
                                                             const unsigned long long* partial,
-                                                            uint32_t* out, int64_t nb,
-                                                            unsigned long long* total) {
+                                                            Out out, int64_t nb,
+                                                            unsigned long long* total, ScanTail tail) {
   const int64_t n = dev_count(n_max, d_n);
   __shared__ unsigned long long bpre[kScanThreads / kWave + 1];
   if (kSums) {
@@ -88,7 +108,10 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_down(In in, int64_t n_max
     if (threadIdx.x == 0) {
       unsigned long long t = 0;
       for (int q = 0; q < kScanThreads / kWave; ++q) t += bpre[q];
-      if (blockIdx.x == 0) *total = t;
+      if (blockIdx.x == 0) {
+        *total = t;
+        write_tail(tail, t, n);
+      }
       bpre[kScanThreads / kWave] = blockIdx.x == 0 ? 0ull : t;
     }
     __syncthreads();
@@ -113,26 +136,35 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_down(In in, int64_t n_max
   uint32_t run = (uint32_t)bp + wpre + inc - s;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    if (base + k < n) out[base + k] = run;
+    if (base + k < n) out(base + k, run, v[k]);
     run += v[k];
   }
 }
 
-// Exclusive scan of in(0..n) into out; total (u64, device) receives the sum.
-// partial needs ceil(n_max/4096) u64 entries; d_n as for dev_count.
-template <typename In>
-inline void scan_exclusive(In in, int64_t n, uint32_t* out, unsigned long long* partial,
-                           unsigned long long* total, hipStream_t st, const unsigned long long* d_n = nullptr) {
+// Exclusive scan of in(0..n) into the sink out; total (u64, device)
+// receives the sum, and the tail its extras.  partial needs
+// ceil(n_max/4096) u64 entries; d_n as for dev_count.
+template <typename In, typename Out>
+inline void scan_to(In in, int64_t n, Out out, unsigned long long* partial, unsigned long long* total,
+                    hipStream_t st, const unsigned long long* d_n = nullptr, ScanTail tail = ScanTail{nullptr, nullptr}) {
   const int64_t nb = ceil_div(n > 0 ? n : 1, kScanTile);
   hipLaunchKernelGGL(k_scan_reduce<In>, dim3((uint32_t)nb), dim3(kScanThreads), 0, st, in, n, d_n, partial);
   if (nb <= 1024) {
-    hipLaunchKernelGGL((k_scan_down<In, true>), dim3((uint32_t)nb), dim3(kScanThreads), 0, st, in, n, d_n,
-                       (const unsigned long long*)partial, out, nb, total);
+    hipLaunchKernelGGL((k_scan_down<In, true, Out>), dim3((uint32_t)nb), dim3(kScanThreads), 0, st, in, n, d_n,
+                       (const unsigned long long*)partial, out, nb, total, tail);
     return;
   }
-  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, partial, nb, total);
-  hipLaunchKernelGGL((k_scan_down<In, false>), dim3((uint32_t)nb), dim3(kScanThreads), 0, st, in, n, d_n,
-                     (const unsigned long long*)partial, out, nb, total);
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, partial, nb, total, tail, n, d_n);
+  hipLaunchKernelGGL((k_scan_down<In, false, Out>), dim3((uint32_t)nb), dim3(kScanThreads), 0, st, in, n, d_n,
+                     (const unsigned long long*)partial, out, nb, total, tail);
+}
+
+// Exclusive scan into an offsets array.
+template <typename In>
+inline void scan_exclusive(In in, int64_t n, uint32_t* out, unsigned long long* partial,
+                           unsigned long long* total, hipStream_t st, const unsigned long long* d_n = nullptr,
+                           ScanTail tail = ScanTail{nullptr, nullptr}) {
+  scan_to(in, n, OffsetsOut{out}, partial, total, st, d_n, tail);
 }
 
 inline size_t scan_partial_count(int64_t n) { return (size_t)ceil_div(n > 0 ? n : 1, kScanTile); }

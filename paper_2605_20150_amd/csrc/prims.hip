@@ -4,7 +4,8 @@
 namespace tide {
 
 __global__ void __launch_bounds__(1024) k_scan_partials(unsigned long long* partial, int64_t nb,
-                                                        unsigned long long* total) {
+                                                        unsigned long long* total, ScanTail tail, int64_t n_max,
+                                                        const unsigned long long* d_n) {
   __shared__ unsigned long long wtot[1024 / kWave];
   __shared__ unsigned long long carry;
   if (threadIdx.x == 0) carry = 0;
@@ -28,7 +29,10 @@ __global__ void __launch_bounds__(1024) k_scan_partials(unsigned long long* part
     if (threadIdx.x == 1023) carry = pre + inc;
     __syncthreads();
   }
-  if (threadIdx.x == 0) *total = carry;
+  if (threadIdx.x == 0) {
+    *total = carry;
+    write_tail(tail, carry, dev_count(n_max, d_n));
+  }
 }
 
 __global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint32_t* keys, int64_t n_max,

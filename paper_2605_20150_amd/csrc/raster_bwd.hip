@@ -181,14 +181,43 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
 }
 
 // ---------------------------------------------- per-pair reduction (fixed order)
-// One wave64 workgroup per 64 consecutive depth-ordered visible pairs.  Their
-// partials are contiguous ([inst_off[s0], inst_off[s0 + 64])), so the wave
+// One DPP step of a segmented inclusive scan: each lane adds the source
+// lane's values where that lane is in the same segment (segments are runs of
+// equal p; a source the pattern leaves out reads -2, which no p equals).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t old, uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)x, CTRL, ROWS, 0xF, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_val(float x) {
+  return __uint_as_float(dpp_u32<CTRL, ROWS>(0u, __float_as_uint(x)));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_val(double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const uint32_t lo = dpp_u32<CTRL, ROWS>(0u, (uint32_t)b), hi = dpp_u32<CTRL, ROWS>(0u, (uint32_t)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <int CTRL, int ROWS, typename T>
+__device__ __forceinline__ void seg_step(int p, T (&v)[kG2]) {
+  const bool same = (int)dpp_u32<CTRL, ROWS>((uint32_t)-2, (uint32_t)p) == p;
+#pragma unroll
+  for (int m = 0; m < kG2; ++m) {
+    const T y = dpp_val<CTRL, ROWS>(v[m]);
+    v[m] = same ? v[m] + y : v[m];
+  }
+}
+
+// Per visible pair, the sum of its instances' partials; one wave64 workgroup
+// per 64 consecutive depth-ordered visible pairs.  Their partials are
+// contiguous ([inst_off[s0], inst_off[s0 + 64])), so the wave
 // walks them 64 instances at a time with coalesced loads; each lane finds its
-// pair by binary search over the 64 offsets, a segmented inclusive scan
-// (shuffles, segments are contiguous) sums equal-pair lanes, and the last
-// lane of each segment adds into that pair's LDS accumulator.  A pair gets at
-// most one add per step and steps run in order, so the sums are
-// deterministic.  Balanced whatever the footprint sizes.
+// pair by binary search over the 64 offsets, a segmented inclusive scan in
+// DPP (row shifts 1, 2, 4, 8, then the broadcasts of lanes 15 and 31; no LDS
+// round trips) sums equal-pair lanes, and the last lane of each segment adds
+// into that pair's LDS accumulator.  A pair gets at most one add per step and
+// steps run in order, so the sums are deterministic.  Balanced whatever the
+// footprint sizes.
 template <typename T>
 __global__ void __launch_bounds__(64) k_reduce_pairs(const uint32_t* __restrict__ vis_rec,
                                                      const uint32_t* __restrict__ inst_off, int64_t n_vis,
@@ -219,18 +248,13 @@ __global__ void __launch_bounds__(64) k_reduce_pairs(const uint32_t* __restrict_
     const T* P = partial + (int64_t)(valid ? e : e0) * kG2;
 #pragma unroll
     for (int m = 0; m < kG2; ++m) v[m] = valid ? P[m] : (T)0;
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-      const int pn = __shfl_up(p, off, kWave);
-      const bool same = lane >= off && pn == p;
-#pragma unroll
-      for (int m = 0; m < kG2; ++m) {
-        const T y = __shfl_up(v[m], off, kWave);
-        v[m] += same ? y : (T)0;
-      }
-    }
-    const int pnext = __shfl_down(p, 1, kWave);
-    const bool seg_end = valid && (lane == kWave - 1 || pnext != p);
+    seg_step<0x111, 0xF>(p, v);   // row_shr:1
+    seg_step<0x112, 0xF>(p, v);   // row_shr:2
+    seg_step<0x114, 0xF>(p, v);   // row_shr:4
+    seg_step<0x118, 0xF>(p, v);   // row_shr:8
+    seg_step<0x142, 0xA>(p, v);   // row_bcast:15 into rows 1 and 3
+    seg_step<0x143, 0xC>(p, v);   // row_bcast:31 into rows 2 and 3
+    const bool seg_end = valid && (lane == kWave - 1 || e + 1 == s_off[lo + 1]);
     if (seg_end) {
 #pragma unroll
       for (int m = 0; m < kG2; ++m) s_acc[p][m] += v[m];

@@ -209,10 +209,10 @@ static tide_status preprocess_t(const tide_pool* pool, const tide_camera* cams, 
   Carver cv(ws);
   unsigned long long* partial = cv.take<unsigned long long>(scan_partial_count(n));
   unsigned long long* total = cv.take<unsigned long long>(1);
-  scan_exclusive(ArrayIn{out->active}, n, out->act_idx, partial, total, st);
+  // the count goes to the caller as u32 from the block that holds the total
+  scan_exclusive(ArrayIn{out->active}, n, out->act_idx, partial, total, st, nullptr,
+                 ScanTail{out->n_active, nullptr});
   TIDE_LAUNCH_CHECK("active scan");
-  // the count as u32 for the caller
-  TIDE_HIP(hipMemcpyAsync(out->n_active, total, 4, hipMemcpyDeviceToDevice, st));
   return TIDE_OK;
 }
 
@@ -270,14 +270,17 @@ __global__ void k_compact_vis(const uint32_t* __restrict__ tt, const float* __re
 // (coalesced writes); a lane finds its pair by binary search over the 64
 // offsets and its tile from the pair's rectangle.  Balanced whatever the
 // footprint sizes.  Instances at or past cap are not written (the call then
-// reports the count it needs).
+// reports the count it needs).  The grid also clears zero[0, n_zero) (the
+// tile ranges, filled in later).
 __global__ void __launch_bounds__(64) k_emit(const uint32_t* __restrict__ vis_rec,
                                              const uint32_t* __restrict__ inst_off,
                                              const uint32_t* __restrict__ rect, int64_t nv_max,
                                              const unsigned long long* __restrict__ d_nvis, int64_t cap,
                                              int64_t n_pidx, int32_t Tx, int32_t Ty, uint32_t* __restrict__ tkey,
-                                             uint32_t* __restrict__ inst_rec) {
+                                             uint32_t* __restrict__ inst_rec, uint32_t* __restrict__ zero,
+                                             int64_t n_zero) {
   const int lane = threadIdx.x;
+  for (int64_t i = (int64_t)blockIdx.x * kWave + lane; i < n_zero; i += (int64_t)gridDim.x * kWave) zero[i] = 0u;
   const int64_t n_vis = dev_count(nv_max, d_nvis);
   __shared__ uint32_t s_off[kWave + 1];
   __shared__ uint32_t s_rec[kWave], s_base[kWave], s_x0[kWave], s_w[kWave];
@@ -312,16 +315,6 @@ __global__ void __launch_bounds__(64) k_emit(const uint32_t* __restrict__ vis_re
     }
     __syncthreads();
   }
-}
-
-// inst_off[n_vis] = n_inst, with both counts read on the device.
-__global__ void k_set_end(uint32_t* inst_off, const unsigned long long* n_vis, const unsigned long long* n_inst) {
-  inst_off[*n_vis] = (uint32_t)*n_inst;
-}
-
-__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
 }
 
 // Per-tile [start, end) of the tile-sorted keys; the count is read on the
@@ -604,10 +597,12 @@ extern "C" tide_status tide_bin_sort(const tide_proj* proj, int32_t tiles_x, int
   BinLayout L = bin_layout(ws, V, N, nt, cap);
 
   // 1. visible pairs, compacted in (camera, pidx) order, keyed by depth bits
+  //    (a kernel of its own: the scan's down-sweep gives a thread 16
+  //    consecutive items, so writing the pairs there would not coalesce)
   scan_exclusive(NonzeroIn{proj->tiles_touched}, nv, L.vis_off, L.partial, &L.totals[0], st);
   if (nv > 0)
-    TIDE_TIMED("compact_vis", st, hipLaunchKernelGGL(k_compact_vis, dim3((uint32_t)ceil_div(nv, 256)), dim3(256), 0, st, proj->tiles_touched,
-                       proj->depth, L.vis_off, nv, L.ka, L.va));
+    TIDE_TIMED("compact_vis", st, hipLaunchKernelGGL(k_compact_vis, dim3((uint32_t)ceil_div(nv, 256)), dim3(256), 0, st,
+                                                     proj->tiles_touched, proj->depth, L.vis_off, nv, L.ka, L.va));
   TIDE_LAUNCH_CHECK("visibility compaction");
   // 2. stable sort of the visible pairs by depth; grids are sized by the
   //    upper bound and the kernels read the visible count from the device
@@ -616,9 +611,9 @@ extern "C" tide_status tide_bin_sort(const tide_proj* proj, int32_t tiles_x, int
   //    (into vis_off, free once the compaction has run)
   radix_sort_pairs(L.ka, L.va, L.kb, L.vb, nv, 32, false, L.hist, L.partial, &L.totals[1], st, &vk, &vrec,
                    &L.totals[0], proj->tiles_touched, L.vis_off);
-  // 3. instance offsets in depth order
-  scan_exclusive(ArrayIn{L.vis_off}, nv, L.inst_off, L.partial, &L.totals[2], st, &L.totals[0]);
-  hipLaunchKernelGGL(k_set_end, dim3(1), dim3(1), 0, st, L.inst_off, &L.totals[0], &L.totals[2]);
+  // 3. instance offsets in depth order, closed by inst_off[n_vis] = n_inst
+  scan_exclusive(ArrayIn{L.vis_off}, nv, L.inst_off, L.partial, &L.totals[2], st, &L.totals[0],
+                 ScanTail{nullptr, L.inst_off});
   TIDE_LAUNCH_CHECK("instance scan");
   // 4. the counts travel to the host while the rest of the binning is queued
   //    behind them: those kernels are sized by the instance capacity and read
@@ -631,12 +626,14 @@ extern "C" tide_status tide_bin_sort(const tide_proj* proj, int32_t tiles_x, int
   }
   TIDE_HIP(hipMemcpyAsync(slot.host, L.totals, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
   TIDE_HIP(hipEventRecord(slot.ev, st));
-  // 5. emit instances in depth order, keyed by global tile id
+  // 5. emit instances in depth order, keyed by global tile id (and clear
+  //    the tile ranges)
+  const int64_t nr = 2 * (int64_t)V * nt;
   {
     const int64_t chunks = ceil_div(nv > 0 ? nv : 1, kWave);
     TIDE_TIMED("emit", st, hipLaunchKernelGGL(k_emit, dim3((uint32_t)(chunks < 32768 ? chunks : 32768)), dim3(kWave), 0,
                                               st, vrec, L.inst_off, proj->rect, nv, &L.totals[0], cap, N, tiles_x,
-                                              tiles_y, L.tka, L.inst_rec));
+                                              tiles_y, L.tka, L.inst_rec, L.ranges, nr));
   }
   TIDE_LAUNCH_CHECK("k_emit");
   // 6. stable sort by tile; values are emission indices
@@ -647,8 +644,6 @@ extern "C" tide_status tide_bin_sort(const tide_proj* proj, int32_t tiles_x, int
   radix_sort_pairs(L.tka, L.tva, L.tkb, L.tvb, cap, bits, true, L.hist, L.partial, &L.totals[3], st, &tk, &te,
                    &L.totals[2]);
   // 7. per-tile ranges
-  const int64_t nr = 2 * (int64_t)V * nt;
-  hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)ceil_div(nr, 256)), dim3(256), 0, st, L.ranges, nr, 0u);
   if (cap > 0) {
     const int64_t nb = ceil_div(cap, 256);
     hipLaunchKernelGGL(k_ranges, dim3((uint32_t)(nb < 65536 ? nb : 65536)), dim3(256), 0, st, tk, cap, &L.totals[2],
