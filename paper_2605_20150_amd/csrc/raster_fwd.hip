@@ -318,14 +318,33 @@ __global__ void __launch_bounds__(64) k_emit(const uint32_t* __restrict__ vis_re
 }
 
 // Per-tile [start, end) of the tile-sorted keys; the count is read on the
-// device (grid-stride).
+// device (grid-stride).  A thread takes four consecutive keys (one 16-byte
+// load when kVec: the keys are 16-byte aligned) and compares each with its
+// neighbours; ~0u stands in past either end (keys are below 2^31).
+template <bool kVec>
 __global__ void k_ranges(const uint32_t* __restrict__ key, int64_t n_max, const unsigned long long* __restrict__ d_n,
                          uint32_t* __restrict__ ranges) {
   const int64_t n = dev_count(n_max, d_n);
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t k = key[j];
-    if (j == 0 || key[j - 1] != k) ranges[2 * (int64_t)k] = (uint32_t)j;
-    if (j == n - 1 || key[j + 1] != k) ranges[2 * (int64_t)k + 1] = (uint32_t)(j + 1);
+  const int64_t stride = 4 * (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j0 = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x); j0 < n; j0 += stride) {
+    uint32_t k[6];   // key[j0 - 1 .. j0 + 4]
+    k[0] = j0 > 0 ? key[j0 - 1] : ~0u;
+    if (kVec && j0 + 4 <= n) {
+      const uint4 q = *reinterpret_cast<const uint4*>(key + j0);
+      k[1] = q.x; k[2] = q.y; k[3] = q.z; k[4] = q.w;
+    } else {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) k[1 + a] = j0 + a < n ? key[j0 + a] : ~0u;
+    }
+    k[5] = j0 + 4 < n ? key[j0 + 4] : ~0u;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int64_t j = j0 + a;
+      if (j < n) {
+        if (k[a] != k[a + 1]) ranges[2 * (int64_t)k[a + 1]] = (uint32_t)j;
+        if (k[a + 2] != k[a + 1]) ranges[2 * (int64_t)k[a + 1] + 1] = (uint32_t)(j + 1);
+      }
+    }
   }
 }
 
@@ -645,9 +664,12 @@ extern "C" tide_status tide_bin_sort(const tide_proj* proj, int32_t tiles_x, int
                    &L.totals[2]);
   // 7. per-tile ranges
   if (cap > 0) {
-    const int64_t nb = ceil_div(cap, 256);
-    hipLaunchKernelGGL(k_ranges, dim3((uint32_t)(nb < 65536 ? nb : 65536)), dim3(256), 0, st, tk, cap, &L.totals[2],
-                       L.ranges);
+    const int64_t nb = ceil_div(ceil_div(cap, 4), 256);
+    const dim3 grid((uint32_t)(nb < 65536 ? nb : 65536));
+    if (((uintptr_t)tk & 15) == 0)
+      hipLaunchKernelGGL(k_ranges<true>, grid, dim3(256), 0, st, tk, cap, &L.totals[2], L.ranges);
+    else
+      hipLaunchKernelGGL(k_ranges<false>, grid, dim3(256), 0, st, tk, cap, &L.totals[2], L.ranges);
   }
   TIDE_LAUNCH_CHECK("k_ranges");
   // 8. launch order of the tiles: longest lists first
