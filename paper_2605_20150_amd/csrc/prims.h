@@ -170,6 +170,7 @@ inline void scan_exclusive(In in, int64_t n, uint32_t* out, unsigned long long* 
 inline size_t scan_partial_count(int64_t n) { return (size_t)ceil_div(n > 0 ? n : 1, kScanTile); }
 
 // ------------------------------------------------------------- radix sort
+template <bool kVec>
 __global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint32_t* keys, int64_t n_max,
                                                              const unsigned long long* d_n, int shift,
                                                              uint32_t* ghist, int64_t nb);

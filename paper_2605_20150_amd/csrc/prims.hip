@@ -35,21 +35,73 @@ __global__ void __launch_bounds__(1024) k_scan_partials(unsigned long long* part
   }
 }
 
+// Adds this lane's run (digit d, count c) to the wave's bins: one add for
+// the whole wave when every lane holds the same digit (the top digits of
+// sorted or narrow-range keys), else one LDS atomic per lane.
+__device__ __forceinline__ void hist_add(uint32_t* hw, uint32_t d, uint32_t c) {
+  const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+  if (__all(d == d0)) {
+    const uint32_t t = wave_sum(c);
+    if (__lane_id() == 0) atomicAdd(&hw[d0], t);   // atomic: other lanes' earlier runs may add to it too
+  } else {
+    atomicAdd(&hw[d], c);
+  }
+}
+
+// Per-block digit histogram.  Each wave counts into bins of its own, a
+// thread takes four consecutive keys per load (16 bytes when kVec: the keys
+// are 16-byte aligned) and adds equal neighbouring digits as one run, and the
+// waves' bins are added at the end.
+template <bool kVec>
 __global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint32_t* keys, int64_t n_max,
                                                              const unsigned long long* d_n, int shift,
                                                              uint32_t* ghist, int64_t nb) {
   const int64_t n = dev_count(n_max, d_n);
-  __shared__ uint32_t h[256];
-  h[threadIdx.x] = 0;
+  __shared__ uint32_t h[kSortWaves][256];
+  for (int k = threadIdx.x; k < kSortWaves * 256; k += kSortThreads) (&h[0][0])[k] = 0;
   __syncthreads();
+  uint32_t* hw = h[threadIdx.x / kWave];
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
-#pragma unroll 4
-  for (int r = 0; r < kSortRounds; ++r) {
-    const int64_t i = base + (int64_t)r * kSortThreads + threadIdx.x;
-    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+#pragma unroll
+  for (int r = 0; r < kSortRounds / 4; ++r) {
+    const int64_t i = base + 4 * ((int64_t)r * kSortThreads + threadIdx.x);
+    uint32_t d[4];
+    int cnt = 0;   // valid keys of the four (a prefix)
+    if (kVec && i + 4 <= n) {
+      const uint4 q = *reinterpret_cast<const uint4*>(keys + i);
+      d[0] = q.x; d[1] = q.y; d[2] = q.z; d[3] = q.w;
+      cnt = 4;
+    } else {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        d[a] = i + a < n ? keys[i + a] : 0u;
+        cnt += i + a < n ? 1 : 0;
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) d[a] = (d[a] >> shift) & 255u;
+    // runs of equal digits among the valid keys; lanes with none add 0 to
+    // their first digit's bin
+    uint32_t cur = d[0], run = cnt > 0 ? 1u : 0u;
+#pragma unroll
+    for (int a = 1; a < 4; ++a) {
+      if (a < cnt) {
+        if (d[a] == cur) {
+          ++run;
+        } else {
+          atomicAdd(&hw[cur], run);
+          cur = d[a];
+          run = 1;
+        }
+      }
+    }
+    hist_add(hw, cur, run);
   }
   __syncthreads();
-  ghist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+  uint32_t c = 0;
+#pragma unroll
+  for (int w = 0; w < kSortWaves; ++w) c += h[w][threadIdx.x];
+  ghist[(int64_t)threadIdx.x * nb + blockIdx.x] = c;
 }
 
 __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint32_t* keys_in,
@@ -145,7 +197,11 @@ void radix_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, in
   const int64_t nb = ceil_div(n > 0 ? n : 1, kSortTile);
   if (n > 0) {
     for (int shift = 0; shift < bits; shift += 8) {
-      hipLaunchKernelGGL(k_radix_hist, dim3((uint32_t)nb), dim3(kSortThreads), 0, st, ki, n, d_n, shift, hist, nb);
+      if (((uintptr_t)ki & 15) == 0)
+        hipLaunchKernelGGL(k_radix_hist<true>, dim3((uint32_t)nb), dim3(kSortThreads), 0, st, ki, n, d_n, shift, hist, nb);
+      else
+        hipLaunchKernelGGL(k_radix_hist<false>, dim3((uint32_t)nb), dim3(kSortThreads), 0, st, ki, n, d_n, shift, hist,
+                           nb);
       scan_exclusive(ArrayIn{hist}, 256 * nb, hist, partial, total, st);
       const bool last = shift + 8 >= bits;
       TIDE_TIMED("radix_scatter", st, hipLaunchKernelGGL(k_radix_scatter, dim3((uint32_t)nb), dim3(kSortThreads), 0, st, ki,
