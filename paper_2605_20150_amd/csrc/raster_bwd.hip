@@ -9,6 +9,13 @@ namespace tide {
 
 constexpr int kG2 = 9;  // du, dv, dA, dB, dC, dopacity, dr, dg, db
 
+// A per-instance record of the kG2 partials, aligned only to its element:
+// accessed as one object, the compiler moves it in 16-byte pieces.
+template <typename T>
+struct __attribute__((aligned(sizeof(T)))) Rec9 {
+  T v[kG2];
+};
+
 // ----------------------------------------------------- compositing adjoint
 // Same lane/pixel layout as the forward.  Each pixel walks back from its
 // last contributor, recovering T_i = T_{i+1} / (1 - alpha_i) and the
@@ -66,9 +73,10 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
   }
   const uint32_t start = ranges[2 * g], end = ranges[2 * g + 1];
   for (uint32_t j = start + maxl + lane; j < end; j += 64) {
-    T* P = partial + (int64_t)inst_e[j] * kG2;
+    Rec9<T> z;
 #pragma unroll
-    for (int m = 0; m < kG2; ++m) P[m] = 0;
+    for (int m = 0; m < kG2; ++m) z.v[m] = 0;
+    *reinterpret_cast<Rec9<T>*>(partial + (int64_t)inst_e[j] * kG2) = z;
   }
   __shared__ T s_u[64], s_v[64], s_Ah[64], s_Bh[64], s_Ch[64], s_A[64], s_B[64], s_C[64], s_o[64], s_r[64],
       s_g[64], s_b[64];
@@ -162,19 +170,20 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
     }
     __syncthreads();
     if (lane < n) {
-      T* P = partial + (int64_t)my_e * kG2;
+      Rec9<T> r;
       if (s_hit[lane]) {
-        T r[kG2];
 #pragma unroll
         for (int m = 0; m < kG2; ++m)
-          r[m] = s_part[lane][0][m] + s_part[lane][1][m];
+          r.v[m] = s_part[lane][0][m] + s_part[lane][1][m];
         // dpower/dA = -dx^2/2, dpower/dB = -dx dy, dpower/dC = -dy^2/2
-        P[0] = r[0]; P[1] = r[1]; P[2] = (T)-0.5 * r[2]; P[3] = -r[3]; P[4] = (T)-0.5 * r[4];
-        P[5] = r[5]; P[6] = r[6]; P[7] = r[7]; P[8] = r[8];
+        r.v[2] *= (T)-0.5;
+        r.v[3] = -r.v[3];
+        r.v[4] *= (T)-0.5;
       } else {
 #pragma unroll
-        for (int m = 0; m < kG2; ++m) P[m] = 0;
+        for (int m = 0; m < kG2; ++m) r.v[m] = 0;
       }
+      *reinterpret_cast<Rec9<T>*>(partial + (int64_t)my_e * kG2) = r;
     }
     __syncthreads();
   }
@@ -244,10 +253,13 @@ __global__ void __launch_bounds__(64) k_reduce_pairs(const uint32_t* __restrict_
       else hi = mid;
     }
     const int p = valid ? lo : -1;
+    // one record load (a lane's 36 bytes as two 16-byte loads and one
+    // 4-byte load: nine single loads at a 36-byte stride made every load
+    // instruction touch 36 cache segments)
+    const Rec9<T> rec = *reinterpret_cast<const Rec9<T>*>(partial + (int64_t)(valid ? e : e0) * kG2);
     T v[kG2];
-    const T* P = partial + (int64_t)(valid ? e : e0) * kG2;
 #pragma unroll
-    for (int m = 0; m < kG2; ++m) v[m] = valid ? P[m] : (T)0;
+    for (int m = 0; m < kG2; ++m) v[m] = valid ? rec.v[m] : (T)0;
     seg_step<0x111, 0xF>(p, v);   // row_shr:1
     seg_step<0x112, 0xF>(p, v);   // row_shr:2
     seg_step<0x114, 0xF>(p, v);   // row_shr:4
