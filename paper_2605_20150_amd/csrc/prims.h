@@ -1,9 +1,11 @@
 // Device-wide exclusive scan and stable LSD radix sort for wave64 (gfx950).
 //
 // Scan: reduce-then-scan over tiles of 4096 elements (256 lanes x 16
-// consecutive items), block partials scanned by one workgroup.
-// Radix sort: 8-bit digits; per tile a 256-bin LDS histogram, a bin-major
-// scan of the per-tile histograms, then a stable scatter whose in-tile ranks
+// consecutive items); with at most 1024 tiles each tile adds up its
+// predecessors' sums itself, else one workgroup scans the tile sums.
+// Radix sort: 8-bit digits; per tile 256-bin LDS histograms (one per wave,
+// added at the end), a bin-major scan of the per-tile histograms, then a
+// stable scatter whose in-tile ranks
 // come from ballot-based peer masks (a wave sees 64 consecutive keys per
 // round, so rank = keys of the same digit in earlier waves + earlier rounds +
 // lower lanes).  Equal keys keep their input order, which is what makes the
