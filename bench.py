@@ -89,7 +89,7 @@ def algorithmic_bytes(kernel, n_pidx, n_kept, n_vis, n_inst, n_active, pixels, V
         return n_vis * (4 + 8 + 36) + n_inst * 36
     if kernel == "adjoint":
         return n_active * (236 + 236 + 8) + n_vis * 36
-    if kernel == "adam":   # the column pass: p, m, v read + written, g read
+    if kernel == "adam":   # p, m, v read and written, g read
         return n_active * (7 * 236)
     if kernel in ("loss_fwd",):
         return pixels * 3 * (4 + 4 + 12)
