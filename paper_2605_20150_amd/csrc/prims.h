@@ -1,7 +1,8 @@
 // Device-wide exclusive scan and stable LSD radix sort for wave64 (gfx950).
 //
 // Scan: reduce-then-scan over tiles of 4096 elements (256 lanes x 16
-// consecutive items); with at most 1024 tiles each tile adds up its
+// consecutive items, moved in 16-byte pieces when the arrays are 16-byte
+// aligned); with at most 1024 tiles each tile adds up its
 // predecessors' sums itself, else one workgroup scans the tile sums.
 // Radix sort: 8-bit digits; per tile 256-bin LDS histograms (one per wave,
 // added at the end), a bin-major scan of the per-tile histograms, then a
@@ -26,20 +27,37 @@ constexpr int kSortRounds = 16;
 constexpr int kSortTile = kSortThreads * kSortRounds;  // 4096
 
 // ------------------------------------------------------------------ scan
-// Input functors: value of element i as u32.
+// Input functors: value of element i as u32; load4 reads elements i..i+3
+// with one 16-byte load (i a multiple of 4, used only when aligned() holds).
+__device__ inline uint4 ld4(const uint32_t* p) { return *reinterpret_cast<const uint4*>(p); }
 struct ArrayIn {
   const uint32_t* a;
   __device__ uint32_t operator()(int64_t i) const { return a[i]; }
+  __device__ void load4(int64_t i, uint32_t* v) const {
+    const uint4 q = ld4(a + i);
+    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+  }
+  bool aligned() const { return ((uintptr_t)a & 15) == 0; }
 };
 struct NonzeroIn {
   const uint32_t* a;
   __device__ uint32_t operator()(int64_t i) const { return a[i] != 0u ? 1u : 0u; }
+  __device__ void load4(int64_t i, uint32_t* v) const {
+    const uint4 q = ld4(a + i);
+    v[0] = q.x != 0u; v[1] = q.y != 0u; v[2] = q.z != 0u; v[3] = q.w != 0u;
+  }
+  bool aligned() const { return ((uintptr_t)a & 15) == 0; }
 };
 
-// Output sinks: element i with exclusive prefix `off` and value v.
+// Output sinks: element i with exclusive prefix `off` and value v; store4
+// writes elements i..i+3 (as load4).
 struct OffsetsOut {   // out[i] = off
   uint32_t* out;
   __device__ void operator()(int64_t i, uint32_t off, uint32_t) const { out[i] = off; }
+  __device__ void store4(int64_t i, const uint32_t* off, const uint32_t*) const {
+    *reinterpret_cast<uint4*>(out + i) = make_uint4(off[0], off[1], off[2], off[3]);
+  }
+  bool aligned() const { return ((uintptr_t)out & 15) == 0; }
 };
 
 // Extras written by whichever block holds the total: a u32 copy of it, and
@@ -58,15 +76,29 @@ __device__ inline int64_t dev_count(int64_t n_max, const unsigned long long* d_n
   return n < n_max ? n : n_max;
 }
 
-template <typename In>
+// A thread's kScanItems consecutive elements: 16-byte loads when kVec and
+// the whole run lies below n, else one element at a time (zero past n).
+template <bool kVec, typename In>
+__device__ inline void scan_items(const In& in, int64_t base, int64_t n, uint32_t* v) {
+  if (kVec && base + kScanItems <= n) {
+#pragma unroll
+    for (int j = 0; j < kScanItems; j += 4) in.load4(base + j, v + j);
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) v[k] = (base + k < n) ? in(base + k) : 0u;
+  }
+}
+
+template <typename In, bool kVec>
 __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(In in, int64_t n_max, const unsigned long long* d_n,
                                                               unsigned long long* partial) {
   const int64_t n = dev_count(n_max, d_n);
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  scan_items<kVec>(in, base, n, v);
   unsigned long long s = 0;
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k)
-    if (base + k < n) s += in(base + k);
+  for (int k = 0; k < kScanItems; ++k) s += v[k];
   s = wave_sum(s);
   __shared__ unsigned long long ws[kScanThreads / kWave];
   if (__lane_id() == 0) ws[threadIdx.x / kWave] = s;
@@ -92,7 +124,7 @@ __device__ inline void write_tail(const ScanTail& tail, unsigned long long t, in
 // kSums: partial holds the blocks' sums (not yet scanned); each block adds
 // up its predecessors' itself and block 0 writes the total (one launch
 // fewer; used when there are at most 1024 blocks).
-template <typename In, bool kSums, typename Out>
+template <typename In, bool kSums, typename Out, bool kVec>
 __global__ void __launch_bounds__(kScanThreads) k_scan_down(In in, int64_t n_max, const unsigned long long* d_n,
                                                             const unsigned long long* partial,
                                                             Out out, int64_t nb,
@@ -120,12 +152,10 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_down(In in, int64_t n_max
   }
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   uint32_t v[kScanItems];
+  scan_items<kVec>(in, base, n, v);
   uint32_t s = 0;
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    v[k] = (base + k < n) ? in(base + k) : 0u;
-    s += v[k];
-  }
+  for (int k = 0; k < kScanItems; ++k) s += v[k];
   // exclusive scan of the 256 thread sums
   const uint32_t inc = wave_incl_scan(s);
   __shared__ uint32_t wtot[kScanThreads / kWave];
@@ -136,10 +166,21 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_down(In in, int64_t n_max
   for (int q = 0; q < w; ++q) wpre += wtot[q];
   const unsigned long long bp = kSums ? bpre[kScanThreads / kWave] : partial[blockIdx.x];
   uint32_t run = (uint32_t)bp + wpre + inc - s;
+  if (kVec && base + kScanItems <= n) {
+    uint32_t o[kScanItems];
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    if (base + k < n) out(base + k, run, v[k]);
-    run += v[k];
+    for (int k = 0; k < kScanItems; ++k) {
+      o[k] = run;
+      run += v[k];
+    }
+#pragma unroll
+    for (int j = 0; j < kScanItems; j += 4) out.store4(base + j, o + j, v + j);
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      if (base + k < n) out(base + k, run, v[k]);
+      run += v[k];
+    }
   }
 }
 
@@ -150,15 +191,27 @@ template <typename In, typename Out>
 inline void scan_to(In in, int64_t n, Out out, unsigned long long* partial, unsigned long long* total,
                     hipStream_t st, const unsigned long long* d_n = nullptr, ScanTail tail = ScanTail{nullptr, nullptr}) {
   const int64_t nb = ceil_div(n > 0 ? n : 1, kScanTile);
-  hipLaunchKernelGGL(k_scan_reduce<In>, dim3((uint32_t)nb), dim3(kScanThreads), 0, st, in, n, d_n, partial);
+  const bool vec = in.aligned() && out.aligned();
+  if (vec)
+    hipLaunchKernelGGL((k_scan_reduce<In, true>), dim3((uint32_t)nb), dim3(kScanThreads), 0, st, in, n, d_n, partial);
+  else
+    hipLaunchKernelGGL((k_scan_reduce<In, false>), dim3((uint32_t)nb), dim3(kScanThreads), 0, st, in, n, d_n, partial);
   if (nb <= 1024) {
-    hipLaunchKernelGGL((k_scan_down<In, true, Out>), dim3((uint32_t)nb), dim3(kScanThreads), 0, st, in, n, d_n,
-                       (const unsigned long long*)partial, out, nb, total, tail);
+    if (vec)
+      hipLaunchKernelGGL((k_scan_down<In, true, Out, true>), dim3((uint32_t)nb), dim3(kScanThreads), 0, st, in, n, d_n,
+                         (const unsigned long long*)partial, out, nb, total, tail);
+    else
+      hipLaunchKernelGGL((k_scan_down<In, true, Out, false>), dim3((uint32_t)nb), dim3(kScanThreads), 0, st, in, n,
+                         d_n, (const unsigned long long*)partial, out, nb, total, tail);
     return;
   }
   hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, partial, nb, total, tail, n, d_n);
-  hipLaunchKernelGGL((k_scan_down<In, false, Out>), dim3((uint32_t)nb), dim3(kScanThreads), 0, st, in, n, d_n,
-                     (const unsigned long long*)partial, out, nb, total, tail);
+  if (vec)
+    hipLaunchKernelGGL((k_scan_down<In, false, Out, true>), dim3((uint32_t)nb), dim3(kScanThreads), 0, st, in, n, d_n,
+                       (const unsigned long long*)partial, out, nb, total, tail);
+  else
+    hipLaunchKernelGGL((k_scan_down<In, false, Out, false>), dim3((uint32_t)nb), dim3(kScanThreads), 0, st, in, n,
+                       d_n, (const unsigned long long*)partial, out, nb, total, tail);
 }
 
 // Exclusive scan into an offsets array.
