@@ -532,20 +532,22 @@ __global__ void __launch_bounds__(64) k_render_fwd(const uint32_t* __restrict__ 
   }
 }
 
-// visits[r][c] += sum over camera c's tiles of tile_visits[r][c * nt + t],
-// in tile order (one workgroup per (row, camera)).
+// visits[r][c] += sum over camera c's tiles of tile_visits[r][c * nt + t]:
+// kVisitParts workgroups per (row, camera), each adding its share of the
+// tiles with one 64-bit atomic (integer sums: exact in any order).
+constexpr int kVisitParts = 16;
 __global__ void __launch_bounds__(256) k_sum_visits(const unsigned long long* __restrict__ tile_visits,
                                                     int64_t nt, int32_t n_cams,
                                                     unsigned long long* __restrict__ visits) {
-  const int rc = blockIdx.x;   // r * n_cams + c
+  const int rc = blockIdx.x / kVisitParts, part = blockIdx.x % kVisitParts;   // rc = r * n_cams + c
   const unsigned long long* p = tile_visits + (int64_t)rc * nt;
   unsigned long long s = 0;
-  for (int64_t t = threadIdx.x; t < nt; t += 256) s += p[t];
+  for (int64_t t = (int64_t)part * 256 + threadIdx.x; t < nt; t += 256 * kVisitParts) s += p[t];
   s = wave_sum(s);
   __shared__ unsigned long long ws[4];
   if (__lane_id() == 0) ws[threadIdx.x / kWave] = s;
   __syncthreads();
-  if (threadIdx.x == 0) visits[rc] += ws[0] + ws[1] + ws[2] + ws[3];
+  if (threadIdx.x == 0) atomicAdd(&visits[rc], ws[0] + ws[1] + ws[2] + ws[3]);
 }
 
 }  // namespace tide
@@ -729,7 +731,7 @@ extern "C" tide_status tide_render_fwd(const tide_proj* proj, const tide_bins* b
                        fr->height, (double)bg[0], (double)bg[1], (double)bg[2], (double*)fr->image,
                        (double*)fr->t_final, fr->last, bins->tile_visits));
   TIDE_LAUNCH_CHECK("k_render_fwd");
-  hipLaunchKernelGGL(k_sum_visits, dim3((uint32_t)(2 * bins->n_cams)), dim3(256), 0, st, bins->tile_visits,
+  hipLaunchKernelGGL(k_sum_visits, dim3((uint32_t)(2 * bins->n_cams * kVisitParts)), dim3(256), 0, st, bins->tile_visits,
                      (int64_t)bins->tiles_x * bins->tiles_y, bins->n_cams, fr->visits);
   TIDE_LAUNCH_CHECK("k_sum_visits");
   return TIDE_OK;
