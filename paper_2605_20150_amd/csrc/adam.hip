@@ -12,10 +12,12 @@ struct AdamK {
   T b1, b2, eps, kappa;
 };
 
-// Three passes over the active rows; inactive rows are never written, so
-// they stay bit-identical.
-//  1. k_adam_rows: per row, step += 1 and the bias corrections
-//     1/(1 - b1^t), 1/sqrt(1 - b2^t) (double precision) into a row table.
+// Passes over the active rows; inactive rows are never written, so they
+// stay bit-identical.
+//  1. Per row, step += 1 and the bias corrections 1/(1 - b1^t),
+//     1/sqrt(1 - b2^t) (double precision): inside k_adam_sweep in single
+//     precision; k_adam_rows into a row table for the double-precision
+//     update.
 //  2. k_adam_sweep (single precision): one thread per row over its 59
 //     columns; k_adam_cols (double precision): a 2-D grid (rows x 59
 //     columns), one element per thread.
@@ -69,17 +71,23 @@ __global__ void __launch_bounds__(256) k_adam_cols(T* __restrict__ params, T* __
 // 0.080 ms; non-temporal moment stores alone changed nothing).
 template <typename T>
 __global__ void __launch_bounds__(256) k_adam_sweep(T* __restrict__ params, T* __restrict__ m1, T* __restrict__ m2,
-                                                    const int32_t* __restrict__ order, int32_t B, int64_t n_pidx,
-                                                    const uint32_t* __restrict__ active,
+                                                    uint32_t* __restrict__ step, const int32_t* __restrict__ order,
+                                                    int32_t B, int64_t n_pidx, const uint32_t* __restrict__ active,
                                                     const uint32_t* __restrict__ act_idx, const T* __restrict__ grad,
-                                                    int64_t ld, AdamK<T> K, const float2* __restrict__ bias) {
+                                                    int64_t ld, AdamK<T> K, double lb1, double lb2) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_pidx || !active[i]) return;
   const int64_t k = i / B;
   const int32_t row = (int32_t)(i - k * B);
   const int64_t o0 = (int64_t)order[k] * kD * B + row;
   const T* gp = grad + (int64_t)act_idx[i];
-  const float2 bc = bias[i];
+  // the row's step and bias corrections (what k_adam_rows computes for the
+  // column-grid update), in the same precision
+  const int64_t si = (int64_t)order[k] * B + row;
+  const uint32_t t = step[si] + 1u;
+  step[si] = t;
+  const double c1 = 1.0 - exp2((double)t * lb1), c2 = 1.0 - exp2((double)t * lb2);
+  const float2 bc = make_float2((float)(1.0 / c1), (float)(1.0 / sqrt(c2)));
 #pragma unroll 4
   for (int j = 0; j < kD; ++j) {
     const int64_t o = o0 + (int64_t)j * B;
@@ -172,21 +180,22 @@ extern "C" tide_status tide_adam_sparse(tide_pool* pool, const tide_proj* proj, 
   const uint32_t gb = (uint32_t)((int64_t)pool->n_order * ceil_div(pool->block_rows, kBoundRows));
   float2* bias = (float2*)ws;
   const double lb1 = std::log2((double)cfg->beta1), lb2 = std::log2((double)cfg->beta2);
-  hipLaunchKernelGGL(k_adam_rows, dim3(gx), dim3(256), 0, st, pool->step, pool->order, pool->block_rows, n,
-                     proj->active, lb1, lb2, bias);
-  TIDE_LAUNCH_CHECK("k_adam_rows");
   if (pool->dtype == TIDE_F32) {
     AdamK<float> K;
     for (int j = 0; j < kD; ++j) K.lr[j] = cfg->lr[j];
     K.b1 = cfg->beta1; K.b2 = cfg->beta2; K.eps = cfg->eps; K.kappa = cfg->kappa;
+    // the row sweep takes the step and bias corrections itself
     TIDE_TIMED("adam", st, hipLaunchKernelGGL(k_adam_sweep<float>, dim3(gx), dim3(256), 0, st,
                                               (float*)pool->params, (float*)pool->exp_avg, (float*)pool->exp_avg_sq,
-                                              pool->order, pool->block_rows, n, proj->active, proj->act_idx,
-                                              (const float*)grad, grad_ld, K, bias));
+                                              pool->step, pool->order, pool->block_rows, n, proj->active,
+                                              proj->act_idx, (const float*)grad, grad_ld, K, lb1, lb2));
     if (spheres || dirty)
       hipLaunchKernelGGL(k_adam_bounds<float>, dim3(gb), dim3(256), 0, st, (const float*)pool->params, pool->order,
                          pool->slot_block, pool->block_rows, n, proj->active, cfg->kappa, spheres, dirty);
   } else {
+    hipLaunchKernelGGL(k_adam_rows, dim3(gx), dim3(256), 0, st, pool->step, pool->order, pool->block_rows, n,
+                       proj->active, lb1, lb2, bias);
+    TIDE_LAUNCH_CHECK("k_adam_rows");
     AdamK<double> K;
     for (int j = 0; j < kD; ++j) K.lr[j] = cfg->lr[j];
     K.b1 = cfg->beta1; K.b2 = cfg->beta2; K.eps = cfg->eps; K.kappa = cfg->kappa;
