@@ -189,6 +189,44 @@ def test_bin_sort_capacity_retry_gives_the_same_lists():
     say(f"instances {bins.n_inst}: retry from capacity 5000 identical")
 
 
+def test_bin_sort_with_a_misaligned_workspace_matches():
+    """A workspace 4 bytes off 16-byte alignment: the scans, the radix
+    histograms and the range pass take their one-element paths instead of
+    16-byte accesses; the lists must equal those of the aligned call."""
+    import ctypes as C
+
+    from paper_2605_20150_amd import _lib as L
+    say("case: dense scene, bin_sort on a workspace 4 bytes off alignment")
+    th, cams = dense_case()
+    rast, pool, proj, bins, _ = gpu_forward(th, cams, block_rows=1024)
+    a = bins_views(rast, bins)
+    lib = L.load()
+    wsb = lib.tide_bin_sort_ws_bytes(proj.n_cams, proj.n_pidx, bins.tiles_x, bins.tiles_y, rast.inst_cap)
+    buf = torch.zeros(wsb + 64, dtype=torch.uint8, device="cuda")
+    base = buf.data_ptr() + 4
+    assert base % 16 == 4
+    b2 = L.tide_bins()
+    pc = proj.c()
+    L.check(lib.tide_bin_sort(C.byref(pc), bins.tiles_x, bins.tiles_y, C.c_void_p(base), wsb, C.byref(b2),
+                              C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+    torch.cuda.synchronize()
+
+    def view(ptr, count):
+        off = int(ptr) - buf.data_ptr()
+        assert off % 4 == 0 and 0 <= off and off + 4 * count <= buf.numel()
+        return buf[off: off + 4 * count].view(torch.int32)
+
+    VT = b2.n_cams * b2.tiles_x * b2.tiles_y
+    assert (b2.n_vis, b2.n_inst) == (bins.n_vis, bins.n_inst)
+    assert torch.equal(view(b2.ranges, 2 * VT).view(VT, 2), a["ranges"])
+    assert torch.equal(view(b2.tile_order, VT), a["tile_order"])
+    assert torch.equal(view(b2.vis_rec, b2.n_vis), a["vis_rec"])
+    assert torch.equal(view(b2.inst_off, b2.n_vis + 1), a["inst_off"])
+    e2 = view(b2.inst_e, b2.n_inst).long()
+    assert torch.equal(view(b2.inst_rec, b2.n_inst)[e2], a["inst_rec"][a["inst_e"].long()])
+    say(f"instances {b2.n_inst}: misaligned workspace gives identical lists")
+
+
 def test_compositing_matches_oracle_on_oracle_records():
     say("case: dense scene, stage-isolated compositing on oracle records")
     th, cams = dense_case()
