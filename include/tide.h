@@ -17,7 +17,12 @@
  *     must be device (HBM) pointers; "host" pointers are ordinary memory.
  *     The library never allocates device memory on the per-iteration path;
  *     calls that need scratch take a caller workspace (ws, ws_bytes) and
- *     report the size they need.
+ *     report the size they need.  Device buffers and workspaces must be at
+ *     least 8-byte aligned (f64 data: 8; records of four-byte values are
+ *     moved as unaligned 16-byte pieces, which need 4); 256-byte alignment,
+ *     what hipMalloc and torch give, lets the scans, histograms and range
+ *     pass of tide_bin_sort use 16-byte accesses (they fall back to
+ *     one-element accesses otherwise).
  *   - Device work is enqueued on the HIP stream passed as `stream`
  *     (a hipStream_t; NULL = the default stream) and is asynchronous unless a
  *     call says it blocks.
