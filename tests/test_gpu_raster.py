@@ -190,21 +190,21 @@ def test_bin_sort_capacity_retry_gives_the_same_lists():
 
 
 def test_bin_sort_with_a_misaligned_workspace_matches():
-    """A workspace 4 bytes off 16-byte alignment: the scans, the radix
+    """A workspace 8 bytes off 16-byte alignment: the scans, the radix
     histograms and the range pass take their one-element paths instead of
     16-byte accesses; the lists must equal those of the aligned call."""
     import ctypes as C
 
     from paper_2605_20150_amd import _lib as L
-    say("case: dense scene, bin_sort on a workspace 4 bytes off alignment")
+    say("case: dense scene, bin_sort on a workspace 8 bytes off 16-byte alignment")
     th, cams = dense_case()
     rast, pool, proj, bins, _ = gpu_forward(th, cams, block_rows=1024)
     a = bins_views(rast, bins)
     lib = L.load()
     wsb = lib.tide_bin_sort_ws_bytes(proj.n_cams, proj.n_pidx, bins.tiles_x, bins.tiles_y, rast.inst_cap)
     buf = torch.zeros(wsb + 64, dtype=torch.uint8, device="cuda")
-    base = buf.data_ptr() + 4
-    assert base % 16 == 4
+    base = buf.data_ptr() + 8
+    assert base % 16 == 8
     b2 = L.tide_bins()
     pc = proj.c()
     L.check(lib.tide_bin_sort(C.byref(pc), bins.tiles_x, bins.tiles_y, C.c_void_p(base), wsb, C.byref(b2),
