@@ -177,12 +177,5 @@ __device__ __forceinline__ double row_sum_to_15(double x) {
   return x;
 }
 
-// After row_sum_to_15: lane 31 adds row 0's total to row 1's and lane 63
-// row 2's to row 3's (lanes 31 and 63 hold the sums of rows 0-1 and 2-3).
-__device__ __forceinline__ float pair_rows(float x) { return x + dpp_f32<0x142, 0xA, false>(x); }
-__device__ __forceinline__ double pair_rows(double x) {
-  const double y = __shfl_up(x, 16, 32);
-  return (__lane_id() & 31) >= 16 ? x + y : x;
-}
 
 }  // namespace tide

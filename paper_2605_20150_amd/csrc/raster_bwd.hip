@@ -22,10 +22,12 @@ struct __attribute__((aligned(sizeof(T)))) Rec9 {
 // normalised colour behind the entry (r_{i-1} = alpha_i c_i + (1-alpha_i) r_i,
 // starting from the background).  The per-pixel update is branch-free; the
 // four pixels of a lane are summed in registers, each row of 16 lanes is
-// reduced with DPP, rows are added in pairs (0 + 1, 2 + 3) and the two pair
-// sums are parked in LDS (small enough for four waves per SIMD); once a
-// batch of 64 entries is done, lane k adds entry k's two pair sums and
-// stores its partial.  Entries no pixel reaches get zero partials.
+// reduced with DPP and the four row sums are parked in LDS; once a batch of
+// 32 entries is done, lane k adds entry k's four row sums and stores its
+// partial.  (Batches of 32 keep the parked sums at the LDS size that 64
+// entries with rows added in pairs took, so occupancy is unchanged, and each
+// taken entry saves the nine pair additions.)  Entries no pixel reaches get
+// zero partials.
 template <typename T>
 __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ order,
                                                    const uint32_t* __restrict__ ranges,
@@ -80,11 +82,11 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
   }
   __shared__ T s_u[64], s_v[64], s_Ah[64], s_Bh[64], s_Ch[64], s_A[64], s_B[64], s_C[64], s_o[64], s_r[64],
       s_g[64], s_b[64];
-  __shared__ T s_part[64][2][kG2];   // per entry, the sums of rows 0-1 and 2-3
+  __shared__ T s_part[32][4][kG2];   // per entry, the sums of the four rows
   __shared__ uint32_t s_hit[64], s_take[64];
   const T ks = (T)Ex<T>::k;
-  for (int32_t hi = (int32_t)maxl; hi > 0; hi -= 64) {
-    const int32_t lo = hi - 64 > 0 ? hi - 64 : 0;
+  for (int32_t hi = (int32_t)maxl; hi > 0; hi -= 32) {
+    const int32_t lo = hi - 32 > 0 ? hi - 32 : 0;
     const int32_t n = hi - lo;
     uint32_t my_e = 0;
     if (lane < n) {
@@ -159,11 +161,8 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
       a_u = row_sum_to_15(a_u); a_v = row_sum_to_15(a_v); a_A = row_sum_to_15(a_A);
       a_B = row_sum_to_15(a_B); a_C = row_sum_to_15(a_C); a_o = row_sum_to_15(a_o);
       a_r = row_sum_to_15(a_r); a_g = row_sum_to_15(a_g); a_b = row_sum_to_15(a_b);
-      a_u = pair_rows(a_u); a_v = pair_rows(a_v); a_A = pair_rows(a_A); a_B = pair_rows(a_B);
-      a_C = pair_rows(a_C); a_o = pair_rows(a_o); a_r = pair_rows(a_r); a_g = pair_rows(a_g);
-      a_b = pair_rows(a_b);
-      if ((lane & 31) == 31) {
-        T* S = s_part[k][lane >> 5];
+      if ((lane & 15) == 15) {
+        T* S = s_part[k][lane >> 4];
         S[0] = a_u; S[1] = a_v; S[2] = a_A; S[3] = a_B; S[4] = a_C;
         S[5] = a_o; S[6] = a_r; S[7] = a_g; S[8] = a_b;
       }
@@ -174,7 +173,7 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
       if (s_hit[lane]) {
 #pragma unroll
         for (int m = 0; m < kG2; ++m)
-          r.v[m] = s_part[lane][0][m] + s_part[lane][1][m];
+          r.v[m] = (s_part[lane][0][m] + s_part[lane][1][m]) + (s_part[lane][2][m] + s_part[lane][3][m]);
         // dpower/dA = -dx^2/2, dpower/dB = -dx dy, dpower/dC = -dy^2/2
         r.v[2] *= (T)-0.5;
         r.v[3] = -r.v[3];
