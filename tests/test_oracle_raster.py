@@ -480,3 +480,100 @@ def test_adam_first_and_second_step_closed_forms_and_mask():
     exp2 = a1 - lr * mh / (np.sqrt(vh) + 1e-15)
     assert np.allclose(a2[act == 1], exp2[act == 1], rtol=1e-12, atol=1e-15)
     assert np.array_equal(a2[act == 0], th[act == 0])
+
+
+# --------------------------------------------- EWA tangent clamp (reading A-5)
+# A Gaussian whose centre lies beyond 1.3 x the half-fov tangent off the
+# optical axis keeps the Jacobian of the pinhole map at the clamp boundary:
+# the covariance is the sandwich with the derivative of the projection taken
+# at the point of the same depth on the boundary ray, and that Jacobian's
+# dependence on the tangent is dropped from the gradient (only its depth
+# dependence remains).  64 x 64 camera, f = 64: the limit is 1.3 * 32 / 64 =
+# 0.65 in both axes.
+CLAMP_CASES = {
+    "x": (0.80, 0.10),      # tangents x / z, y / z of the centre
+    "y": (-0.15, -0.78),
+    "xy": (0.74, 0.70),
+    "none": (0.30, -0.20),  # inside the limits: the plain sandwich
+}
+
+
+def _clamp_case(name, q=(0.8, 0.3, -0.4, 0.2)):
+    tx, ty = CLAMP_CASES[name]
+    z = 3.0
+    # camera at the origin of world = camera space (R = I, t = 0), so the
+    # centre's camera coordinates are (tx z, ty z, z)
+    mu = np.array([tx * z, ty * z, z])
+    th = one_gaussian(mu, np.log([0.55, 0.42, 0.5]), q=q, ologit=1.2, dc=(0.7, 0.4, 0.3), rest=0.03)
+    th[0, 14:] = np.random.default_rng(17).normal(0, 0.05, size=45)
+    return th, cam_row(t=(0.0, 0.0, 0.0))
+
+
+def _pix(p, f=64.0, c=32.0):
+    return np.array([f * p[0] / p[2] + c, f * p[1] / p[2] + c])
+
+
+def _num_jacobian(p):
+    J = np.zeros((2, 3))
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = 1e-6
+        J[:, a] = (_pix(p + e) - _pix(p - e)) / 2e-6
+    return J
+
+
+@pytest.mark.parametrize("name", ["x", "y", "xy", "none"])
+def test_clamped_ewa_covariance_uses_the_boundary_jacobian(name):
+    th, cam = _clamp_case(name)
+    p = oracle.project(th, cam)
+    assert p["keep"][0, 0], "the footprint must reach the image"
+    mu = th[0, :3]
+    lim = 1.3 * 32 / 64
+    tx, ty = mu[0] / mu[2], mu[1] / mu[2]
+    assert (abs(tx) > lim) == ("x" in name) and (abs(ty) > lim) == ("y" in name)
+    pc = np.array([np.clip(tx, -lim, lim) * mu[2], np.clip(ty, -lim, lim) * mu[2], mu[2]])
+    q = th[0, 6:10]
+    rot = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+    Sig = rot @ np.diag(np.exp(2 * th[0, 3:6])) @ rot.T
+    S = _num_jacobian(pc) @ Sig @ _num_jacobian(pc).T
+    cov = p["cov2d"][0, 0]
+    assert np.allclose([cov[0] - 0.3, cov[1], cov[2] - 0.3], [S[0, 0], S[0, 1], S[1, 1]], rtol=1e-6, atol=1e-9)
+    if name != "none":
+        # not vacuous: the Jacobian at the centre itself gives another footprint
+        S0 = _num_jacobian(mu) @ Sig @ _num_jacobian(mu).T
+        assert np.abs(np.array([cov[0] - 0.3, cov[1], cov[2] - 0.3]) - [S0[0, 0], S0[0, 1], S0[1, 1]]).max() > \
+            1e-2 * np.abs(S0).max()
+    # the mean itself is not clamped
+    assert np.abs([p["u"][0, 0], p["v"][0, 0]] - _pix(mu)).max() < 1e-12
+
+
+@pytest.mark.parametrize("name", ["x", "y", "xy"])
+def test_clamped_ewa_backward_matches_central_differences_all_columns(name):
+    """All 59 columns of a single off-axis Gaussian under a linear loss
+    L = sum(w * image) against FP64 central differences (eps = 1e-6) in
+    the clamped regime, where the derivative of the covariance with respect
+    to the centre goes through the depth of the clamped Jacobian only."""
+    th, cam = _clamp_case(name)
+    w = np.random.default_rng(18).normal(size=(1, 3, 64, 64))
+    base = _decisions(th, cam)
+    grad = oracle.backward(th, cam, w)
+
+    def L(t):
+        return float((oracle.render(t, cam)["image"] * w).sum())
+
+    checked = 0
+    for col in range(59):
+        e = 1e-6
+        tp, tm = th.copy(), th.copy()
+        tp[0, col] += e
+        tm[0, col] -= e
+        if any(not np.array_equal(a, b) for a, b in zip(_decisions(tp, cam), base)) or \
+           any(not np.array_equal(a, b) for a, b in zip(_decisions(tm, cam), base)):
+            continue
+        fd = (L(tp) - L(tm)) / (2 * e)
+        assert abs(grad[0, col] - fd) <= 1e-5 * abs(fd) + 1e-8, (name, col, grad[0, col], fd)
+        checked += 1
+    assert checked >= 55
+    # the mean's gradient is not dominated by the unclamped mean shift: the
+    # covariance's share is what the clamp changes
+    assert np.abs(grad[0, :3]).max() > 0
