@@ -264,8 +264,9 @@ typedef struct {
 } tide_adam_cfg;
 
 size_t tide_adam_ws_bytes(int64_t n_pidx);
-/* ws: tide_adam_ws_bytes(proj->n_pidx) bytes of device scratch (per-row bias
- * corrections). */
+/* ws: tide_adam_ws_bytes(proj->n_pidx) bytes of device scratch, 16-byte
+ * aligned (the double-precision per-row bias corrections of the TIDE_F64
+ * update). */
 tide_status tide_adam_sparse(tide_pool* pool, const tide_proj* proj, const void* grad,
                              int64_t grad_ld, const tide_adam_cfg* cfg, float* spheres,
                              uint8_t* dirty, int64_t n_blocks, void* ws, size_t ws_bytes,

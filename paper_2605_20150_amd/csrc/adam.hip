@@ -15,9 +15,9 @@ struct AdamK {
 // Passes over the active rows; inactive rows are never written, so they
 // stay bit-identical.
 //  1. Per row, step += 1 and the bias corrections 1/(1 - b1^t),
-//     1/sqrt(1 - b2^t) (double precision): inside k_adam_sweep in single
-//     precision; k_adam_rows into a row table for the double-precision
-//     update.
+//     1/sqrt(1 - b2^t), evaluated in double precision: inside k_adam_sweep,
+//     rounded to single precision for its update; k_adam_rows into a row
+//     table of doubles for the double-precision update.
 //  2. k_adam_sweep (single precision): one thread per row over its 59
 //     columns; k_adam_cols (double precision): a 2-D grid (rows x 59
 //     columns), one element per thread.
@@ -25,7 +25,7 @@ struct AdamK {
 //     bounding-sphere refresh r_k = max(r_k, |mu - c_k| + 3 kappa max scale).
 __global__ void __launch_bounds__(256) k_adam_rows(uint32_t* __restrict__ step, const int32_t* __restrict__ order,
                                                    int32_t B, int64_t n_pidx, const uint32_t* __restrict__ active,
-                                                   double lb1, double lb2, float2* __restrict__ bias) {
+                                                   double lb1, double lb2, double2* __restrict__ bias) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_pidx || !active[i]) return;
   const int64_t k = i / B;
@@ -34,7 +34,7 @@ __global__ void __launch_bounds__(256) k_adam_rows(uint32_t* __restrict__ step, 
   const uint32_t t = step[si] + 1u;
   step[si] = t;
   const double c1 = 1.0 - exp2((double)t * lb1), c2 = 1.0 - exp2((double)t * lb2);
-  bias[i] = make_float2((float)(1.0 / c1), (float)(1.0 / sqrt(c2)));
+  bias[i] = make_double2(1.0 / c1, 1.0 / sqrt(c2));
 }
 
 template <typename T>
@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(256) k_adam_cols(T* __restrict__ params, T* __
                                                    const int32_t* __restrict__ order, int32_t B, int64_t n_pidx,
                                                    const uint32_t* __restrict__ active,
                                                    const uint32_t* __restrict__ act_idx, const T* __restrict__ grad,
-                                                   int64_t ld, AdamK<T> K, const float2* __restrict__ bias) {
+                                                   int64_t ld, AdamK<T> K, const double2* __restrict__ bias) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (i >= n_pidx || !active[i]) return;
@@ -50,7 +50,7 @@ __global__ void __launch_bounds__(256) k_adam_cols(T* __restrict__ params, T* __
   const int32_t row = (int32_t)(i - k * B);
   const int64_t o = ((int64_t)order[k] * kD + j) * B + row;
   const T g = grad[(int64_t)act_idx[i] + (int64_t)j * ld];
-  const float2 bc = bias[i];
+  const double2 bc = bias[i];
   const T m = K.b1 * m1[o] + ((T)1 - K.b1) * g;
   const T v = K.b2 * m2[o] + ((T)1 - K.b2) * g * g;
   m1[o] = m;
@@ -157,7 +157,7 @@ __global__ void __launch_bounds__(256) k_adam_bounds(const T* __restrict__ param
 
 using namespace tide;
 
-extern "C" size_t tide_adam_ws_bytes(int64_t n_pidx) { return align_up((size_t)(n_pidx > 0 ? n_pidx : 1) * 8) + 256; }
+extern "C" size_t tide_adam_ws_bytes(int64_t n_pidx) { return align_up((size_t)(n_pidx > 0 ? n_pidx : 1) * 16) + 256; }
 
 extern "C" tide_status tide_adam_sparse(tide_pool* pool, const tide_proj* proj, const void* grad, int64_t grad_ld,
                                         const tide_adam_cfg* cfg, float* spheres, uint8_t* dirty, int64_t n_blocks,
@@ -172,13 +172,14 @@ extern "C" tide_status tide_adam_sparse(tide_pool* pool, const tide_proj* proj, 
                  "bad Adam constants");
   TIDE_CHECK_ARG((!spheres && !dirty) || n_blocks > 0, "n_blocks must be given with spheres/dirty");
   TIDE_CHECK_ARG(ws_bytes >= tide_adam_ws_bytes(proj->n_pidx), "adam workspace too small");
+  TIDE_CHECK_ARG(aligned16(ws), "adam workspace must be 16-byte aligned");
   hipStream_t st = (hipStream_t)stream;
   const int64_t n = proj->n_pidx;
   if (n == 0) return TIDE_OK;
   const uint32_t gx = (uint32_t)ceil_div(n, 256);
   // bound workgroups: kBoundRows indices each, never straddling a block
   const uint32_t gb = (uint32_t)((int64_t)pool->n_order * ceil_div(pool->block_rows, kBoundRows));
-  float2* bias = (float2*)ws;
+  double2* bias = (double2*)ws;
   const double lb1 = std::log2((double)cfg->beta1), lb2 = std::log2((double)cfg->beta2);
   if (pool->dtype == TIDE_F32) {
     AdamK<float> K;

@@ -494,6 +494,11 @@ struct tide_residency {
     if (host_pool) return nullptr;
     hipEvent_t ev = fences[fence_next];
     fence_next = (fence_next + 1) % (int)fences.size();
+    // The slot was last recorded for a copy that many copies back, and the
+    // host entry of that copy may still hold it: let that copy finish before
+    // the slot is re-recorded, so a wait on the old handle never returns
+    // ahead of the copy it stood for.
+    (void)hipEventSynchronize(ev);
     (void)hipEventRecord(ev, s);
     return ev;
   }
@@ -1053,18 +1058,21 @@ tide_status tide_stream_delta(tide_residency* res, const int32_t* knext_ids, con
     }
     off += knext_counts[j];
   }
-  // 2. recency: age 0 for the accessed resident blocks R_t intersect K_t
+  // 2. recency: age 0 for the accessed resident blocks R_t intersect K_t.
+  //    The new ages are kept aside and stored only once the call can no
+  //    longer fail, so a rejected call leaves the tier's state unchanged.
+  std::vector<double> age(res->K);
   {
     std::vector<uint8_t> acc(res->K, 0);
     for (int32_t k : res->Kcur)
       if (res->R.count(k)) acc[k] = 1;
-    for (int64_t k = 0; k < res->K; ++k) res->age[k] = acc[k] ? 0.0 : res->age[k] + 1.0;
+    for (int64_t k = 0; k < res->K; ++k) age[k] = acc[k] ? 0.0 : res->age[k] + 1.0;
   }
   // 3.-5. candidates, scores, camera-balanced Top-C
   std::set<int32_t> Ct = res->R;
   Ct.insert(Kn.begin(), Kn.end());
   const double lam = res->lambda, gam = res->gamma;
-  auto score = [&](int32_t k) { return lam * (Kn.count(k) ? 1.0 : 0.0) + (1.0 - lam) * std::pow(gam, res->age[k]); };
+  auto score = [&](int32_t k) { return lam * (Kn.count(k) ? 1.0 : 0.0) + (1.0 - lam) * std::pow(gam, age[k]); };
   auto better = [&](int32_t a, int32_t b) {
     const double sa = score(a), sb = score(b);
     return sa != sb ? sa > sb : a < b;
@@ -1102,7 +1110,11 @@ tide_status tide_stream_delta(tide_residency* res, const int32_t* knext_ids, con
     for (int32_t k : res->R)
       if (!chosen.count(k)) Sm.push_back(k);
   }
-  if (out_plus) TIDE_CHECK_ARG((int64_t)Sp.size() <= cap && (int64_t)Sm.size() <= cap, "delta output capacity");
+  if (out_plus) TIDE_CHECK_ARG((int64_t)Sp.size() <= cap, "S+ (%zu blocks) exceeds the output capacity %lld", Sp.size(),
+                               (long long)cap);
+  if (out_minus) TIDE_CHECK_ARG((int64_t)Sm.size() <= cap, "S- (%zu blocks) exceeds the output capacity %lld",
+                                Sm.size(), (long long)cap);
+  res->age.swap(age);
   if (n_plus) *n_plus = (int32_t)Sp.size();
   if (n_minus) *n_minus = (int32_t)Sm.size();
   if (out_plus) std::copy(Sp.begin(), Sp.end(), out_plus);

@@ -103,6 +103,53 @@ def test_alg1_decisions_match_oracle(tmp_path):
     t.close()
 
 
+def test_stream_delta_rejects_a_small_output_without_changing_state(tmp_path):
+    """An output array too small for S+ or S- (the other one null) is an
+    argument error, whichever of the two is given, and the rejected call
+    leaves the tier as it was: the next call's S+ and S- still follow Alg. 1
+    from the state before the rejection."""
+    import ctypes as C
+
+    from paper_2605_20150_amd import _lib as L
+    th = scene()
+    t, pool = build(tmp_path, th, n_slots=6, capacity=6, cache=6)
+    rng = np.random.default_rng(44)
+    sets = walk_sets(rng, t.K, 30)
+    age = np.full(t.K, 1e9)
+    Kt = sorted(set(x for s in sets[0] for x in s))
+    t.ensure_resident(Kt)
+    R = sorted(t.resident_slots())
+    tried = {"plus": 0, "minus": 0}
+    for i in range(1, len(sets)):
+        Rn, sp_ref, sm_ref, age, _ = oracle.alg1(R, Kt, sets[i], age, 0.75, 0.9, 6)
+        t.end_iteration()
+        lists = [sorted(set(int(x) for x in k)) for k in sets[i]]
+        flat = np.ascontiguousarray([x for l in lists for x in l] or [0], dtype=np.int32)
+        counts = np.ascontiguousarray([len(l) for l in lists], dtype=np.int32)
+        buf = np.zeros(t.K, dtype=np.int32)
+        npl, nmi = C.c_int32(-7), C.c_int32(-7)
+        pi32 = C.POINTER(C.c_int32)
+        fp, cp, bp = (a.ctypes.data_as(pi32) for a in (flat, counts, buf))
+        for which, need in (("plus", len(sp_ref)), ("minus", len(sm_ref))):
+            if need == 0:
+                continue
+            args = (bp, None) if which == "plus" else (None, bp)
+            rc = t.lib.tide_stream_delta(t.h, fp, cp, len(lists), None, args[0], C.byref(npl), args[1],
+                                         C.byref(nmi), need - 1)
+            assert rc == L.TIDE_EINVAL, (i, which, rc)
+            assert npl.value == -7 and nmi.value == -7 and not buf.any()
+            tried[which] += 1
+        sp, sm = t.stream_delta(sets[i])
+        t.sync_bounds()
+        assert sp.tolist() == sp_ref and sm.tolist() == sm_ref, i
+        Kt = sorted(set(x for s in sets[i] for x in s))
+        t.ensure_resident(Kt)
+        R = sorted(t.resident_slots())
+        assert R == Rn.tolist()
+    assert tried["plus"] > 0 and tried["minus"] > 0
+    t.close()
+
+
 def test_residency_moves_data_and_writes_back(tmp_path, odirect=False):
     """Blocks updated while resident are written back through the host cache
     (dirty) to patch segments; a tiny host cache forces flushes; a reopened
