@@ -58,6 +58,7 @@ def _declare(L):
     L.orc_sh_basis_grad.argtypes = [_d, _d]
     L.orc_project.argtypes = [_d, C.c_int64, _d, C.c_int, _d, _i32, _d]
     L.orc_tile_rect.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int, C.c_int, _i32]
+    L.orc_tile_rects.argtypes = [_d, _d, _i32, C.c_int64, C.c_int, C.c_int, _i32]
     L.orc_bin.argtypes = [_d, _d, _d, _i32, _i32, C.c_int64, _d, C.c_int, _i64, C.c_int64, _i64]
     L.orc_bin.restype = C.c_int64
     L.orc_composite.argtypes = [_i64, _i64, _d, C.c_int64, _d, C.c_int, _d, _d, _d, _i32, _i64, _d, _d]
@@ -136,6 +137,16 @@ def project(theta, cams):
 def tile_rect(u, v, r, Tx, Ty):
     out = np.zeros(4, dtype=np.int32)
     lib().orc_tile_rect(float(u), float(v), int(r), int(Tx), int(Ty), _p(out, _i32))
+    return out
+
+
+def tile_rects(u, v, r, Tx, Ty):
+    """O4's rectangle (x0, y0, x1, y1) for each of the n triples (u, v, r);
+    int32 [n, 4], empty rectangles as zeros."""
+    u, v = _f64(u).ravel(), _f64(v).ravel()
+    r = np.ascontiguousarray(r, dtype=np.int32).ravel()
+    out = np.zeros((u.size, 4), dtype=np.int32)
+    lib().orc_tile_rects(_p(u, _d), _p(v, _d), _p(r, _i32), u.size, int(Tx), int(Ty), _p(out, _i32))
     return out
 
 

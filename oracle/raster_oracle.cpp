@@ -464,6 +464,18 @@ void orc_tile_rect(double u, double v, int r, int Tx, int Ty, int32_t* rect) {
   for (int k = 0; k < 4; ++k) rect[k] = q[k];
 }
 
+// O4's tile rectangle for n (u, v, r) triples on one camera's Tx x Ty grid
+// (the same rule as orc_tile_rect, one call per triple).
+void orc_tile_rects(const double* u, const double* v, const int32_t* r, int64_t n, int Tx, int Ty,
+                    int32_t* rect) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    int q[4];
+    tile_rect(u[i], v[i], r[i], Tx, Ty, q);
+    for (int k = 0; k < 4; ++k) rect[4 * i + k] = q[k];
+  }
+}
+
 // Binning and sort, O6, for all cameras.  Inputs are per (camera, Gaussian):
 // u, v, depth, integer radius and keep flag.  Returns the number of
 // instances; fills the outputs only when it does not exceed `cap`.

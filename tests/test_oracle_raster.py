@@ -166,6 +166,20 @@ def test_tile_rect_matches_interval_enumeration():
         assert list(oracle.tile_rect(u, v, r, 7, 5)) == _brute_rect(u, v, r, 7, 5), (u, v, r)
 
 
+def test_bulk_tile_rects_match_interval_enumeration():
+    """The many-triple form of O4's rectangle against the same enumeration
+    (it drives the stage-isolated comparison of the GPU's rectangles)."""
+    rng = np.random.default_rng(9)
+    n = 400
+    u = rng.uniform(-40, 140, n).astype(np.float32).astype(np.float64)
+    v = rng.uniform(-40, 120, n).astype(np.float32).astype(np.float64)
+    u[:4] = (16.0, 15.999999, -5.0, 31.5)
+    r = rng.integers(0, 30, n).astype(np.int32)
+    got = oracle.tile_rects(u, v, r, 7, 5)
+    for i in range(n):
+        assert list(got[i]) == _brute_rect(u[i], v[i], int(r[i]), 7, 5), (u[i], v[i], r[i])
+
+
 # ------------------------------------------------------------- sort (O6)
 def test_binning_matches_brute_force_per_tile_scan():
     th = synth.dense_scene(400, 11, logscale_mu=-3.0).astype(np.float64)
