@@ -30,9 +30,16 @@ METRIC = "train iters/s & Gaussian-pixel visits/s fwd+bwd; HBM GB/s vs peak; sta
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 
-# Algorithmic work per unit (counted from the formulas each kernel evaluates)
-FLOPS_PER_FWD_VISIT = 21      # offset 2, exponent 8, exp 1, alpha 1, transmittance 2, weight 1, colour 6
-FLOPS_PER_BWD_VISIT = 64      # the forward terms plus T recovery, colour/alpha/conic/mean adjoints
+# Algorithmic work per visit of the compositing kernels, the byte/flop model
+# of the method's per-pixel formulas: about 20 arithmetic operations and one
+# exponential per forward visit (offset 2, exponent 8, exp 1, alpha 1,
+# transmittance 2, weight 1, colour 6), about 50 and two transcendentals
+# (exponential, reciprocal) per backward visit; a transcendental counts as one.
+FLOPS_PER_FWD_VISIT = 21
+FLOPS_PER_BWD_VISIT = 52
+# Kernels bound by HBM: their algorithmic GB/s is reported as a fraction of
+# the 8 TB/s peak as well.
+HBM_BOUND = ("preprocess", "reduce_pairs", "adjoint", "adam", "loss_fwd", "loss_bwd")
 # HBM traffic per launch of the dominant kernel from two rocprofv3 counter
 # passes (FETCH_SIZE, WRITE_SIZE) of this benchmark, each scaled by what the
 # counter reads for a plain 1 GiB device copy (x1.9999 and x1.0000), and the
@@ -50,6 +57,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="OpenMP threads of the oracle in the CPU baseline (0 = all cores)")
+    ap.add_argument("--cpu-baseline-only", action="store_true",
+                    help="time only the oracle's iteration (no GPU), e.g. at --cpu-threads 1")
     ap.add_argument("--n-blobs", type=int, default=200)
     ap.add_argument("--per-blob", type=int, default=5000)
     ap.add_argument("--workload", choices=["aerial", "city", "city-ablation", "city-budget", "city-order",
@@ -112,34 +123,52 @@ def measured_traffic(kernel):
     return t["bytes"] if h.hexdigest()[:16] == t["sha256_16"] else None
 
 
-def cpu_baseline(theta, cams, targets0):
-    """The FP64 oracle (as it stands) on one view of batch 0: forward, loss,
-    backward and masked Adam over all 1M Gaussians; the batch has 4 views, so
-    one iteration costs 4 such samples."""
+def cpu_baseline(theta, cams, targets, threads=0):
+    """The FP64 oracle (as it stands), built -O3 -march=native on this host,
+    over one whole iteration of the timed workload: the 4 views of batch 0
+    through projection, binning, compositing, loss, backward and masked
+    Adam, each stage timed.  threads = 0 uses every core the OpenMP runtime
+    offers."""
+    import tempfile
+
     import numpy as np
 
     import oracle
+    from paper_2605_20150_amd.synth import cams_array
+    so = os.path.join(tempfile.gettempdir(), f"liboracle_native_{os.getpid()}.so")
+    oracle.build(force=True, so=so, native=True)
+    oracle.use(so)
+    used = oracle.set_threads(threads)
     th = theta.astype(np.float64)
-    cm = __import__("paper_2605_20150_amd.synth", fromlist=["cams_array"]).cams_array(cams[:1])
-    t0 = time.perf_counter()
-    r = oracle.render(th, cm)
-    t1 = time.perf_counter()
-    _, dimg = oracle.loss(r["image"], targets0[:1])
-    t2 = time.perf_counter()
+    cm = cams_array(cams)
+    t = [time.perf_counter()]
+    p = oracle.project(th, cm)
+    t.append(time.perf_counter())
+    radius = np.where(p["keep"], p["radius"], 0)
+    gid, ranges = oracle.bin_sort(p["u"], p["v"], np.float32(p["depth"]).astype(np.float64), radius, p["keep"], cm)
+    t.append(time.perf_counter())
+    rec = np.concatenate([p["u"][..., None], p["v"][..., None], p["conic"], p["opacity"][..., None], p["rgb"]], -1)
+    r = oracle.composite(gid, ranges, rec, cm)
+    t.append(time.perf_counter())
+    _, dimg = oracle.loss(r["image"], targets)
+    t.append(time.perf_counter())
     g = oracle.backward(th, cm, dimg)
-    t3 = time.perf_counter()
-    act = r["keep"].any(0).astype(np.uint8)
+    t.append(time.perf_counter())
     z = np.zeros_like(th)
-    oracle.adam(th, z, z, np.zeros(th.shape[0], dtype=np.int64), g, act)
-    t4 = time.perf_counter()
-    per_view = t4 - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": 1.0 / (4.0 * per_view), "unit": "iters/s", "cores": threads, "kind": "oracle",
-            "cpu": cpu_model(),
-            "sample": (f"FP64 oracle, one 1920x1080 view of batch 0 over all {th.shape[0]} Gaussians: "
-                       f"forward {t1 - t0:.1f} s, loss {t2 - t1:.1f} s, backward {t3 - t2:.1f} s, "
-                       f"Adam {t4 - t3:.1f} s; iteration = 4 views"),
-            "visits_per_s_fwd": float(r["visits"].sum()) / (t1 - t0)}
+    oracle.adam(th, z, z, np.zeros(th.shape[0], dtype=np.int64), g, p["keep"].any(0).astype(np.uint8))
+    t.append(time.perf_counter())
+    os.remove(so)
+    names = ["project", "bin_sort", "composite", "loss", "backward", "adam"]
+    stages = {k: round(t[i + 1] - t[i], 3) for i, k in enumerate(names)}
+    total = t[-1] - t[0]
+    visits = float(r["visits"].sum())
+    return {"value": 1.0 / total, "unit": "iters/s", "cores": used, "kind": "oracle", "cpu": cpu_model(),
+            "build": "g++ -O3 -march=native -fopenmp -ffp-contract=off (no fast-math)",
+            "sample": (f"one whole iteration: the FP64 oracle over all {th.shape[0]} Gaussians and the 4 "
+                       f"1920x1080 views of batch 0, {total:.1f} s; the backward recomputes its forward"),
+            "stage_s": stages,
+            "visits_per_s_fwd": visits / (stages["composite"] + stages["bin_sort"] + stages["project"]),
+            "gaussians_per_s_project": th.shape[0] * len(cams) / stages["project"]}
 
 
 def cpu_model():
@@ -524,6 +553,11 @@ def main():
     theta, cams = synth.aerial_workload(n_blobs=args.n_blobs, per_blob=args.per_blob)
     N = theta.shape[0]
     V = 4
+    if args.cpu_baseline_only:
+        # the oracle's time does not depend on the target's content
+        tg = np.zeros((V, 3, cams[0].height, cams[0].width))
+        print(json.dumps({"cpu_baseline": cpu_baseline(theta, cams[:V], tg, args.cpu_threads)}), flush=True)
+        return
     n_batches = len(cams) // V
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     dev = torch.device("cuda:0")
@@ -628,6 +662,8 @@ def main():
         by = algorithmic_bytes(k, pool.n_pidx, n_kept, n_vis, n_inst, n_active, pixels, V)
         kernels[k] = {"ms": round(kern_ms[k], 4),
                       "alg_GBps": round(by / (kern_ms[k] * 1e-3) / 1e9, 1) if kern_ms[k] > 0 else None}
+        if k in HBM_BOUND and kern_ms[k] > 0:
+            kernels[k]["hbm_frac"] = round(by / (kern_ms[k] * 1e-3) / 1e9 / HBM_PEAK_GBS, 3)
     fwd_tflops = fwd_visits * FLOPS_PER_FWD_VISIT / (kern_ms["render_fwd"] * 1e-3) / 1e12
     bwd_tflops = bwd_visits * FLOPS_PER_BWD_VISIT / (kern_ms["render_bwd"] * 1e-3) / 1e12
     kernels["render_fwd"]["alg_TFLOPs"] = round(fwd_tflops, 2)
@@ -636,7 +672,10 @@ def main():
         ach = fwd_tflops if dominant == "render_fwd" else bwd_tflops
         roof = {"kernel": dominant, "bound": "alu", "achieved": round(ach, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(ach / FP32_VECTOR_PEAK_TFLOPS, 4),
-                "traffic": measured_traffic(dominant)}
+                "traffic": measured_traffic(dominant),
+                "note": (f"algorithmic: {FLOPS_PER_BWD_VISIT if dominant == 'render_bwd' else FLOPS_PER_FWD_VISIT} "
+                         f"operations per visit (entries up to each pixel's last contributor for the "
+                         f"backward, entries evaluated for the forward) over the kernel's own launch time")}
     else:
         by = algorithmic_bytes(dominant, pool.n_pidx, n_kept, n_vis, n_inst, n_active, pixels, V)
         ach = by / (kern_ms[dominant] * 1e-3) / 1e9
@@ -660,7 +699,7 @@ def main():
         "kernels": kernels,
         "kernels_note": f"ms of the dominant kernel from its events in the timed region; the others from an "
                         f"untimed pass of {P} steps with every kernel's events armed",
-        "stall_s_per_iter": 0.0,
+        "stall_s_per_iter": None,
         "roofline": roof,
     }
     if args.copy_calibration:
@@ -671,8 +710,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if not args.no_cpu_baseline:
-        tg0 = targets[0][:1].double().cpu().numpy()
-        out["cpu_baseline"] = cpu_baseline(theta, cams, tg0)
+        tg0 = targets[0].double().cpu().numpy()
+        out["cpu_baseline"] = cpu_baseline(theta, cams[:V], tg0, args.cpu_threads)
     print(json.dumps(out), flush=True)
 
 

@@ -20,16 +20,23 @@ _SO = os.path.join(_HERE, "liboracle.so")
 _SOURCES = ["raster_oracle.cpp", "tier_oracle.cpp", "mlp_oracle.cpp"]
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with g++ (-O2, OpenMP, no fast-math)."""
+# IEEE double arithmetic exactly as written: no fast-math, and no fused
+# multiply-adds contracted by the compiler (so that a build for the host's
+# own instruction set gives the same bits as the portable one)
+_FLAGS = ["-std=c++17", "-fopenmp", "-fPIC", "-shared", "-fno-fast-math", "-ffp-contract=off"]
+
+
+def build(force: bool = True, so: str = _SO, native: bool = False) -> str:
+    """Compile the oracle with g++ (OpenMP).  The portable build (-O2) is the
+    one the tests load; ``native`` gives -O3 -march=native for timing it on
+    the machine that builds it."""
     srcs = [os.path.join(_HERE, s) for s in _SOURCES if os.path.exists(os.path.join(_HERE, s))]
-    if force or not os.path.exists(_SO):
-        tmp = _SO + ".tmp"
-        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-fno-fast-math",
-               "-o", tmp] + srcs
-        subprocess.check_call(cmd)
-        os.replace(tmp, _SO)
-    return _SO
+    if force or not os.path.exists(so):
+        tmp = so + ".tmp"
+        opt = ["-O3", "-march=native"] if native else ["-O2"]
+        subprocess.check_call(["g++"] + opt + _FLAGS + ["-o", tmp] + srcs)
+        os.replace(tmp, so)
+    return so
 
 
 _lib = None
@@ -45,6 +52,21 @@ def lib():
     return _lib
 
 
+def use(so: str):
+    """Load the oracle from another build of the same sources (a native
+    build for timing); later calls go to it."""
+    global _lib
+    _lib = C.CDLL(so)
+    _declare(_lib)
+    return _lib
+
+
+def set_threads(n: int) -> int:
+    """OpenMP threads of the oracle's loops (0 keeps the current count);
+    returns the count in effect."""
+    return int(lib().orc_set_threads(int(n)))
+
+
 _d = C.POINTER(C.c_double)
 _i32 = C.POINTER(C.c_int32)
 _i64 = C.POINTER(C.c_int64)
@@ -58,6 +80,8 @@ def _declare(L):
     L.orc_sh_basis_grad.argtypes = [_d, _d]
     L.orc_project.argtypes = [_d, C.c_int64, _d, C.c_int, _d, _i32, _d]
     L.orc_tile_rect.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int, C.c_int, _i32]
+    L.orc_set_threads.argtypes = [C.c_int]
+    L.orc_set_threads.restype = C.c_int
     L.orc_tile_rects.argtypes = [_d, _d, _i32, C.c_int64, C.c_int, C.c_int, _i32]
     L.orc_bin.argtypes = [_d, _d, _d, _i32, _i32, C.c_int64, _d, C.c_int, _i64, C.c_int64, _i64]
     L.orc_bin.restype = C.c_int64

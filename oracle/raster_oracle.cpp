@@ -32,6 +32,8 @@
 // All loops are plain: projection per (camera, Gaussian), binning by direct
 // enumeration of every tile against the coverage rule, std::stable_sort,
 // per-pixel compositing, direct 11x11 convolution.
+#include <omp.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -462,6 +464,13 @@ void orc_tile_rect(double u, double v, int r, int Tx, int Ty, int32_t* rect) {
   int q[4];
   tile_rect(u, v, r, Tx, Ty, q);
   for (int k = 0; k < 4; ++k) rect[k] = q[k];
+}
+
+// Threads the OpenMP loops of the oracle use (timing runs only; results do
+// not depend on it).  Returns the count in effect.
+int orc_set_threads(int n) {
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
 }
 
 // O4's tile rectangle for n (u, v, r) triples on one camera's Tx x Ty grid

@@ -76,3 +76,13 @@ def test_algorithmic_bytes_per_unit():
 
 def test_cpu_model_names_the_sockets():
     assert "socket" in bench.cpu_model()
+
+
+def test_compositing_work_per_visit_is_the_stated_model():
+    """The ALU roofline counts the method's per-visit formulas: about 20
+    operations and one exponential per forward visit, about 50 and two
+    transcendentals per backward visit."""
+    assert bench.FLOPS_PER_FWD_VISIT == 21
+    assert bench.FLOPS_PER_BWD_VISIT == 52
+    assert set(bench.HBM_BOUND) <= set(bench.KERNELS)
+    assert "render_bwd" not in bench.HBM_BOUND and "render_fwd" not in bench.HBM_BOUND
