@@ -4,8 +4,9 @@ Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
 import this package.  The product library never loads it and shares no code
 with it.  This module is ctypes glue: it marshals numpy arrays into the C++
 oracle (``raster_oracle.cpp``, ``tier_oracle.cpp``, ``mlp_oracle.cpp``) and
-holds none of the arithmetic itself.  ``ordering.py`` is the one oracle
-written in Python: the training-view order.
+holds none of the arithmetic itself.  ``ordering.py`` (the training-view
+order) and ``logstore.py`` (the log-structured block store and a reader of
+its persisted Index) are the oracles written in Python.
 """
 from __future__ import annotations
 
