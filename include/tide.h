@@ -144,7 +144,10 @@ tide_status tide_preprocess(const tide_pool* pool, const tide_camera* cams, int3
                             tide_proj* out, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
- * Tile binning and depth sort.  Every kept (camera, Gaussian) pair is
+ * Tile binning and depth sort, the tile stage of the standard 3DGS
+ * rasterization pipeline that the paper runs unchanged on the resident
+ * visible blocks (Sec. 3.3, Level 2; Sec. 3.2, Stage 3).  Every kept
+ * (camera, Gaussian) pair is
  * duplicated once per covered tile and the instances are ordered by
  * (camera, tile, depth, pidx): first the visible pairs are sorted stably by
  * depth (LSD radix, 8-bit digits), then the instances, emitted in that depth
@@ -227,7 +230,10 @@ tide_status tide_loss(const void* image, const void* target, int32_t n_views, in
                       size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
- * Backward of the rasterizer: the compositing adjoint per tile (reverse walk
+ * Backward of the rasterizer, the standard 3DGS backward that the paper runs
+ * on the resident blocks (Sec. 3.2, Stage 3; Sec. 3.3, Level 2: only the
+ * contributing set I_t receives non-zero gradients, so the gradient is kept
+ * compact over the active rows): the compositing adjoint per tile (reverse walk
  * from each pixel's last contributor), a fixed-order sum of per-instance
  * 2-D gradients per (camera, Gaussian), then the adjoint of projection,
  * EWA, activations and SH, summed over cameras in order.  Deterministic:
