@@ -143,6 +143,25 @@ size_t tide_preprocess_ws_bytes(int64_t n_pidx);
 tide_status tide_preprocess(const tide_pool* pool, const tide_camera* cams, int32_t n_cams,
                             tide_proj* out, void* ws, size_t ws_bytes, void* stream);
 
+/* Allocation-free variant of tide_preprocess, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, checks and results as
+ * tide_preprocess, without the workspace: the active scan's scratch (its
+ * per-4096-pidx block sums and total) is a static device array of
+ * TIDE_PREPROCESS_NOALLOC_SCRATCH bytes, one per GPU, whose address is looked
+ * up on the first call on each device (hipGetSymbolAddress) and which is held
+ * until the process ends.  The call allocates nothing, host or device.
+ *   n_pidx above TIDE_PREPROCESS_NOALLOC_MAX_PIDX -> TIDE_ECAPACITY, before
+ *   any device work (use tide_preprocess with a workspace instead).
+ * Every call on a GPU shares that GPU's scratch and leaves its contents there;
+ * nothing in it needs to start at zero (each call writes what it reads).
+ * Calls that overlap on one GPU (two streams, two host threads) race on it:
+ * the caller serialises them. */
+#define TIDE_PREPROCESS_NOALLOC_SCRATCH 262144
+#define TIDE_PREPROCESS_NOALLOC_MAX_PIDX 134086656 /* 32736 scan blocks of 4096 */
+tide_status tide_preprocess_noalloc(const tide_pool* pool, const tide_camera* cams, int32_t n_cams,
+                                    tide_proj* out, void* stream);
+
 /* ------------------------------------------------------------------------
  * Tile binning and depth sort, the tile stage of the standard 3DGS
  * rasterization pipeline that the paper runs unchanged on the resident

@@ -22,6 +22,8 @@ TIDE_F32 = 0
 TIDE_F64 = 1
 TIDE_D = 59
 TIDE_MAX_CAMS = 8
+TIDE_PREPROCESS_NOALLOC_SCRATCH = 262144
+TIDE_PREPROCESS_NOALLOC_MAX_PIDX = 134086656
 
 
 class TideError(RuntimeError):
@@ -111,6 +113,7 @@ SIGNATURES = {
     "tide_abi_version": (C.c_int32, []),
     "tide_preprocess_ws_bytes": (C.c_size_t, [C.c_int64]),
     "tide_preprocess": (C.c_int32, [_P(tide_pool), _P(tide_camera), C.c_int32, _P(tide_proj), _vp, C.c_size_t, _vp]),
+    "tide_preprocess_noalloc": (C.c_int32, [_P(tide_pool), _P(tide_camera), C.c_int32, _P(tide_proj), _vp]),
     "tide_bin_sort_ws_bytes": (C.c_size_t, [C.c_int32, C.c_int64, C.c_int32, C.c_int32, C.c_int64]),
     "tide_bin_sort": (C.c_int32, [_P(tide_proj), C.c_int32, C.c_int32, _vp, C.c_size_t, _P(tide_bins), _vp]),
     "tide_render_fwd": (C.c_int32, [_P(tide_proj), _P(tide_bins), _P(C.c_float), _P(tide_frame), _vp]),

@@ -554,6 +554,34 @@ __global__ void __launch_bounds__(256) k_sum_visits(const unsigned long long* __
 
 using namespace tide;
 
+// ------------------------------------------------- preprocess without allocation
+// Device scratch of tide_preprocess_noalloc: the active scan's per-block sums
+// (one u64 per 4096 pidx) and its total.  One copy per GPU, held until the
+// process ends; host code reaches it only through the address that
+// hipGetSymbolAddress returns on that device (kept in g_noalloc_ptr).
+constexpr size_t kNoallocScratchBytes = 256 * 1024;
+static_assert(kNoallocScratchBytes == (size_t)TIDE_PREPROCESS_NOALLOC_SCRATCH, "header and scratch size differ");
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+static std::mutex g_noalloc_mu;
+static void* g_noalloc_ptr[64];
+
+// Address of the current device's scratch, looked up once per device.
+static tide_status noalloc_scratch(void** out) {
+  int dev = 0;
+  TIDE_HIP(hipGetDevice(&dev));
+  TIDE_CHECK_ARG(dev >= 0 && dev < 64, "device ordinal %d beyond the 64 this library tracks", dev);
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    TIDE_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    TIDE_CHECK_ARG(p != nullptr, "hipGetSymbolAddress gave a null scratch address");
+    g_noalloc_ptr[dev] = p;
+  }
+  *out = g_noalloc_ptr[dev];
+  return TIDE_OK;
+}
+
 extern "C" size_t tide_preprocess_ws_bytes(int64_t n_pidx) { return preprocess_ws_bytes(n_pidx); }
 
 extern "C" tide_status tide_preprocess(const tide_pool* pool, const tide_camera* cams, int32_t n_cams,
@@ -567,6 +595,33 @@ extern "C" tide_status tide_preprocess(const tide_pool* pool, const tide_camera*
   TIDE_CHECK_ARG(out->n_pidx == (int64_t)pool->n_order * pool->block_rows, "proj.n_pidx must be n_order * block_rows");
   TIDE_CHECK_ARG(ws && ws_bytes >= preprocess_ws_bytes(out->n_pidx), "workspace too small (%zu < %zu)", ws_bytes,
                  preprocess_ws_bytes(out->n_pidx));
+  hipStream_t st = (hipStream_t)stream;
+  return pool->dtype == TIDE_F32 ? preprocess_t<float>(pool, cams, n_cams, out, ws, st)
+                                 : preprocess_t<double>(pool, cams, n_cams, out, ws, st);
+}
+
+extern "C" tide_status tide_preprocess_noalloc(const tide_pool* pool, const tide_camera* cams, int32_t n_cams,
+                                               tide_proj* out, void* stream) {
+  tide_status s;
+  if ((s = check_pool(pool)) != TIDE_OK) return s;
+  if ((s = check_cams(cams, n_cams)) != TIDE_OK) return s;
+  if ((s = check_proj(out)) != TIDE_OK) return s;
+  TIDE_CHECK_ARG(out->n_cams == n_cams, "proj.n_cams (%d) != n_cams (%d)", out->n_cams, n_cams);
+  TIDE_CHECK_ARG(out->dtype == pool->dtype, "proj and pool dtypes differ");
+  TIDE_CHECK_ARG(out->n_pidx == (int64_t)pool->n_order * pool->block_rows, "proj.n_pidx must be n_order * block_rows");
+  if (out->n_pidx > (int64_t)TIDE_PREPROCESS_NOALLOC_MAX_PIDX) {
+    set_error("tide_preprocess_noalloc: n_pidx %lld exceeds the maximum %lld of its %zu-byte static scratch "
+              "(use tide_preprocess with a workspace)",
+              (long long)out->n_pidx, (long long)TIDE_PREPROCESS_NOALLOC_MAX_PIDX, kNoallocScratchBytes);
+    return TIDE_ECAPACITY;
+  }
+  if (preprocess_ws_bytes(out->n_pidx) > kNoallocScratchBytes) {  // guards the constant above
+    set_error("tide_preprocess_noalloc: scratch of %zu bytes is short of %zu", kNoallocScratchBytes,
+              preprocess_ws_bytes(out->n_pidx));
+    return TIDE_ECAPACITY;
+  }
+  void* ws = nullptr;
+  if ((s = noalloc_scratch(&ws)) != TIDE_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   return pool->dtype == TIDE_F32 ? preprocess_t<float>(pool, cams, n_cams, out, ws, st)
                                  : preprocess_t<double>(pool, cams, n_cams, out, ws, st);

@@ -53,3 +53,25 @@ def test_null_arguments_rejected_before_launch():
     assert lib.tide_loss(None, None, 1, 8, 8, 0, None, None, None, 0, None) == L.TIDE_EINVAL
     cfg = L.tide_adam_cfg()
     assert lib.tide_adam_sparse(None, None, None, 0, C.byref(cfg), None, None, 0, None, 0, None) == L.TIDE_EINVAL
+
+
+def test_noalloc_preprocess_rejects_a_size_beyond_its_scratch_on_the_host():
+    """tide_preprocess_noalloc refuses n_pidx above its static scratch before
+    any device call (host buffers stand in for the device pointers, which
+    the size check never touches)."""
+    lib = L.load()
+    host = (C.c_double * 64)()
+    p = C.cast(host, C.c_void_p).value
+    pool = L.tide_pool()
+    pool.params = pool.exp_avg = pool.exp_avg_sq = pool.step = p
+    pool.slot_block = pool.slot_rows = pool.order = p
+    pool.block_rows, pool.n_order, pool.n_slots, pool.dtype = 65536, 2047, 2047, L.TIDE_F32
+    proj = L.tide_proj()
+    proj.rec = proj.depth = proj.rect = proj.tiles_touched = proj.active = proj.act_idx = proj.n_active = p
+    proj.n_pidx, proj.n_cams, proj.dtype = 65536 * 2047, 1, L.TIDE_F32
+    assert proj.n_pidx > L.TIDE_PREPROCESS_NOALLOC_MAX_PIDX
+    cam = L.camera_array([type("Cam", (), dict(R=[1, 0, 0, 0, 1, 0, 0, 0, 1], t=[0, 0, 3], fx=64, fy=64, cx=32,
+                                                cy=32, width=64, height=64, z_near=0.2, z_far=1e4))()])
+    assert lib.tide_preprocess_noalloc(C.byref(pool), cam, 1, C.byref(proj), None) == L.TIDE_ECAPACITY
+    assert b"exceeds the maximum" in lib.tide_last_error()
+    assert lib.tide_preprocess_noalloc(None, cam, 1, C.byref(proj), None) == L.TIDE_EINVAL
