@@ -207,6 +207,26 @@ double rect_margin(double u, double v, int r) {
   return std::min(std::min(dm(u + r), dm(u - r)), std::min(dm(v + r), dm(v - r)));
 }
 
+// Whether p_z = R_20 mu_0 + R_21 mu_1 + R_22 mu_2 + t_2, evaluated left to
+// right in double precision, is exact: every product and every partial sum
+// carries no rounding error (error-free transformations: the product's error
+// is fma(a, b, -ab), the sum's that of Knuth's two-sum).  An exact p_z is the
+// same whatever evaluation order or fused multiply-adds another double
+// evaluation uses, so its depth decisions carry no uncertainty.
+bool depth_exact(const Cam& c, const double* mu) {
+  double s = 0;
+  for (int k = 0; k < 3; ++k) {
+    const double a = c.R[6 + k], b = mu[k];
+    const double p = a * b;
+    if (std::fma(a, b, -p) != 0) return false;
+    const double t = s + p, bp = t - s;
+    if ((s - (t - bp)) + (p - bp) != 0) return false;
+    s = t;
+  }
+  const double t = s + c.t[2], bp = t - s;
+  return (s - (t - bp)) + (c.t[2] - bp) == 0;
+}
+
 void project_one(const double* th, const Cam& c, Fwd& f) {
   const double* mu = th;
   f.keep = false;
@@ -224,9 +244,11 @@ void project_one(const double* th, const Cam& c, Fwd& f) {
   // midpoint of single precision that another evaluation order of p_z
   // rounds it the other way.
   f.derr = 0;
-  f.margin = std::min(f.margin, key_midpoint_distance(pz) / nf_err);
-  f.margin = std::min(f.margin, std::fabs(pz - c.znear) / nf_err);
-  f.margin = std::min(f.margin, std::fabs(pz - c.zfar) / nf_err);
+  if (!depth_exact(c, mu)) {
+    f.margin = std::min(f.margin, key_midpoint_distance(pz) / nf_err);
+    f.margin = std::min(f.margin, std::fabs(pz - c.znear) / nf_err);
+    f.margin = std::min(f.margin, std::fabs(pz - c.zfar) / nf_err);
+  }
   if (!(pz > c.znear) || pz > c.zfar) return;
 
   // activations
@@ -368,7 +390,12 @@ void composite_tile(const Cam& c, int tx, int ty, const int64_t* list, int64_t l
         const double a_raw = g.op * std::exp(power);
         const double alpha = std::min(0.99, a_raw);
         const double gx = g.A * dx + g.B * dy, gy = g.B * dx + g.C * dy;
-        const double epow = std::sqrt(gx * gx + gy * gy) * g.perr + kTieRel * (std::fabs(power) + 1.0);
+        // single-precision rounding acts on the three terms of the quadratic
+        // form, which can be far larger than their sum (an elongated
+        // footprint away from its centre), so the bound is relative to
+        // their magnitudes, not to the power
+        const double terms = 0.5 * (g.A * dx * dx + g.C * dy * dy) + std::fabs(g.B * dx * dy);
+        const double epow = std::sqrt(gx * gx + gy * gy) * g.perr + kTieRel * (terms + 1.0);
         mg = std::min(mg, std::fabs(power + std::log(255.0 * g.op)) / epow);
         if (alpha < 1.0 / 255.0) continue;
         const double ea = (a_raw < 0.99 ? alpha / (1 - alpha) * epow : 0.0) + kTieRel;

@@ -361,6 +361,9 @@ def bins_views(rast: Rasterizer, bins: L.tide_bins) -> dict:
         return ws[off: off + 4 * count].view(torch.int32)
 
     V, T = bins.n_cams, bins.tiles_x * bins.tiles_y
+    tv_off = int(bins.tile_visits) - base
+    assert tv_off % 8 == 0 and 0 <= tv_off and tv_off + 16 * V * T <= ws.numel()
     return dict(vis_rec=view(bins.vis_rec, bins.n_vis), inst_off=view(bins.inst_off, bins.n_vis + 1),
                 inst_e=view(bins.inst_e, bins.n_inst), inst_rec=view(bins.inst_rec, bins.n_inst),
-                ranges=view(bins.ranges, 2 * V * T).view(V * T, 2), tile_order=view(bins.tile_order, V * T))
+                ranges=view(bins.ranges, 2 * V * T).view(V * T, 2), tile_order=view(bins.tile_order, V * T),
+                tile_visits=ws[tv_off: tv_off + 16 * V * T].view(torch.int64).view(2, V * T)[0])

@@ -1,9 +1,17 @@
 """GPU parity of the rasterizer hot path against the FP64 oracle (MI355X).
 
 Tolerances: image max-abs <= 1e-4 and gradient error <= 1e-3 per attribute
-group (relative L2, plus an elementwise bound), outside near-tie decisions
-(relative decision margin < 2^-20, counted and reported); tile lists and
-sort order bit-exact on identical FP32 inputs.
+group (relative L2, plus an elementwise bound), outside near-tie decisions,
+counted, reported and capped at 1 % of the pixels or rows compared; tile
+rectangles, tile lists, sort order and ranges bit-exact on the GPU's own FP32
+projection; the oracle's compositing of the GPU's own records within 1e-5.
+
+Near ties.  The oracle divides every jump decision's margin by a first-order
+bound of the single-precision error of its inputs, in units of 16 ulps; a
+ratio below NEAR_TIE marks the decision (and its pixel or row) a near tie.
+NEAR_TIE = 1/16 (one ulp): over the benchmark's 1920x1080 aerial frame every
+pixel whose end-to-end error exceeds 1e-4 has a ratio below 0.016, and no
+pixel at or above 1/16 exceeds 2.5e-5.
 """
 import math
 import sys
@@ -17,7 +25,8 @@ from paper_2605_20150_amd import synth
 from paper_2605_20150_amd.raster import (LR59, Pool, Rasterizer, adam_cfg, bins_views, dense_grad, render)
 
 pytestmark = pytest.mark.gpu
-NEAR_TIE = 1.0   # decision margin below its first-order FP32 uncertainty
+NEAR_TIE = 1.0 / 16   # decision margin below one ulp of its inputs' single-precision error
+TIE_CEILING = 0.01    # the largest fraction of pixels or rows a near-tie exclusion may remove
 GROUPS = {"mean": slice(0, 3), "scale": slice(3, 6), "rot": slice(6, 10), "opacity": slice(10, 11),
           "sh_dc": slice(11, 14), "sh_rest": slice(14, 59)}
 
@@ -48,6 +57,111 @@ def gpu_records(proj, V, N):
 
 def near_tie_pixels(ref):
     return ref["pix_margin"] < NEAR_TIE
+
+
+def excluded(mask, what):
+    """Reports an exclusion and holds it under the ceiling."""
+    frac = float(np.mean(mask)) if mask.size else 0.0
+    say(f"near-tie {what}: {int(np.sum(mask))} of {mask.size} ({100 * frac:.3f} %)")
+    assert frac <= TIE_CEILING, f"{100 * frac:.2f} % of {what} excluded"
+    return mask
+
+
+def oracle_lists(th, cams):
+    """The oracle's own tile lists (gids) and ranges, from its FP64
+    projection with single-precision depth keys, as its renderer builds them."""
+    cm = synth.cams_array(cams)
+    p = oracle.project(th.astype(np.float64), cm)
+    key = p["depth"].astype(np.float32).astype(np.float64)
+    return oracle.bin_sort(p["u"], p["v"], key, p["radius"], p["keep"], cm)
+
+
+def gpu_lists(rast, bins, n_pidx):
+    """The GPU's tile lists (pidx, the global id in an all-resident pool),
+    ranges and per-tile forward visit counts."""
+    b = bins_views(rast, bins)
+    inst_rec = b["inst_rec"].cpu().numpy().astype(np.int64)
+    inst_e = b["inst_e"].cpu().numpy().astype(np.int64)
+    lst = inst_rec[inst_e] % n_pidx
+    return lst, b["ranges"].cpu().numpy().astype(np.int64), b["tile_visits"].cpu().numpy()
+
+
+def contributor(last, lst, ranges, W, H):
+    """Per pixel, the id of its last contributing entry (-1 if none): a
+    list position mapped through the pixel's tile list, so that lists which
+    differ by a near-tie entry elsewhere compare equal."""
+    V = last.shape[0]
+    Tx, Ty = (W + 15) // 16, (H + 15) // 16
+    ys, xs = np.mgrid[0:H, 0:W]
+    tile = (ys // 16) * Tx + xs // 16
+    out = np.full(last.shape, -1, dtype=np.int64)
+    for c in range(V):
+        start = ranges[c * Tx * Ty + tile, 0]
+        has = last[c] > 0
+        out[c][has] = lst[start[has] + last[c][has].astype(np.int64) - 1]
+    return out
+
+
+def gpu_rects(proj, V, N):
+    """The GPU's tile rectangles [V, N, 4] (x0, y0, x1, y1; zeros where culled)."""
+    r = proj.rect.view(V, -1, 2)[:, :N].cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    tt = proj.tiles_touched.view(V, -1)[:, :N].cpu().numpy()
+    out = np.stack([r[..., 0] & 0xFFFF, r[..., 0] >> 16, r[..., 1] & 0xFFFF, r[..., 1] >> 16], axis=-1)
+    out[tt == 0] = 0
+    return out
+
+
+def normalised_ranges(rng):
+    """Tile ranges with every empty tile as [0, 0) (the library leaves an
+    empty tile's range at zero, the oracle at the running offset)."""
+    r = rng.copy()
+    r[r[:, 1] == r[:, 0]] = 0
+    return r
+
+
+def lists_equal_per_tile(glst, grng, olst, orng):
+    """[tiles] True where the GPU's and the oracle's tile lists are equal."""
+    gl, ol = grng[:, 1] - grng[:, 0], orng[:, 1] - orng[:, 0]
+    eq = gl == ol
+    for t in np.nonzero(eq & (gl > 0))[0]:
+        eq[t] = np.array_equal(glst[grng[t, 0]:grng[t, 1]], olst[orng[t, 0]:orng[t, 1]])
+    return eq
+
+
+def check_visits_and_contributors(rast, proj, bins, fr, th, cams, ref, tie_px):
+    """End to end: each pixel's last contributor equals the oracle's outside
+    near-tie pixels, and the per-tile forward visit counts are equal on every
+    tile whose list equals the oracle's and holds no near-tie pixel.  (A
+    near-tie pair decision, a rectangle edge or a cull, can put an entry in
+    one side's list only; such tiles are counted, capped at 5 %, and left
+    out of the visit comparison.)"""
+    W, H = cams[0].width, cams[0].height
+    olst, orng = oracle_lists(th, cams)
+    glst, grng, gvis = gpu_lists(rast, bins, proj.n_pidx)
+    same = lists_equal_per_tile(glst, grng, olst, orng)
+    diff = ~same
+    frac = float(diff.mean())
+    say(f"tiles whose list differs from the oracle's: {int(diff.sum())} of {diff.size} ({100 * frac:.3f} %)")
+    assert frac <= 0.05
+    cmp = same & ~(tile_sums(tie_px.astype(np.int64), W, H) > 0)
+    ovis = tile_sums(ref["visits"], W, H)
+    assert np.array_equal(gvis[cmp], ovis[cmp]), f"{int((gvis != ovis)[cmp].sum())} tiles with different visit counts"
+    say(f"visits: {int(gvis.sum())} GPU, {int(ovis.sum())} oracle; equal on the {int(cmp.sum())} tiles compared")
+    gc = contributor(fr.last.cpu().numpy(), glst, grng, W, H)
+    oc = contributor(ref["last"], olst, orng, W, H)
+    assert np.array_equal(gc[~tie_px], oc[~tie_px]), f"{int((gc != oc)[~tie_px].sum())} pixels"
+    if same.all():
+        assert np.array_equal(normalised_ranges(grng), normalised_ranges(orng))
+        assert np.array_equal(fr.last.cpu().numpy()[~tie_px], ref["last"][~tie_px])
+
+
+def tile_sums(per_pixel, W, H):
+    """[V, H, W] -> [V * tiles] sums over each 16x16 tile (row-major tiles)."""
+    V = per_pixel.shape[0]
+    Tx, Ty = (W + 15) // 16, (H + 15) // 16
+    pad = np.zeros((V, Ty * 16, Tx * 16), dtype=per_pixel.dtype)
+    pad[:, :H, :W] = per_pixel
+    return pad.reshape(V, Ty, 16, Tx, 16).sum(axis=(2, 4)).reshape(-1)
 
 
 def dense_case():
@@ -82,16 +196,16 @@ def test_tiny_scene_image_matches_oracle():
     theta, cams, _ = synth.tiny_workload()
     cm = synth.cams_array(cams)
     ref = oracle.render(theta.astype(np.float64), cm)
-    _, _, proj, bins, fr = gpu_forward(theta, cams)
+    rast, _, proj, bins, fr = gpu_forward(theta, cams)
     img = fr.image.double().cpu().numpy()
-    tie = near_tie_pixels(ref)
-    say(f"near-tie pixels: {int(tie.sum())}")
+    tie = excluded(near_tie_pixels(ref), "pixels")
     err = np.abs(img - ref["image"]).max(axis=1)[~tie].max()
     say(f"image max-abs error {err:.3e}")
     assert err <= 1e-4
+    check_visits_and_contributors(rast, proj, bins, fr, theta, cams, ref, tie)
+    if not tie.any():
+        assert int(fr.visits_fwd.sum()) == int(ref["visits"].sum())
     last = fr.last.cpu().numpy()
-    assert np.array_equal(last[~tie], ref["last"][~tie])
-    assert int(fr.visits_fwd.sum()) == int(ref["visits"].sum()) or tie.any()
     # the backward walks every entry up to each pixel's last contributor
     assert np.array_equal(fr.visits_bwd.cpu().numpy(), last.reshape(last.shape[0], -1).sum(1))
     assert np.abs(fr.t_final.double().cpu().numpy() - ref["t_final"])[~tie].max() <= 1e-5
@@ -136,6 +250,59 @@ def oracle_inputs_into(rast, proj, th, cams):
     torch.cuda.synchronize()
     r64 = rec[:, :N].astype(np.float64)
     return r64, radius, keep, bins, fr
+
+
+def stage_isolated_on_the_gpu_projection(rast, proj, bins, fr, cams, views):
+    """The oracle's O4 and O6 on the GPU's own FP32 (u, v), integer radius and
+    FP32 depth: rectangles, tile counts, lists and ranges bit-identical with
+    no exclusions; then the oracle's O7 (FP64) on the GPU's own records over
+    those lists: image and T_final within 1e-5, last and per-tile visit
+    counts equal, outside the pixels with a near-tie decision."""
+    V, N = proj.n_cams, proj.n_pidx
+    W, H = cams[0].width, cams[0].height
+    Tx, Ty = bins.tiles_x, bins.tiles_y
+    T = Tx * Ty
+    rec = proj.rec.view(V, N, 12).cpu().numpy().astype(np.float64)
+    dep = proj.depth.view(V, N).cpu().numpy().astype(np.float64)
+    tt = proj.tiles_touched.view(V, N).cpu().numpy().astype(np.int64)
+    keep = tt > 0
+    rad = rec[..., 10].astype(np.int32)
+    grect = gpu_rects(proj, V, N)
+    orect = oracle.tile_rects(rec[..., 0][keep], rec[..., 1][keep], rad[keep], Tx, Ty)
+    assert np.array_equal(orect, grect[keep]), f"{int((orect != grect[keep]).any(1).sum())} rectangles differ"
+    assert np.array_equal((orect[:, 2] - orect[:, 0]) * (orect[:, 3] - orect[:, 1]), tt[keep])
+    say(f"rectangles and tile counts of {int(keep.sum())} kept pairs identical")
+    glst, grng, gvis = gpu_lists(rast, bins, N)
+    cm = synth.cams_array(cams)
+    img = fr.image.double().cpu().numpy()
+    tf = fr.t_final.double().cpu().numpy()
+    last = fr.last.cpu().numpy()
+    for c in views:
+        sl = slice(c, c + 1)
+        gid, orng = oracle.bin_sort(rec[sl, :, 0], rec[sl, :, 1], dep[sl], rad[sl], keep[sl], cm[sl])
+        s0 = int((grng[:c * T, 1] - grng[:c * T, 0]).sum())      # instances of the earlier views
+        assert np.array_equal(normalised_ranges(orng + s0), normalised_ranges(grng[c * T:(c + 1) * T])), \
+            f"view {c}: ranges differ"
+        assert np.array_equal(gid, glst[s0:s0 + len(gid)]), f"view {c}: lists differ"
+        orng = orng + s0
+        iso = oracle.composite(glst, orng, rec[sl, :, :9], cm[sl])
+        tie = excluded(iso["pix_margin"][0] < NEAR_TIE, f"pixels of view {c} (stage-isolated)")
+        err = np.abs(img[c] - iso["image"][0]).max(axis=0)
+        say(f"view {c}: {len(gid)} instances, lists identical; compositing error {err[~tie].max():.3e} "
+            f"(all pixels {err.max():.3e})")
+        assert err[~tie].max() <= 1e-5
+        assert np.abs(tf[c] - iso["t_final"][0])[~tie].max() <= 1e-5
+        assert np.array_equal(last[c][~tie], iso["last"][0][~tie])
+        tie_t = tile_sums(tie[None].astype(np.int64), W, H) > 0
+        ov = tile_sums(iso["visits"], W, H)
+        assert np.array_equal(gvis[c * T:(c + 1) * T][~tie_t], ov[~tie_t])
+
+
+def test_binning_and_compositing_on_the_gpu_projection():
+    say("case: dense scene, 3 cameras 150x110 (ragged tiles), block 1024; the GPU's own projection")
+    th, cams = dense_case()
+    rast, pool, proj, bins, fr = gpu_forward(th, cams, block_rows=1024)
+    stage_isolated_on_the_gpu_projection(rast, proj, bins, fr, cams, range(3))
 
 
 def test_binning_is_bit_exact_on_oracle_inputs():
@@ -235,7 +402,7 @@ def test_compositing_matches_oracle_on_oracle_records():
     cm = synth.cams_array(cams)
     gid, ranges = oracle.bin_sort(rec[..., 0], rec[..., 1], rec[..., 9], radius, keep, cm)
     ref = oracle.composite(gid, ranges, rec[..., :9], cm)
-    tie = near_tie_pixels(ref)
+    tie = excluded(near_tie_pixels(ref), "pixels")
     img = fr.image.double().cpu().numpy()
     err = np.abs(img - ref["image"]).max(axis=1)[~tie].max()
     say(f"near-tie pixels {int(tie.sum())}, image max-abs error {err:.3e}")
@@ -249,12 +416,13 @@ def test_dense_scene_end_to_end_matches_oracle():
     th, cams = dense_case()
     cm = synth.cams_array(cams)
     ref = oracle.render(th.astype(np.float64), cm)
-    _, _, proj, bins, fr = gpu_forward(th, cams, block_rows=1024)
-    tie = near_tie_pixels(ref)
+    rast, _, proj, bins, fr = gpu_forward(th, cams, block_rows=1024)
+    tie = excluded(near_tie_pixels(ref), "pixels")
     img = fr.image.double().cpu().numpy()
     err = np.abs(img - ref["image"]).max(axis=1)[~tie]
-    say(f"near-tie pixels {int(tie.sum())} of {tie.size}; image max-abs error {err.max():.3e}")
+    say(f"image max-abs error {err.max():.3e}")
     assert err.max() <= 1e-4
+    check_visits_and_contributors(rast, proj, bins, fr, th, cams, ref, tie)
 
 
 def long_list_case():
@@ -282,18 +450,18 @@ def test_lists_longer_than_two_to_the_sixteen():
     lens = (b["ranges"][:, 1] - b["ranges"][:, 0]).cpu().numpy()
     say(f"list lengths {int(lens.min())}..{int(lens.max())}, last up to {int(fr.last.max())}")
     assert lens.min() > 65536
+    # pixels walk thousands of entries near the 1/255 floor, so a few percent
+    # of them hold a near-tie decision; none is excluded here
     tie = near_tie_pixels(ref)
     err = np.abs(fr.image.double().cpu().numpy() - ref["image"]).max(axis=1)
-    say(f"near-tie pixels {int(tie.sum())} of {tie.size}; image max-abs error {err[~tie].max():.3e}")
-    assert err[~tie].max() <= 1e-4
+    say(f"near-tie pixels {int(tie.sum())} of {tie.size} (not excluded); image max-abs error {err.max():.3e}")
+    assert err.max() <= 1e-4
     assert int(fr.visits_bwd.sum()) == int(fr.last.sum(dtype=torch.int64))
     W = np.random.Generator(np.random.PCG64(33)).normal(size=ref["image"].shape)
     g_ref = oracle.backward(th64, cm, W)
     g = rast.backward(pool, cams, proj, bins, fr, torch.tensor(W, dtype=torch.float32, device="cuda"))
     gd = dense_grad(proj, g, th.shape[0]).double().cpu().numpy()
-    tie_rows = (ref["pair_margin"] < NEAR_TIE).any(axis=0)
-    say(f"near-tie rows {int(tie_rows.sum())} of {th.shape[0]}")
-    assert (~tie_rows).sum() > 0.5 * th.shape[0]
+    tie_rows = excluded((ref["pair_margin"] < NEAR_TIE).any(axis=0), "rows")
     assert_grad_close(gd[~tie_rows], g_ref[~tie_rows])
 
 
@@ -391,8 +559,7 @@ def test_dense_scene_gradient_matches_oracle():
     g = rast.backward(pool, cams, proj, bins, fr, torch.tensor(dimg, dtype=torch.float32, device="cuda"))
     gd = dense_grad(proj, g, th.shape[0]).double().cpu().numpy()
     # rows whose pairs or pixels sit at a near-tie decision are excluded
-    tie_rows = (ref["pair_margin"] < NEAR_TIE).any(axis=0)
-    say(f"near-tie rows {int(tie_rows.sum())}")
+    tie_rows = excluded((ref["pair_margin"] < NEAR_TIE).any(axis=0), "rows")
     assert_grad_close(gd[~tie_rows], g_ref[~tie_rows])
 
 
@@ -464,36 +631,25 @@ def test_sparse_adam_matches_oracle_and_leaves_inactive_rows():
     N = th.shape[0]
     rng = np.random.default_rng(8)
     cfg = adam_cfg(LR59)
-    ref_p, ref_m, ref_v = th.astype(np.float64), np.zeros((N, 59)), np.zeros((N, 59))
-    ref_s = np.zeros(N, dtype=np.int64)
     act = proj.active[:N].cpu().numpy().astype(bool)
     assert act.sum() < N
     nblk = pool.n_slots
     spheres = torch.zeros((nblk, 4), dtype=torch.float32, device="cuda")
     dirty = torch.zeros((nblk,), dtype=torch.uint8, device="cuda")
-    before = pool.params.clone()
+    grads = []
     for it in range(2):
-        gd = rng.normal(size=(N, 59)) * 1e-3
-        g = torch.zeros((59, pool.n_pidx), dtype=torch.float32, device="cuda")
+        gd = (rng.normal(size=(N, 59)) * 1e-3).astype(np.float32)
+        gd[~act] = 0
         idx = proj.act_idx[:N].cpu().numpy()
         gc = np.zeros((59, pool.n_pidx), dtype=np.float32)
         gc[:, idx[act]] = gd[act].T
-        g.copy_(torch.tensor(gc))
-        rast.adam(pool, proj, g, cfg, spheres, dirty)
-        ref_p, ref_m, ref_v, ref_s = oracle.adam(ref_p, ref_m, ref_v, ref_s, gd.astype(np.float32).astype(np.float64),
-                                                 act.astype(np.uint8))
+        rast.adam(pool, proj, torch.tensor(gc, device="cuda"), cfg, spheres, dirty)
+        grads.append(gd.astype(np.float64))
     torch.cuda.synchronize()
-    p = pool.dense(N).double().cpu().numpy()
-    dp_ref = ref_p - th.astype(np.float64)
-    dp = p - th.astype(np.float64)
-    lr = np.array(LR59)
-    assert (np.abs(dp - dp_ref) <= 1e-3 * np.abs(dp_ref) + 1e-3 * lr + 1e-6).all()
-    assert torch.equal(pool.dense(N)[~torch.tensor(act, device="cuda")],
-                       Pool.from_dense(torch.tensor(th, device="cuda"), 256).dense(N)[~torch.tensor(act, device="cuda")])
-    st = pool.step.view(-1)[:N].cpu().numpy()
-    assert np.array_equal(st, ref_s)
+    check_adam(pool, grads, act, th.astype(np.float64), LR59)
     assert dirty.cpu().numpy().tolist() == [1] * nblk
     # sphere radius covers every updated row: |mu - c| + 3 kappa max(scale)
+    p = pool.dense(N).double().cpu().numpy()
     mu = p[:, :3]
     reach = np.linalg.norm(mu, axis=1) + 3 * 1.32 * np.exp(p[:, 3:6].max(1))
     sr = spheres.cpu().numpy()
@@ -501,27 +657,112 @@ def test_sparse_adam_matches_oracle_and_leaves_inactive_rows():
         rows = np.arange(b * 256, min(N, (b + 1) * 256))
         rows = rows[act[rows]]
         assert sr[b, 3] >= reach[rows].max() * (1 - 1e-6)
-    del before
 
 
 # --------------------------------------------------- full-size workload
+def test_aerial_full_frames_on_the_gpu_projection():
+    say("case: aerial 1M Gaussians, 4 views 1920x1080, blocks of 65536 (the benchmark's launch shape); "
+        "the oracle's binning and compositing on the GPU's own projection")
+    theta, cams = synth.aerial_workload()
+    cams = cams[:4]
+    rast, pool, proj, bins, fr = gpu_forward(theta, cams, block_rows=65536)
+    stage_isolated_on_the_gpu_projection(rast, proj, bins, fr, cams, range(4))
+
+
 def test_aerial_full_size_view_matches_oracle():
-    say("case: aerial 1M Gaussians, one 1920x1080 view, blocks of 65536 (the benchmark's launch shape)")
+    say("case: aerial 1M Gaussians, one 1920x1080 view end to end, blocks of 65536")
     theta, cams = synth.aerial_workload()
     cams = cams[:4]
     cm = synth.cams_array(cams[:1])
     ref = oracle.render(theta.astype(np.float64), cm)
-    _, _, proj, bins, fr = gpu_forward(theta, cams, block_rows=65536)
-    img = fr.image[:1].double().cpu().numpy()
-    tie = near_tie_pixels(ref)
+    rast, _, proj, bins, fr = gpu_forward(theta, cams[:1], block_rows=65536)
+    img = fr.image.double().cpu().numpy()
+    tie = excluded(near_tie_pixels(ref), "pixels")
     err = np.abs(img - ref["image"]).max(axis=1)
-    say(f"near-tie pixels {int(tie.sum())} of {tie.size}; max-abs error {err[~tie].max():.3e}; "
-        f"pixels over 1e-4: {int((err[~tie] > 1e-4).sum())}; near-tie pixels over 1e-4: "
+    say(f"max-abs error {err[~tie].max():.3e}; near-tie pixels over 1e-4: "
         f"{int((err[tie] > 1e-4).sum())} (max {err[tie].max() if tie.any() else 0.0:.3e})")
     assert err[~tie].max() <= 1e-4
     # a near-tie decision that flips moves a pixel by at most one entry's
     # contribution at the 1/255 alpha floor (or by T below 1e-4): <= 1e-2
     assert err.max() <= 1e-2
-    vis_ref = int(ref["visits"].sum())
-    say(f"visits gpu {int(fr.visits_fwd[0])} oracle {vis_ref}")
+    check_visits_and_contributors(rast, proj, bins, fr, theta, cams[:1], ref, tie)
     assert int(fr.visits_bwd[0]) == int(fr.last[0].sum(dtype=torch.int64))
+
+
+def crop_camera(cam, x0, y0, size=256):
+    """A size x size window of ``cam`` at the 16-aligned pixel (x0, y0): the
+    principal point shifts, so its tiles are tiles of the full frame."""
+    return synth.Camera(cam.R, cam.t, cam.fx, cam.fy, cam.cx - x0, cam.cy - y0, size, size, cam.z_near, cam.z_far)
+
+
+def check_adam(pool, grads, act, p0, cfg_lr):
+    """The GPU's masked Adam after one step per gradient of ``grads`` (dense
+    [N, 59], FP32 values) against the oracle's FP64 updates from the same
+    inputs.
+
+    Bound (reading of the Adam tolerance for FP32 parameter storage): the
+    update Delta = p_new - p_old may differ from the oracle's by
+    1e-3 |Delta_ref| + 1e-3 lr_j plus one unit in the last place of the
+    stored FP32 parameter, the rounding of the store itself, which at
+    |p| ~ 250 m is 1.5e-5, far above 1e-3 lr for the means.  Entries whose
+    gradient is nonzero and below 1e-6 of their group's largest are
+    sign-ambiguous at eps = 1e-15 and are counted and excluded; a zero
+    gradient must leave the parameter exactly where it was on both sides."""
+    N = p0.shape[0]
+    ref_p, ref_m, ref_v = p0.astype(np.float64), np.zeros((N, 59)), np.zeros((N, 59))
+    ref_s = np.zeros(N, dtype=np.int64)
+    for g in grads:
+        ref_p, ref_m, ref_v, ref_s = oracle.adam(ref_p, ref_m, ref_v, ref_s, g, act.astype(np.uint8))
+    p = pool.dense(N).double().cpu().numpy()
+    d_gpu, d_ref = p - p0, ref_p - p0
+    lr = np.array(cfg_lr)
+    ulp = np.spacing(np.abs(ref_p).astype(np.float32)).astype(np.float64)
+    amb = np.zeros((N, 59), dtype=bool)
+    for g in grads:
+        for sl in GROUPS.values():
+            a = np.abs(g[:, sl])
+            amb[:, sl] |= (a > 0) & (a < 1e-6 * a.max())     # a zero gradient moves nothing on either side
+    cmp = act[:, None] & ~amb
+    say(f"Adam: {int(cmp.sum())} entries compared, {int((act[:, None] & amb).sum())} sign-ambiguous excluded")
+    bad = (np.abs(d_gpu - d_ref) > 1e-3 * np.abs(d_ref) + 1e-3 * lr + ulp) & cmp
+    assert bad.sum() == 0, f"{int(bad.sum())} updates outside the bound"
+    assert np.array_equal(p[~act], p0[~act])
+    assert np.array_equal(pool.step.view(-1)[:N].cpu().numpy(), ref_s)
+
+
+def test_aerial_crop_gradient_adam_and_contributors():
+    say("case: aerial 1M Gaussians, 256x256 crop of view 0 at (832, 416), blocks of 65536: image, visits, "
+        "contributors, gradient, two Adam steps")
+    theta, cams = synth.aerial_workload()
+    crop = crop_camera(cams[0], 832, 416)
+    N = theta.shape[0]
+    cm = synth.cams_array([crop])
+    th64 = theta.astype(np.float64)
+    ref = oracle.render(th64, cm)
+    rast, pool, proj, bins, fr = gpu_forward(theta, [crop], block_rows=65536)
+    tie = excluded(near_tie_pixels(ref), "pixels of the crop")
+    err = np.abs(fr.image.double().cpu().numpy() - ref["image"]).max(axis=1)
+    say(f"crop image max-abs error {err[~tie].max():.3e} (all pixels {err.max():.3e})")
+    assert err[~tie].max() <= 1e-4
+    check_visits_and_contributors(rast, proj, bins, fr, theta, [crop], ref, tie)
+    # the photometric loss against a target rendered from perturbed parameters
+    tgt = oracle.render(synth.perturbed(theta, 0.05, 11).astype(np.float64), cm)["image"]
+    _, dimg = oracle.loss(ref["image"], tgt)
+    g_ref = oracle.backward(th64, cm, dimg)
+    g = rast.backward(pool, [crop], proj, bins, fr, torch.tensor(dimg, dtype=torch.float32, device="cuda"))
+    gd32 = dense_grad(proj, g, N)
+    gd = gd32.double().cpu().numpy()
+    act = proj.active[:N].cpu().numpy().astype(bool)
+    nz = act | (np.abs(g_ref).sum(1) > 0)
+    say(f"active rows {int(act.sum())}; rows with an oracle gradient {int((np.abs(g_ref).sum(1) > 0).sum())}")
+    pair_tie = (ref["pair_margin"] < NEAR_TIE).any(axis=0)
+    assert not (act != ref["keep"].any(axis=0))[~pair_tie].any(), "active sets differ outside near ties"
+    tie_rows = excluded(pair_tie[nz], "active rows")
+    rows = np.nonzero(nz)[0][~tie_rows]
+    assert_grad_close(gd[rows], g_ref[rows])
+    # two masked Adam steps with the GPU's gradient, both sides from the same inputs
+    cfg = adam_cfg(LR59)
+    for _ in range(2):
+        rast.adam(pool, proj, g, cfg)
+    torch.cuda.synchronize()
+    check_adam(pool, [gd, gd], act, theta.astype(np.float64), LR59)

@@ -14,7 +14,14 @@ street-level cameras at 1.7 m, 1600x900, horizontal fov 60 deg, z_far
    CPU); every GPU-active row must lie in them.
 3. The FP64 instance of the same kernels against central differences
    (eps 1e-6) on 64 sampled parameters of the crop, with a linear loss
-   L = sum(W * image), W seeded.
+   L = sum(W * image), W seeded.  The difference L(theta + eps) -
+   L(theta - eps) is taken as sum(W * (image+ - image-)), so that only the
+   pixels the step changes carry rounding (a difference of two sums over
+   196 608 terms would leave a noise of about 1e-6 in the derivative); the
+   tolerance is then 1e-4 |fd| + 1e-8.
+
+Near ties: decision margins below 1/16 of their single-precision error
+bound (one ulp), counted and held under 1 % of the pixels or rows compared.
 """
 import sys
 
@@ -29,7 +36,8 @@ from paper_2605_20150_amd.raster import Pool, Rasterizer, dense_grad
 
 pytestmark = pytest.mark.gpu
 B = 65536
-NEAR_TIE = 1.0
+NEAR_TIE = 1.0 / 16
+TIE_CEILING = 0.01
 
 
 def say(m):
@@ -111,6 +119,7 @@ def test_street_50m_rates_crop_gradient_and_finite_differences():
     tie_px = ref["pix_margin"] < NEAR_TIE
     say(f"crop image max-abs error {img_err[~tie_px].max():.3e} ({int(tie_px.sum())} near-tie pixels of "
         f"{tie_px.size}; all pixels {img_err.max():.3e})")
+    assert tie_px.mean() <= TIE_CEILING
     assert img_err[~tie_px].max() <= 1e-4
     # a near-tie decision that flips moves a pixel by at most one entry's
     # contribution at the 1/255 alpha floor (or by T below 1e-4)
@@ -119,7 +128,7 @@ def test_street_50m_rates_crop_gradient_and_finite_differences():
     ok = ~tie_rows
     act_sub = np.isin(rows, active)
     say(f"active rows compared: {int((act_sub & ok).sum())} of {int(act_sub.sum())}")
-    assert (act_sub & ok).sum() >= 0.5 * act_sub.sum()
+    assert (act_sub & ~ok).sum() <= TIE_CEILING * act_sub.sum()
     rel = np.linalg.norm(g_gpu[ok] - g_ref[ok]) / np.linalg.norm(g_ref[ok])
     bound = 1e-3 * np.abs(g_ref[ok]) + 1e-4 * np.abs(g_ref[ok]).max()
     bad = int((np.abs(g_gpu[ok] - g_ref[ok]) > bound).sum())
@@ -134,11 +143,11 @@ def test_street_50m_rates_crop_gradient_and_finite_differences():
     rast = Rasterizer("cuda")
     Wt = torch.from_numpy(Wc).cuda()
 
-    def loss_and_state():
+    def image_and_state():
         proj, bins, fr = rast.forward(pool, [crop])
-        return float((fr.image * Wt).sum()), proj, bins, fr
+        return fr.image.clone(), proj, bins, fr
 
-    l0, proj, bins, fr = loss_and_state()
+    _, proj, bins, fr = image_and_state()
     g64 = rast.backward(pool, [crop], proj, bins, fr, Wt)
     gd = dense_grad(proj, g64, N)
     base_tt = proj.tiles_touched.clone()
@@ -154,21 +163,21 @@ def test_street_50m_rates_crop_gradient_and_finite_differences():
         i, j = int(act[a]), int(rng.integers(0, 59))
         slot, r = i // B, i % B
         orig = pool.params[slot, j, r].item()
-        vals = []
+        imgs = []
         flip = False
         for d in (eps, -eps):
             pool.params[slot, j, r] = orig + d
-            lv, p2, _, f2 = loss_and_state()
+            im, p2, _, f2 = image_and_state()
             flip = flip or not torch.equal(p2.tiles_touched, base_tt) or not torch.equal(f2.last, base_last)
-            vals.append(lv)
+            imgs.append(im)
         pool.params[slot, j, r] = orig
         if flip:
             replaced += 1
             continue
-        fd = (vals[0] - vals[1]) / (2 * eps)
+        fd = float((Wt * (imgs[0] - imgs[1])).sum()) / (2 * eps)
         err = abs(gsel[a, j] - fd)
         worst = max(worst, err / (abs(fd) + 1e-12))
-        assert err <= 1e-4 * abs(fd) + 1e-6, (i, j, gsel[a, j], fd)
+        assert err <= 1e-4 * abs(fd) + 1e-8, (i, j, gsel[a, j], fd)
         done += 1
-    say(f"64 FP64 samples within 1e-4 |fd| + 1e-6 (largest relative error {worst:.2e}, at a small |fd|); "
+    say(f"64 FP64 samples within 1e-4 |fd| + 1e-8 (largest relative error {worst:.2e}); "
         f"{replaced} replaced for a decision flip")

@@ -174,3 +174,62 @@ def test_paper_default_placement_equals_its_resident_emulation(tmp_path):
     dense = pool.dense(theta.shape[0]).cpu().numpy()
     assert np.array_equal(dense, O.params())
     O.tier.close()
+
+
+def test_random_layout_changes_the_working_set_not_the_images(tmp_path):
+    """The ablation without spatial locality (Sec. 4.4, the ablation table):
+    the same Gaussians assigned to blocks in a seeded random order instead of
+    the spatial one.  Every block's bounding sphere then spans the strip, so
+    Level-1 culling keeps every block at every iteration (K_t = all K) while
+    the spatial layout keeps fewer, and the random run moves more bytes to
+    the GPU.  What is rendered does not change: the tile lists hold the same
+    Gaussians in the same (depth, id) order except where two entries of a
+    tile share a single-precision depth (the id decides there, and the two
+    layouts number the Gaussians differently), so every iteration's image
+    agrees to FP32 rounding and nearly every pixel bit for bit.  The walk
+    streams, renders and runs the backward and Adam with learning rates of
+    zero: with training on, a tie's rounding difference could flip the sign
+    of a near-zero gradient entry, which Adam (eps = 1e-15) turns into a full
+    learning-rate step, and the runs would drift apart for that reason alone."""
+    from paper_2605_20150_amd.raster import adam_cfg
+    theta = strip_scene()
+    B = 4096
+    T = 12
+    N = theta.shape[0]
+    K = (N + B - 1) // B
+    batches = walk(T)
+    perm = np.random.Generator(np.random.PCG64(57)).permutation(N)
+    say(f"case: {N} Gaussians in {K} blocks, {T} iterations, spatial vs random block assignment")
+    rast = Rasterizer("cuda")
+    tpool = Pool.from_dense(torch.tensor(synth.perturbed(theta, 0.05, 51), device="cuda"), B)
+    targets = []
+    for t in range(T):
+        _, _, fr = rast.forward(tpool, batches[t])
+        targets.append(fr.image.clone())
+    Om = OutOfCoreTrainer(theta, B, str(tmp_path / "spatial"), capacity=K, spare_slots=2, host_cache_blocks=8)
+    Orr = OutOfCoreTrainer(theta[perm], B, str(tmp_path / "random"), capacity=K, spare_slots=2, host_cache_blocks=8)
+    Om.cfg = adam_cfg([0.0] * 59)
+    Orr.cfg = adam_cfg([0.0] * 59)
+    same_px = []
+    for t in range(T):
+        fm, lm = Om.iterate(batches[t], targets[t], batches[t + 1])
+        fq, lq = Orr.iterate(batches[t], targets[t], batches[t + 1])
+        torch.cuda.synchronize()
+        d = (fm.image - fq.image).abs()
+        same_px.append(float((d == 0).float().mean()))
+        assert float(d.max()) <= 1e-5, f"iteration {t}: images differ by {float(d.max()):.3e}"
+        assert abs(float(lm) - float(lq)) <= 1e-6 * abs(float(lm))
+    km = [len(k) for k in Om.k_sets]
+    kr = [len(k) for k in Orr.k_sets]
+    say(f"|K_t| spatial {km}, random {kr}; bit-identical pixels per iteration: min {min(same_px):.6f}")
+    assert kr == [K] * T
+    assert max(km) < K
+    assert min(same_px) >= 0.999
+    pr = np.empty_like(theta)
+    pr[perm] = Orr.params()
+    assert np.array_equal(pr, Om.params()) and np.array_equal(pr, theta)
+    sm, sr = Om.tier.stats(), Orr.tier.stats()
+    say(f"H2D bytes spatial {sm['h2d_bytes']}, random {sr['h2d_bytes']}")
+    assert sr["h2d_bytes"] > sm["h2d_bytes"]
+    Om.tier.close()
+    Orr.tier.close()

@@ -270,6 +270,31 @@ def test_depth_ties_in_single_precision_keep_gid_order():
     assert np.abs(out["image"][0, :, py, px] - expect).max() < 1e-14
 
 
+def test_depth_key_tie_margin_only_where_the_double_depth_is_inexact():
+    """Near-tie model of the depth key: a camera depth exactly on a rounding
+    midpoint of single precision is a tie only when its double-precision
+    evaluation could round differently elsewhere.  With an axis-aligned
+    camera and a representable mean it is exact (no tie, margin above the
+    threshold); with a rotated camera the same midpoint is reached only up to
+    double rounding and is flagged (margin below 1/16)."""
+    # identity camera at t = (0, 0, 3): p_z = 3 + 2^-23 exactly, the midpoint
+    # between the floats 3 and 3 + 2^-22
+    mu_z = 2.0 ** -23
+    th = one_gaussian((0.0, 0.0, mu_z), (-1.5, -1.5, -1.5))
+    p = oracle.project(th, cam_row())
+    assert p["depth"][0, 0] == 3.0 + 2.0 ** -23
+    assert p["keep"][0, 0] and p["margin"][0, 0] > 1.0 / 16
+    # rotated camera: choose the mean so that the double p_z lands on the
+    # same midpoint to within a few units of double rounding
+    R = Rotation.from_euler("xyz", [0.031, -0.027, 0.013]).as_matrix()
+    mu = np.array([0.0123456789, -0.0234567891, 0.0])
+    mu[2] = (3.0 + 2.0 ** -23 - 3.0 - R[2, 0] * mu[0] - R[2, 1] * mu[1]) / R[2, 2]
+    th = one_gaussian(mu, (-1.5, -1.5, -1.5))
+    p = oracle.project(th, cam_row(R=R))
+    assert abs(p["depth"][0, 0] - (3.0 + 2.0 ** -23)) < 1e-14
+    assert p["keep"][0, 0] and p["margin"][0, 0] < 1.0 / 16
+
+
 def _brute_render(th, cams):
     """Tile-free renderer: for each pixel gather every kept Gaussian whose
     rect contains the pixel's tile, order by (depth, gid), composite."""
