@@ -46,7 +46,7 @@ HBM_BOUND = ("preprocess", "reduce_pairs", "adjoint", "adam", "loss_fwd", "loss_
 # hash of the kernel's sources when they were taken: the figure is reported
 # only while the sources are unchanged.
 TRAFFIC = {"render_bwd": {"bytes": 3960.0e6, "sources": ["raster_bwd.hip", "raster.h"],
-                          "sha256_16": "ff0926ed2cc5672d"}}
+                          "sha256_16": "0ced145811b62fa4"}}
 KERNELS = ["preprocess", "compact_vis", "emit", "render_fwd", "loss_fwd", "loss_bwd", "render_bwd",
            "reduce_pairs", "adjoint", "adam"]
 
@@ -63,7 +63,7 @@ def parse():
                     help="time only the oracle's iteration (no GPU), e.g. at --cpu-threads 1")
     ap.add_argument("--n-blobs", type=int, default=200)
     ap.add_argument("--per-blob", type=int, default=5000)
-    ap.add_argument("--workload", choices=["aerial", "city", "city-ablation", "city-budget", "city-order",
+    ap.add_argument("--workload", choices=["aerial", "street50m", "city", "city-ablation", "city-budget", "city-order",
                                            "layout"],
                     default="aerial",
                     help="aerial: resident training (default); city: out-of-core street city, exact-only "
@@ -543,6 +543,51 @@ def main():
         return order_main(args)
     if args.workload == "layout":
         return layout_main(args)
+    if args.workload == "street50m":
+        return street_main(args)
+    import numpy as np
+
+    from paper_2605_20150_amd import synth
+
+    theta, cams = synth.aerial_workload(n_blobs=args.n_blobs, per_blob=args.per_blob)
+    V = 4
+    if args.cpu_baseline_only:
+        # the oracle's time does not depend on the target's content
+        tg = np.zeros((V, 3, cams[0].height, cams[0].width))
+        print(json.dumps({"cpu_baseline": cpu_baseline(theta, cams[:V], tg, args.cpu_threads)}), flush=True)
+        return
+    resident_run(args, theta, cams, 1920, 1080,
+                 {"workload": f"aerial resident training, {theta.shape[0] // 1000000}M Gaussians, batch 4 x 1920x1080"},
+                 with_cpu_baseline=not args.no_cpu_baseline)
+
+
+def street_main(args):
+    """The 50M-Gaussian scale case resident in HBM: the aerial blob recipe
+    over 2 x 2 km (3200 blobs of 15 625 Gaussians, sigma 5 m, heights U(0, 40)
+    m, seed 20), blobs laid out in the library's Morton order of their
+    centres, trained from a street-level walk (1.7 m eye height along a
+    street at y = 7 m, 1 m per pose, looking along the street, 1600x900,
+    horizontal fov 60 deg, z_far 1000 m), batches of 4 consecutive poses."""
+    import numpy as np
+
+    from paper_2605_20150_amd import predictor as P
+    from paper_2605_20150_amd import synth
+
+    centres = synth.blob_centres(3200, 1000.0, (0.0, 40.0), 20)
+    order = P.morton_order(centres.astype(np.float32))
+    theta = synth.blob_scene_parallel(3200, 15625, 1000.0, (0.0, 40.0), 5.0, 20, order=order)
+    f = synth.focal_for_hfov(1600, 60)
+    n_poses = 4 * (args.warmup + args.steps)
+    cams = [synth.look_at((-400.0 + p, 7.0, 1.7), (-300.0 + p, 7.0, 1.7), (0, 0, 1), 1600, 900, f, z_far=1000.0)
+            for p in range(n_poses)]
+    resident_run(args, theta, cams, 1600, 900,
+                 {"workload": "street-level resident training, 50M Gaussians over 2 x 2 km, batch 4 x 1600x900"},
+                 with_cpu_baseline=False)
+
+
+def resident_run(args, theta, cams, W, H, workload, with_cpu_baseline):
+    """Resident training steps (forward, loss, backward, masked Adam) over
+    batches of 4 consecutive views; prints the JSON line."""
     import numpy as np
     import torch
 
@@ -550,14 +595,8 @@ def main():
     from paper_2605_20150_amd import _lib as L
     from paper_2605_20150_amd.raster import LR59, Pool, Rasterizer, adam_cfg
 
-    theta, cams = synth.aerial_workload(n_blobs=args.n_blobs, per_blob=args.per_blob)
     N = theta.shape[0]
     V = 4
-    if args.cpu_baseline_only:
-        # the oracle's time does not depend on the target's content
-        tg = np.zeros((V, 3, cams[0].height, cams[0].width))
-        print(json.dumps({"cpu_baseline": cpu_baseline(theta, cams[:V], tg, args.cpu_threads)}), flush=True)
-        return
     n_batches = len(cams) // V
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     dev = torch.device("cuda:0")
@@ -654,7 +693,7 @@ def main():
     fwd_visits = np.mean([int(s[3][0].sum().item()) for s in stats])
     bwd_visits = np.mean([int(s[3][1].sum().item()) for s in stats])
     n_kept = n_active
-    pixels = V * 1920 * 1080
+    pixels = V * W * H
     iters = args.steps / wall
 
     kernels = {}
@@ -687,9 +726,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(1e3 * wall / args.steps, 3),
         "iters_per_s_median": round(1e3 / float(np.median(step_ms)), 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "aerial resident training, 1M Gaussians, batch 4 x 1920x1080",
-                   "gaussians": N, "views_per_step": V, "width": 1920, "height": 1080, "block_rows": B,
-                   "parallelism": "single GPU"},
+        "config": dict(workload, gaussians=N, views_per_step=V, width=W, height=H, block_rows=B,
+                       parallelism="single GPU"),
         "visits_per_s": {"fwd": round(fwd_visits / (kern_ms["render_fwd"] * 1e-3), 1),
                          "bwd": round(bwd_visits / (kern_ms["render_bwd"] * 1e-3), 1),
                          "fwd_plus_bwd": round((fwd_visits + bwd_visits) /
@@ -709,7 +747,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    if not args.no_cpu_baseline:
+    if with_cpu_baseline:
         tg0 = targets[0].double().cpu().numpy()
         out["cpu_baseline"] = cpu_baseline(theta, cams[:V], tg0, args.cpu_threads)
     print(json.dumps(out), flush=True)

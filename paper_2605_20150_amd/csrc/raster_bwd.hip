@@ -280,12 +280,146 @@ __global__ void __launch_bounds__(64) k_reduce_pairs(const uint32_t* __restrict_
 }
 
 // --------------------------------------------------- preprocess adjoint
-// Thread per processing index; only active rows work.  Recomputes the
-// forward quantities of each camera that kept the Gaussian, chains the 2-D
-// gradients back to mean, log-scale, quaternion, opacity logit and SH, sums
-// the cameras in index order and writes the compact gradient row.
+template <typename T, int N>
+struct __attribute__((aligned(sizeof(T)))) VecN {
+  T v[N];
+};
+
+// Per camera: the geometry adjoint (mean through the projection, covariance
+// through EWA) for one (Gaussian, camera) pair's 2-D gradients.
 template <typename T>
-__global__ void __launch_bounds__(128) k_adjoint(const T* __restrict__ params, const int32_t* __restrict__ order,
+__device__ __forceinline__ void adj_geom_cam(const DevCam<T>& cm, T mu0, T mu1, T mu2, const T (&Sg)[9], T gu, T gv,
+                                             T gA, T gB, T gC, T (&dSig)[9], T& dmu0, T& dmu1, T& dmu2) {
+  // recompute p, J, T, Sigma', conic
+  const T px = cm.R[0] * mu0 + cm.R[1] * mu1 + cm.R[2] * mu2 + cm.t[0];
+  const T py = cm.R[3] * mu0 + cm.R[4] * mu1 + cm.R[5] * mu2 + cm.t[1];
+  const T pz = cm.R[6] * mu0 + cm.R[7] * mu1 + cm.R[8] * mu2 + cm.t[2];
+  const T iz = (T)1 / pz;
+  const T txz = px * iz, tyz = py * iz;
+  const bool clx = txz < -cm.limx || txz > cm.limx;
+  const bool cly = tyz < -cm.limy || tyz > cm.limy;
+  const T xi = txz < -cm.limx ? -cm.limx : (txz > cm.limx ? cm.limx : txz);
+  const T eta = tyz < -cm.limy ? -cm.limy : (tyz > cm.limy ? cm.limy : tyz);
+  const T J00 = cm.fx * iz, J02 = -cm.fx * xi * iz, J11 = cm.fy * iz, J12 = -cm.fy * eta * iz;
+  T Tm[6];
+  Tm[0] = J00 * cm.R[0] + J02 * cm.R[6]; Tm[1] = J00 * cm.R[1] + J02 * cm.R[7]; Tm[2] = J00 * cm.R[2] + J02 * cm.R[8];
+  Tm[3] = J11 * cm.R[3] + J12 * cm.R[6]; Tm[4] = J11 * cm.R[4] + J12 * cm.R[7]; Tm[5] = J11 * cm.R[5] + J12 * cm.R[8];
+  T TS[6];  // T Sigma (2x3)
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+      TS[3 * a + b] = Tm[3 * a] * Sg[b] + Tm[3 * a + 1] * Sg[3 + b] + Tm[3 * a + 2] * Sg[6 + b];
+  const T c00 = TS[0] * Tm[0] + TS[1] * Tm[1] + TS[2] * Tm[2] + (T)0.3;
+  const T c01 = TS[0] * Tm[3] + TS[1] * Tm[4] + TS[2] * Tm[5];
+  const T c11 = TS[3] * Tm[3] + TS[4] * Tm[4] + TS[5] * Tm[5] + (T)0.3;
+  const T idet = (T)1 / (c00 * c11 - c01 * c01);
+  const T A = c11 * idet, Bc = -c01 * idet, C = c00 * idet;
+  // dL/dSigma' = -Q Gq Q, Q = [[A, B], [B, C]], Gq = [[gA, gB/2], [gB/2, gC]]
+  const T hB = (T)0.5 * gB;
+  const T q00 = A * gA + Bc * hB, q01 = A * hB + Bc * gC, q10 = Bc * gA + C * hB, q11 = Bc * hB + C * gC;
+  const T d00 = -(q00 * A + q01 * Bc), d01 = -(q00 * Bc + q01 * C), d11 = -(q10 * Bc + q11 * C);
+  const T dS[4] = {d00, d01, d01, d11};
+  // dL/dSigma += T^T dS T
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+      dSig[3 * a + b] += Tm[a] * (dS[0] * Tm[b] + dS[1] * Tm[3 + b]) + Tm[3 + a] * (dS[2] * Tm[b] + dS[3] * Tm[3 + b]);
+  // dL/dT = 2 dS T Sigma = 2 dS TS
+  T dT[6];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    dT[b] = 2 * (dS[0] * TS[b] + dS[1] * TS[3 + b]);
+    dT[3 + b] = 2 * (dS[2] * TS[b] + dS[3] * TS[3 + b]);
+  }
+  // dL/dJ = dT W^T (entries 00, 02, 11, 12)
+  const T dJ00 = dT[0] * cm.R[0] + dT[1] * cm.R[1] + dT[2] * cm.R[2];
+  const T dJ02 = dT[0] * cm.R[6] + dT[1] * cm.R[7] + dT[2] * cm.R[8];
+  const T dJ11 = dT[3] * cm.R[3] + dT[4] * cm.R[4] + dT[5] * cm.R[5];
+  const T dJ12 = dT[3] * cm.R[6] + dT[4] * cm.R[7] + dT[5] * cm.R[8];
+  const T iz2 = iz * iz;
+  T dpx = gu * cm.fx * iz, dpy = gv * cm.fy * iz;
+  T dpz = -(gu * cm.fx * px + gv * cm.fy * py) * iz2;
+  dpz += -dJ00 * cm.fx * iz2 - dJ11 * cm.fy * iz2;
+  if (!clx) {
+    dpx += dJ02 * (-cm.fx * iz2);
+    dpz += dJ02 * ((T)2 * cm.fx * px * iz2 * iz);
+  } else {
+    dpz += dJ02 * (cm.fx * xi * iz2);
+  }
+  if (!cly) {
+    dpy += dJ12 * (-cm.fy * iz2);
+    dpz += dJ12 * ((T)2 * cm.fy * py * iz2 * iz);
+  } else {
+    dpz += dJ12 * (cm.fy * eta * iz2);
+  }
+  dmu0 += cm.R[0] * dpx + cm.R[3] * dpy + cm.R[6] * dpz;
+  dmu1 += cm.R[1] * dpx + cm.R[4] * dpy + cm.R[7] * dpz;
+  dmu2 += cm.R[2] * dpx + cm.R[5] * dpy + cm.R[8] * dpz;
+}
+
+// Per (camera, colour channel): the colour adjoint of SH degree 3 for the
+// channel's 16 coefficients, and the viewing direction's share of the mean
+// gradient (linear in the channel's contribution).
+template <typename T>
+__device__ __forceinline__ void adj_colour_cam(const ShK<T>& K, const DevCam<T>& cm, T mu0, T mu1, T mu2,
+                                               const T (&sh)[16], T gcol, T (&gs)[16], T& dmu0, T& dmu1, T& dmu2) {
+  T dx = mu0 - cm.pos[0], dy = mu1 - cm.pos[1], dz = mu2 - cm.pos[2];
+  const T len = Mth<T>::sqrt(dx * dx + dy * dy + dz * dz);
+  const T il = (T)1 / len;
+  dx *= il; dy *= il; dz *= il;
+  T Y[16];
+  sh_eval<T>(K, dx, dy, dz, Y);
+  T raw = (T)0.5;
+#pragma unroll
+  for (int m = 0; m < 16; ++m) raw += Y[m] * sh[m];
+  const T graw = raw < 0 ? (T)0 : gcol;
+  T wk[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    gs[m] += Y[m] * graw;
+    wk[m] = sh[m] * graw;
+  }
+  {
+    const T x = dx, y = dy, z = dz, xx = x * x, yy = y * y, zz = z * z;
+    T gx = 0, gy = 0, gz = 0;
+    gy += -K.c1 * wk[1];
+    gz += K.c1 * wk[2];
+    gx += -K.c1 * wk[3];
+    gx += K.c2a * y * wk[4]; gy += K.c2a * x * wk[4];
+    gy += -K.c2a * z * wk[5]; gz += -K.c2a * y * wk[5];
+    gx += -2 * K.c2b * x * wk[6]; gy += -2 * K.c2b * y * wk[6]; gz += 4 * K.c2b * z * wk[6];
+    gx += -K.c2a * z * wk[7]; gz += -K.c2a * x * wk[7];
+    gx += 2 * K.c2c * x * wk[8]; gy += -2 * K.c2c * y * wk[8];
+    gx += -K.c3a * 6 * x * y * wk[9]; gy += -K.c3a * (3 * xx - 3 * yy) * wk[9];
+    gx += K.c3b * y * z * wk[10]; gy += K.c3b * x * z * wk[10]; gz += K.c3b * x * y * wk[10];
+    gx += 2 * K.c3c * x * y * wk[11]; gy += -K.c3c * (4 * zz - xx - 3 * yy) * wk[11];
+    gz += -8 * K.c3c * y * z * wk[11];
+    gx += -6 * K.c3d * x * z * wk[12]; gy += -6 * K.c3d * y * z * wk[12];
+    gz += K.c3d * (6 * zz - 3 * xx - 3 * yy) * wk[12];
+    gx += -K.c3c * (4 * zz - 3 * xx - yy) * wk[13]; gy += 2 * K.c3c * x * y * wk[13];
+    gz += -8 * K.c3c * x * z * wk[13];
+    gx += 2 * K.c3e * x * z * wk[14]; gy += -2 * K.c3e * y * z * wk[14]; gz += K.c3e * (xx - yy) * wk[14];
+    gx += -K.c3a * (3 * xx - 3 * yy) * wk[15]; gy += 6 * K.c3a * x * y * wk[15];
+    const T dd = gx * x + gy * y + gz * z;
+    dmu0 += (gx - dd * x) * il;
+    dmu1 += (gy - dd * y) * il;
+    dmu2 += (gz - dd * z) * il;
+  }
+}
+
+// Thread per processing index; only active rows work.  Each kept camera's
+// 36-byte record of 2-D gradients is read once, as one object: pass 1 chains
+// its geometry part (u, v, conic) back to mean, log-scale and quaternion,
+// cameras in order, and parks its opacity and colour part in LDS; pass 2
+// runs the opacity and then the colour, one channel at a time (that
+// channel's 16 coefficients and 16 sums live at once; the viewing direction
+// and SH basis are recomputed per channel), cameras in order.  91 VGPRs and
+// 32 KB of LDS per 256 threads: five waves per SIMD, against two when the
+// 48 SH sums were held together.
+template <typename T>
+__global__ void __launch_bounds__(256) k_adjoint(const T* __restrict__ params, const int32_t* __restrict__ order,
                                                  int32_t B, int64_t n_pidx, CamSet<T> cs,
                                                  const uint32_t* __restrict__ tt, const uint32_t* __restrict__ active,
                                                  const uint32_t* __restrict__ act_idx, const T* __restrict__ g2d,
@@ -296,86 +430,13 @@ __global__ void __launch_bounds__(128) k_adjoint(const T* __restrict__ params, c
   const int32_t row = (int32_t)(i - k * B);
   const int32_t slot = order[k];
   const T* P = params + (int64_t)slot * kD * B + row;
+  const int V = cs.n;
+  uint32_t keepm = 0;
+#pragma unroll 1
+  for (int c = 0; c < V; ++c) keepm |= (tt[(int64_t)c * n_pidx + i] != 0 ? 1u : 0u) << c;
   const T mu0 = P[0], mu1 = P[B], mu2 = P[2 * (int64_t)B];
   const T s0 = Mth<T>::exp(P[3 * (int64_t)B]), s1 = Mth<T>::exp(P[4 * (int64_t)B]),
           s2 = Mth<T>::exp(P[5 * (int64_t)B]);
-  // Pass 1 over the cameras: colour (SH and the viewing direction) and
-  // opacity.  The 48 SH sums are stored before pass 2, so the two passes'
-  // registers need not be live together (320 -> 249 VGPRs: two waves per
-  // SIMD instead of one).
-  const T op = (T)1 / ((T)1 + Mth<T>::exp(-P[10 * (int64_t)B]));
-  T gsh[48];
-#pragma unroll
-  for (int m = 0; m < 48; ++m) gsh[m] = 0;
-  T dmu0 = 0, dmu1 = 0, dmu2 = 0, dlogit = 0;
-#pragma unroll 1
-  for (int c = 0; c < cs.n; ++c) {
-    const int64_t o = (int64_t)c * n_pidx + i;
-    if (tt[o] == 0) continue;
-    const DevCam<T>& cm = cs.c[c];
-    const T* G2 = g2d + o * kG2;
-    const T gop = G2[5];
-    const T gcol[3] = {G2[6], G2[7], G2[8]};
-    // ---- colour
-    T dx = mu0 - cm.pos[0], dy = mu1 - cm.pos[1], dz = mu2 - cm.pos[2];
-    const T len = Mth<T>::sqrt(dx * dx + dy * dy + dz * dz);
-    const T il = (T)1 / len;
-    dx *= il; dy *= il; dz *= il;
-    T Y[16];
-    sh_eval<T>(cs.sh, dx, dy, dz, Y);
-    T graw[3];
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-      T raw = (T)0.5;
-#pragma unroll
-      for (int m = 0; m < 16; ++m) raw += Y[m] * P[(int64_t)(11 + 3 * m + ch) * B];
-      graw[ch] = raw < 0 ? (T)0 : gcol[ch];
-    }
-    T wk[16];
-#pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      gsh[3 * m] += Y[m] * graw[0];
-      gsh[3 * m + 1] += Y[m] * graw[1];
-      gsh[3 * m + 2] += Y[m] * graw[2];
-      wk[m] = P[(int64_t)(11 + 3 * m) * B] * graw[0] + P[(int64_t)(12 + 3 * m) * B] * graw[1] +
-              P[(int64_t)(13 + 3 * m) * B] * graw[2];
-    }
-    {
-      const ShK<T>& K = cs.sh;
-      const T x = dx, y = dy, z = dz, xx = x * x, yy = y * y, zz = z * z;
-      T gx = 0, gy = 0, gz = 0;
-      gy += -K.c1 * wk[1];
-      gz += K.c1 * wk[2];
-      gx += -K.c1 * wk[3];
-      gx += K.c2a * y * wk[4]; gy += K.c2a * x * wk[4];
-      gy += -K.c2a * z * wk[5]; gz += -K.c2a * y * wk[5];
-      gx += -2 * K.c2b * x * wk[6]; gy += -2 * K.c2b * y * wk[6]; gz += 4 * K.c2b * z * wk[6];
-      gx += -K.c2a * z * wk[7]; gz += -K.c2a * x * wk[7];
-      gx += 2 * K.c2c * x * wk[8]; gy += -2 * K.c2c * y * wk[8];
-      gx += -K.c3a * 6 * x * y * wk[9]; gy += -K.c3a * (3 * xx - 3 * yy) * wk[9];
-      gx += K.c3b * y * z * wk[10]; gy += K.c3b * x * z * wk[10]; gz += K.c3b * x * y * wk[10];
-      gx += 2 * K.c3c * x * y * wk[11]; gy += -K.c3c * (4 * zz - xx - 3 * yy) * wk[11];
-      gz += -8 * K.c3c * y * z * wk[11];
-      gx += -6 * K.c3d * x * z * wk[12]; gy += -6 * K.c3d * y * z * wk[12];
-      gz += K.c3d * (6 * zz - 3 * xx - 3 * yy) * wk[12];
-      gx += -K.c3c * (4 * zz - 3 * xx - yy) * wk[13]; gy += 2 * K.c3c * x * y * wk[13];
-      gz += -8 * K.c3c * x * z * wk[13];
-      gx += 2 * K.c3e * x * z * wk[14]; gy += -2 * K.c3e * y * z * wk[14]; gz += K.c3e * (xx - yy) * wk[14];
-      gx += -K.c3a * (3 * xx - 3 * yy) * wk[15]; gy += 6 * K.c3a * x * y * wk[15];
-      const T dd = gx * x + gy * y + gz * z;
-      dmu0 += (gx - dd * x) * il;
-      dmu1 += (gy - dd * y) * il;
-      dmu2 += (gz - dd * z) * il;
-    }
-    dlogit += gop * op * ((T)1 - op);
-  }
-  const int64_t a = act_idx[i];
-  T* G = grad + a;
-  G[10 * ld] = dlogit;
-#pragma unroll
-  for (int m = 0; m < 48; ++m) G[(int64_t)(11 + m) * ld] = gsh[m];
-
-  // Pass 2: geometry (mean through the projection, covariance)
   const T qw0 = P[6 * (int64_t)B], qx0 = P[7 * (int64_t)B], qy0 = P[8 * (int64_t)B], qz0 = P[9 * (int64_t)B];
   const T qn = Mth<T>::sqrt(qw0 * qw0 + qx0 * qx0 + qy0 * qy0 + qz0 * qz0);
   const T iq = (T)1 / qn;
@@ -394,85 +455,21 @@ __global__ void __launch_bounds__(128) k_adjoint(const T* __restrict__ params, c
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int b = 0; b < 3; ++b) Sg[3 * a + b] = M[3 * a] * M[3 * b] + M[3 * a + 1] * M[3 * b + 1] + M[3 * a + 2] * M[3 * b + 2];
-
   T dSig[9];
 #pragma unroll
   for (int m = 0; m < 9; ++m) dSig[m] = 0;
+  T dmu0 = 0, dmu1 = 0, dmu2 = 0;
+  // per camera, d/dopacity and d/dcolour wait in LDS for pass 2
+  __shared__ T s_q[TIDE_MAX_CAMS][4][256];
+  const int tx = threadIdx.x;
 #pragma unroll 1
-  for (int c = 0; c < cs.n; ++c) {
-    const int64_t o = (int64_t)c * n_pidx + i;
-    if (tt[o] == 0) continue;
-    const DevCam<T>& cm = cs.c[c];
-    const T* G2 = g2d + o * kG2;
-    const T gu = G2[0], gv = G2[1], gA = G2[2], gB = G2[3], gC = G2[4];
-    // ---- geometry: recompute p, J, T, Sigma', conic
-    const T px = cm.R[0] * mu0 + cm.R[1] * mu1 + cm.R[2] * mu2 + cm.t[0];
-    const T py = cm.R[3] * mu0 + cm.R[4] * mu1 + cm.R[5] * mu2 + cm.t[1];
-    const T pz = cm.R[6] * mu0 + cm.R[7] * mu1 + cm.R[8] * mu2 + cm.t[2];
-    const T iz = (T)1 / pz;
-    const T txz = px * iz, tyz = py * iz;
-    const bool clx = txz < -cm.limx || txz > cm.limx;
-    const bool cly = tyz < -cm.limy || tyz > cm.limy;
-    const T xi = txz < -cm.limx ? -cm.limx : (txz > cm.limx ? cm.limx : txz);
-    const T eta = tyz < -cm.limy ? -cm.limy : (tyz > cm.limy ? cm.limy : tyz);
-    const T J00 = cm.fx * iz, J02 = -cm.fx * xi * iz, J11 = cm.fy * iz, J12 = -cm.fy * eta * iz;
-    T Tm[6];
-    Tm[0] = J00 * cm.R[0] + J02 * cm.R[6]; Tm[1] = J00 * cm.R[1] + J02 * cm.R[7]; Tm[2] = J00 * cm.R[2] + J02 * cm.R[8];
-    Tm[3] = J11 * cm.R[3] + J12 * cm.R[6]; Tm[4] = J11 * cm.R[4] + J12 * cm.R[7]; Tm[5] = J11 * cm.R[5] + J12 * cm.R[8];
-    T TS[6];  // T Sigma (2x3)
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 3; ++b)
-        TS[3 * a + b] = Tm[3 * a] * Sg[b] + Tm[3 * a + 1] * Sg[3 + b] + Tm[3 * a + 2] * Sg[6 + b];
-    const T c00 = TS[0] * Tm[0] + TS[1] * Tm[1] + TS[2] * Tm[2] + (T)0.3;
-    const T c01 = TS[0] * Tm[3] + TS[1] * Tm[4] + TS[2] * Tm[5];
-    const T c11 = TS[3] * Tm[3] + TS[4] * Tm[4] + TS[5] * Tm[5] + (T)0.3;
-    const T idet = (T)1 / (c00 * c11 - c01 * c01);
-    const T A = c11 * idet, Bc = -c01 * idet, C = c00 * idet;
-    // dL/dSigma' = -Q Gq Q, Q = [[A, B], [B, C]], Gq = [[gA, gB/2], [gB/2, gC]]
-    const T hB = (T)0.5 * gB;
-    const T q00 = A * gA + Bc * hB, q01 = A * hB + Bc * gC, q10 = Bc * gA + C * hB, q11 = Bc * hB + C * gC;
-    const T d00 = -(q00 * A + q01 * Bc), d01 = -(q00 * Bc + q01 * C), d11 = -(q10 * Bc + q11 * C);
-    const T dS[4] = {d00, d01, d01, d11};
-    // dL/dSigma += T^T dS T
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int b = 0; b < 3; ++b)
-        dSig[3 * a + b] += Tm[a] * (dS[0] * Tm[b] + dS[1] * Tm[3 + b]) + Tm[3 + a] * (dS[2] * Tm[b] + dS[3] * Tm[3 + b]);
-    // dL/dT = 2 dS T Sigma = 2 dS TS
-    T dT[6];
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      dT[b] = 2 * (dS[0] * TS[b] + dS[1] * TS[3 + b]);
-      dT[3 + b] = 2 * (dS[2] * TS[b] + dS[3] * TS[3 + b]);
-    }
-    // dL/dJ = dT W^T (entries 00, 02, 11, 12)
-    const T dJ00 = dT[0] * cm.R[0] + dT[1] * cm.R[1] + dT[2] * cm.R[2];
-    const T dJ02 = dT[0] * cm.R[6] + dT[1] * cm.R[7] + dT[2] * cm.R[8];
-    const T dJ11 = dT[3] * cm.R[3] + dT[4] * cm.R[4] + dT[5] * cm.R[5];
-    const T dJ12 = dT[3] * cm.R[6] + dT[4] * cm.R[7] + dT[5] * cm.R[8];
-    const T iz2 = iz * iz;
-    T dpx = gu * cm.fx * iz, dpy = gv * cm.fy * iz;
-    T dpz = -(gu * cm.fx * px + gv * cm.fy * py) * iz2;
-    dpz += -dJ00 * cm.fx * iz2 - dJ11 * cm.fy * iz2;
-    if (!clx) {
-      dpx += dJ02 * (-cm.fx * iz2);
-      dpz += dJ02 * ((T)2 * cm.fx * px * iz2 * iz);
-    } else {
-      dpz += dJ02 * (cm.fx * xi * iz2);
-    }
-    if (!cly) {
-      dpy += dJ12 * (-cm.fy * iz2);
-      dpz += dJ12 * ((T)2 * cm.fy * py * iz2 * iz);
-    } else {
-      dpz += dJ12 * (cm.fy * eta * iz2);
-    }
-    dmu0 += cm.R[0] * dpx + cm.R[3] * dpy + cm.R[6] * dpz;
-    dmu1 += cm.R[1] * dpx + cm.R[4] * dpy + cm.R[7] * dpz;
-    dmu2 += cm.R[2] * dpx + cm.R[5] * dpy + cm.R[8] * dpz;
+  for (int c = 0; c < V; ++c) {
+    if (!((keepm >> c) & 1u)) continue;
+    const VecN<T, 9> r = *reinterpret_cast<const VecN<T, 9>*>(g2d + ((int64_t)c * n_pidx + i) * kG2);
+    s_q[c][0][tx] = r.v[5]; s_q[c][1][tx] = r.v[6]; s_q[c][2][tx] = r.v[7]; s_q[c][3][tx] = r.v[8];
+    adj_geom_cam<T>(cs.c[c], mu0, mu1, mu2, Sg, r.v[0], r.v[1], r.v[2], r.v[3], r.v[4], dSig, dmu0, dmu1, dmu2);
   }
+  T* G = grad + act_idx[i];
   // Sigma = M M^T: dM = 2 dSig M (dSig symmetric)
   T dM[9];
 #pragma unroll
@@ -495,12 +492,45 @@ __global__ void __launch_bounds__(128) k_adjoint(const T* __restrict__ params, c
   dq[2] = 2 * (-2 * y * g9[0] + x * g9[1] + w * g9[2] + x * g9[3] + z * g9[5] - w * g9[6] + z * g9[7] - 2 * y * g9[8]);
   dq[3] = 2 * (-2 * z * g9[0] - w * g9[1] + x * g9[2] + w * g9[3] - 2 * z * g9[4] + y * g9[5] + x * g9[6] + y * g9[7]);
   const T dqq = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
-  G[0] = dmu0; G[ld] = dmu1; G[2 * ld] = dmu2;
   G[3 * ld] = gls[0]; G[4 * ld] = gls[1]; G[5 * ld] = gls[2];
   G[6 * ld] = (dq[0] - dqq * w) * iq;
   G[7 * ld] = (dq[1] - dqq * x) * iq;
   G[8 * ld] = (dq[2] - dqq * y) * iq;
   G[9 * ld] = (dq[3] - dqq * z) * iq;
+  // opacity
+  const T op = (T)1 / ((T)1 + Mth<T>::exp(-P[10 * (int64_t)B]));
+  T dlogit = 0;
+#pragma unroll 1
+  for (int c = 0; c < V; ++c)
+    if ((keepm >> c) & 1u) dlogit += s_q[c][0][tx] * op * ((T)1 - op);
+  G[10 * ld] = dlogit;
+  // colour, one channel at a time
+#pragma unroll 1
+  for (int ch = 0; ch < 3; ++ch) {
+    T sh[16], gs[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      sh[m] = P[(int64_t)(11 + 3 * m + ch) * B];
+      gs[m] = 0;
+    }
+#pragma unroll 1
+    for (int c = 0; c < V; ++c) {
+      if (!((keepm >> c) & 1u)) continue;
+      const T gcol = s_q[c][1 + ch][tx];
+      adj_colour_cam<T>(cs.sh, cs.c[c], mu0, mu1, mu2, sh, gcol, gs, dmu0, dmu1, dmu2);
+    }
+#pragma unroll
+    for (int m = 0; m < 16; ++m) G[(int64_t)(11 + 3 * m + ch) * ld] = gs[m];
+  }
+  G[0] = dmu0; G[ld] = dmu1; G[2 * ld] = dmu2;
+}
+
+template <typename T>
+static void launch_adjoint(const tide_pool* pool, const tide_proj* proj, const CamSet<T>& cs, const T* g2d,
+                           T* grad, int64_t ld, hipStream_t st) {
+  hipLaunchKernelGGL(k_adjoint<T>, dim3((uint32_t)ceil_div(proj->n_pidx, 256)), dim3(256), 0, st,
+                     (const T*)pool->params, pool->order, pool->block_rows, proj->n_pidx, cs, proj->tiles_touched,
+                     proj->active, proj->act_idx, g2d, grad, ld);
 }
 
 template <typename T>
@@ -551,9 +581,7 @@ extern "C" tide_status tide_render_bwd(const tide_pool* pool, const tide_camera*
     TIDE_LAUNCH_CHECK("k_reduce_pairs");
     const CamSet<float> cs = make_camset<float>(cams, n_cams);
     if (proj->n_pidx > 0)
-      TIDE_TIMED("adjoint", st, hipLaunchKernelGGL(k_adjoint<float>, dim3((uint32_t)ceil_div(proj->n_pidx, 128)), dim3(128), 0, st,
-                         (const float*)pool->params, pool->order, pool->block_rows, proj->n_pidx, cs,
-                         proj->tiles_touched, proj->active, proj->act_idx, (const float*)g2d, (float*)grad, grad_ld));
+      TIDE_TIMED("adjoint", st, launch_adjoint<float>(pool, proj, cs, g2d, (float*)grad, grad_ld, st));
     TIDE_LAUNCH_CHECK("k_adjoint");
   } else {
     double* partial = cv.take<double>((size_t)(bins->n_inst > 0 ? bins->n_inst : 1) * kG2);
@@ -571,10 +599,7 @@ extern "C" tide_status tide_render_bwd(const tide_pool* pool, const tide_camera*
     TIDE_LAUNCH_CHECK("k_reduce_pairs");
     const CamSet<double> cs = make_camset<double>(cams, n_cams);
     if (proj->n_pidx > 0)
-      TIDE_TIMED("adjoint", st, hipLaunchKernelGGL(k_adjoint<double>, dim3((uint32_t)ceil_div(proj->n_pidx, 128)), dim3(128), 0, st,
-                         (const double*)pool->params, pool->order, pool->block_rows, proj->n_pidx, cs,
-                         proj->tiles_touched, proj->active, proj->act_idx, (const double*)g2d, (double*)grad,
-                         grad_ld));
+      TIDE_TIMED("adjoint", st, launch_adjoint<double>(pool, proj, cs, g2d, (double*)grad, grad_ld, st));
     TIDE_LAUNCH_CHECK("k_adjoint");
   }
   return TIDE_OK;
