@@ -47,6 +47,13 @@ HBM_BOUND = ("preprocess", "reduce_pairs", "adjoint", "adam", "loss_fwd", "loss_
 # only while the sources are unchanged.
 TRAFFIC = {"render_bwd": {"bytes": 3960.0e6, "sources": ["raster_bwd.hip", "raster.h"],
                           "sha256_16": "0ced145811b62fa4"}}
+# Executed-instruction view of the dominant kernel from one SQ counter pass
+# of this benchmark (profiles/render_aerial1M_sq_instructions.md): VALU
+# wave-instructions per launch and the busy cycles per VALU instruction of a
+# SIMD (4 cycles is one wave64 instruction back to back on a 16-lane SIMD),
+# reported while the kernel's sources are those the counters were taken on.
+ISSUE = {"render_bwd": {"valu_wave_instr": 1083.45e6, "cycles_per_valu_per_simd": 3.61,
+                        "sources": ["raster_bwd.hip", "raster.h"], "sha256_16": TRAFFIC["render_bwd"]["sha256_16"]}}
 KERNELS = ["preprocess", "compact_vis", "emit", "render_fwd", "loss_fwd", "loss_bwd", "render_bwd",
            "reduce_pairs", "adjoint", "adam"]
 
@@ -109,18 +116,33 @@ def algorithmic_bytes(kernel, n_pidx, n_kept, n_vis, n_inst, n_active, pixels, V
     return 0
 
 
-def measured_traffic(kernel):
-    """Counter-measured bytes per launch, or None if the kernel's sources have
-    changed since the counters were taken."""
+def sources_unchanged(t):
     import hashlib
-    t = TRAFFIC.get(kernel)
-    if t is None:
-        return None
     h = hashlib.sha256()
     for f in t["sources"]:
         with open(os.path.join(ROOT, "paper_2605_20150_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    return t["bytes"] if h.hexdigest()[:16] == t["sha256_16"] else None
+    return h.hexdigest()[:16] == t["sha256_16"]
+
+
+def measured_traffic(kernel):
+    """Counter-measured bytes per launch, or None if the kernel's sources have
+    changed since the counters were taken."""
+    t = TRAFFIC.get(kernel)
+    if t is None:
+        return None
+    return t["bytes"] if sources_unchanged(t) else None
+
+
+def measured_issue(kernel):
+    """The executed-instruction figures of ISSUE, or None (as for traffic)."""
+    t = ISSUE.get(kernel)
+    if t is None or not sources_unchanged(t):
+        return None
+    return {"valu_wave_instr_per_launch": t["valu_wave_instr"],
+            "cycles_per_valu_per_simd": t["cycles_per_valu_per_simd"],
+            "note": "rocprofv3 SQ_INSTS_VALU and GRBM_GUI_ACTIVE / 8 over 1024 SIMDs; 4 cycles per wave64 "
+                    "VALU instruction is back-to-back issue"}
 
 
 def cpu_baseline(theta, cams, targets, threads=0):
@@ -711,7 +733,7 @@ def resident_run(args, theta, cams, W, H, workload, with_cpu_baseline):
         ach = fwd_tflops if dominant == "render_fwd" else bwd_tflops
         roof = {"kernel": dominant, "bound": "alu", "achieved": round(ach, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(ach / FP32_VECTOR_PEAK_TFLOPS, 4),
-                "traffic": measured_traffic(dominant),
+                "traffic": measured_traffic(dominant), "executed": measured_issue(dominant),
                 "note": (f"algorithmic: {FLOPS_PER_BWD_VISIT if dominant == 'render_bwd' else FLOPS_PER_FWD_VISIT} "
                          f"operations per visit (entries up to each pixel's last contributor for the "
                          f"backward, entries evaluated for the forward) over the kernel's own launch time")}

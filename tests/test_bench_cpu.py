@@ -42,6 +42,17 @@ def test_traffic_only_while_the_sources_are_unchanged(monkeypatch):
     assert bench.measured_traffic("render_bwd") is None
 
 
+def test_executed_instructions_only_while_the_sources_are_unchanged(monkeypatch):
+    src = ["raster_bwd.hip", "raster.h"]
+    entry = {"valu_wave_instr": 5.0e8, "cycles_per_valu_per_simd": 3.5, "sources": src}
+    monkeypatch.setattr(bench, "ISSUE", {"render_bwd": dict(entry, sha256_16=_hash(src))})
+    got = bench.measured_issue("render_bwd")
+    assert got["valu_wave_instr_per_launch"] == 5.0e8 and got["cycles_per_valu_per_simd"] == 3.5
+    assert bench.measured_issue("render_fwd") is None
+    monkeypatch.setattr(bench, "ISSUE", {"render_bwd": dict(entry, sha256_16="0" * 16)})
+    assert bench.measured_issue("render_bwd") is None
+
+
 def test_committed_traffic_entry_names_existing_sources():
     for kernel, t in bench.TRAFFIC.items():
         assert kernel in bench.KERNELS
