@@ -145,24 +145,10 @@ def measured_issue(kernel):
                     "VALU instruction is back-to-back issue"}
 
 
-def cpu_baseline(theta, cams, targets, threads=0):
-    """The FP64 oracle (as it stands), built -O3 -march=native on this host,
-    over one whole iteration of the timed workload: the 4 views of batch 0
-    through projection, binning, compositing, loss, backward and masked
-    Adam, each stage timed.  threads = 0 uses every core the OpenMP runtime
-    offers."""
-    import tempfile
-
+def _oracle_iteration(oracle, th, cm, targets):
+    """One whole training iteration of the FP64 oracle; per-stage seconds and
+    the forward's visit count."""
     import numpy as np
-
-    import oracle
-    from paper_2605_20150_amd.synth import cams_array
-    so = os.path.join(tempfile.gettempdir(), f"liboracle_native_{os.getpid()}.so")
-    oracle.build(force=True, so=so, native=True)
-    oracle.use(so)
-    used = oracle.set_threads(threads)
-    th = theta.astype(np.float64)
-    cm = cams_array(cams)
     t = [time.perf_counter()]
     p = oracle.project(th, cm)
     t.append(time.perf_counter())
@@ -179,18 +165,65 @@ def cpu_baseline(theta, cams, targets, threads=0):
     z = np.zeros_like(th)
     oracle.adam(th, z, z, np.zeros(th.shape[0], dtype=np.int64), g, p["keep"].any(0).astype(np.uint8))
     t.append(time.perf_counter())
-    os.remove(so)
     names = ["project", "bin_sort", "composite", "loss", "backward", "adam"]
-    stages = {k: round(t[i + 1] - t[i], 3) for i, k in enumerate(names)}
-    total = t[-1] - t[0]
-    visits = float(r["visits"].sum())
+    return {k: round(t[i + 1] - t[i], 4) for i, k in enumerate(names)}, float(r["visits"].sum())
+
+
+def cpu_baseline(theta, cams, targets, threads=0):
+    """The FP64 oracle (as it stands), built -O3 -march=native on this host,
+    over one whole iteration of the timed workload: the 4 views of batch 0
+    through projection, binning, compositing, loss, backward and masked
+    Adam, each stage timed.  threads = 0 uses every core the OpenMP runtime
+    offers.  Beside it: one thread on a bounded sample (the forward of view
+    0), and the tiny scene (1000 Gaussians, one 64x64 view) for a whole
+    iteration on all threads and on one."""
+    import tempfile
+
+    import numpy as np
+
+    import oracle
+    from paper_2605_20150_amd import synth
+    from paper_2605_20150_amd.synth import cams_array
+    so = os.path.join(tempfile.gettempdir(), f"liboracle_native_{os.getpid()}.so")
+    oracle.build(force=True, so=so, native=True)
+    oracle.use(so)
+    used = oracle.set_threads(threads)
+    th = theta.astype(np.float64)
+    cm = cams_array(cams)
+    stages, visits = _oracle_iteration(oracle, th, cm, targets)
+    total = sum(stages.values())
+    # one thread: the forward of view 0
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    p = oracle.project(th, cm[:1])
+    radius = np.where(p["keep"], p["radius"], 0)
+    gid, ranges = oracle.bin_sort(p["u"], p["v"], np.float32(p["depth"]).astype(np.float64), radius, p["keep"],
+                                  cm[:1])
+    rec = np.concatenate([p["u"][..., None], p["v"][..., None], p["conic"], p["opacity"][..., None], p["rgb"]], -1)
+    r1 = oracle.composite(gid, ranges, rec, cm[:1])
+    t1 = time.perf_counter() - t0
+    single = {"cores": 1, "s": round(t1, 3),
+              "sample": "the forward (projection, binning, compositing) of view 0 of batch 0",
+              "visits_per_s_fwd": float(r1["visits"].sum()) / t1}
+    # the tiny scene, all threads and one
+    tth, tcams, ttgt = synth.tiny_workload()
+    tcm = cams_array(tcams)
+    ttarget = oracle.render(ttgt.astype(np.float64), tcm)["image"]
+    tiny = {}
+    for name, n in (("all_threads", used), ("one_thread", 1)):
+        oracle.set_threads(n)
+        st, _ = _oracle_iteration(oracle, tth.astype(np.float64), tcm, ttarget)
+        tiny[name] = {"iters_per_s": 1.0 / sum(st.values()), "stage_s": st}
+    oracle.set_threads(used)
+    os.remove(so)
     return {"value": 1.0 / total, "unit": "iters/s", "cores": used, "kind": "oracle", "cpu": cpu_model(),
             "build": "g++ -O3 -march=native -fopenmp -ffp-contract=off (no fast-math)",
             "sample": (f"one whole iteration: the FP64 oracle over all {th.shape[0]} Gaussians and the 4 "
                        f"1920x1080 views of batch 0, {total:.1f} s; the backward recomputes its forward"),
             "stage_s": stages,
             "visits_per_s_fwd": visits / (stages["composite"] + stages["bin_sort"] + stages["project"]),
-            "gaussians_per_s_project": th.shape[0] * len(cams) / stages["project"]}
+            "gaussians_per_s_project": th.shape[0] * len(cams) / stages["project"],
+            "single_thread": single, "tiny_scene": tiny}
 
 
 def cpu_model():
