@@ -6,12 +6,6 @@
 
 namespace tide {
 
-template <typename T>
-struct AdamK {
-  T lr[kD];
-  T b1, b2, eps, kappa;
-};
-
 // Passes over the active rows; inactive rows are never written, so they
 // stay bit-identical.
 //  1. Per row, step += 1 and the bias corrections 1/(1 - b1^t),
@@ -51,11 +45,11 @@ __global__ void __launch_bounds__(256) k_adam_cols(T* __restrict__ params, T* __
   const int64_t o = ((int64_t)order[k] * kD + j) * B + row;
   const T g = grad[(int64_t)act_idx[i] + (int64_t)j * ld];
   const double2 bc = bias[i];
-  const T m = K.b1 * m1[o] + ((T)1 - K.b1) * g;
-  const T v = K.b2 * m2[o] + ((T)1 - K.b2) * g * g;
+  T p = params[o], m = m1[o], v = m2[o];
+  adam_col<T>(p, m, v, g, K.lr[j], K.b1, K.b2, K.eps, (T)bc.x, (T)bc.y);
   m1[o] = m;
   m2[o] = v;
-  params[o] -= K.lr[j] * (m * (T)bc.x) / (Mth<T>::sqrt(v) * (T)bc.y + K.eps);
+  params[o] = p;
 }
 
 // The same update with one thread per row sweeping its 59 columns: the
@@ -92,11 +86,12 @@ __global__ void __launch_bounds__(256) k_adam_sweep(T* __restrict__ params, T* _
   for (int j = 0; j < kD; ++j) {
     const int64_t o = o0 + (int64_t)j * B;
     const T g = __builtin_nontemporal_load(gp + (int64_t)j * ld);
-    const T m = K.b1 * __builtin_nontemporal_load(m1 + o) + ((T)1 - K.b1) * g;
-    const T v = K.b2 * __builtin_nontemporal_load(m2 + o) + ((T)1 - K.b2) * g * g;
+    T p = __builtin_nontemporal_load(params + o);
+    T m = __builtin_nontemporal_load(m1 + o), v = __builtin_nontemporal_load(m2 + o);
+    adam_col<T>(p, m, v, g, K.lr[j], K.b1, K.b2, K.eps, (T)bc.x, (T)bc.y);
     __builtin_nontemporal_store(m, m1 + o);
     __builtin_nontemporal_store(v, m2 + o);
-    __builtin_nontemporal_store(params[o] - K.lr[j] * (m * (T)bc.x) / (Mth<T>::sqrt(v) * (T)bc.y + K.eps), params + o);
+    __builtin_nontemporal_store(p, params + o);
   }
 }
 

@@ -37,6 +37,25 @@ struct CamSet {
 template <typename T>
 CamSet<T> make_camset(const tide_camera* cams, int n);
 
+// Masked Adam constants (Appendix A, the masked update equation).
+template <typename T>
+struct AdamK {
+  T lr[kD];
+  T b1, b2, eps, kappa;
+};
+
+// One column of the masked Adam update of an active row: first and second
+// moments, then the parameter, with the row's bias corrections
+// bcx = 1/(1 - b1^t) and bcy = 1/sqrt(1 - b2^t).  The Adam sweep and the
+// backward with the update fused both apply this function, so the two give
+// the same bits.
+template <typename T>
+__device__ __forceinline__ void adam_col(T& p, T& m, T& v, T g, T lr, T b1, T b2, T eps, T bcx, T bcy) {
+  m = b1 * m + ((T)1 - b1) * g;
+  v = b2 * v + ((T)1 - b2) * g * g;
+  p = p - lr * (m * bcx) / (Mth<T>::sqrt(v) * bcy + eps);
+}
+
 // Tile rectangle with exact integer-vs-real comparisons: tile tx is covered
 // iff 16 tx - r <= u and 16 (tx+1) + r > u (same in y), clamped to the grid.
 // Returns false for an empty rectangle.
@@ -166,6 +185,9 @@ __device__ __forceinline__ float row_sum_to_15(float x) {
   x += dpp_f32<0x112, 0xF, true>(x);
   x += dpp_f32<0x114, 0xF, true>(x);
   x += dpp_f32<0x118, 0xF, true>(x);
+  // the sum is only read in lane 15; without this the compiler sinks the
+  // last add under that lane's branch and pays a DPP move plus an add for it
+  asm volatile("" : "+v"(x));
   return x;
 }
 __device__ __forceinline__ double row_sum_to_15(double x) {

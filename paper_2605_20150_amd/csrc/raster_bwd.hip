@@ -143,7 +143,10 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
         const T a_ok = ok ? alpha : (T)0;
         const T G_ok = okg ? G : (T)0;
         const T r_ok = okg ? araw : (T)0;
-        const T Tn = ok ? Tr[q] * Mth<T>::rcp_fast((T)1 - alpha) : Tr[q];
+        // a pixel the entry does not reach keeps its T: a_ok = 0 and the
+        // hardware reciprocal of 1 is exactly 1 (exact at powers of two), so
+        // no select is needed after the product
+        const T Tn = Tr[q] * Mth<T>::rcp_fast((T)1 - a_ok);
         Tr[q] = Tn;
         const T w = a_ok * Tn;
         a_r += w * g0[q]; a_g += w * g1[q]; a_b += w * g2[q];
