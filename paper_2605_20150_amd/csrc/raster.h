@@ -190,6 +190,21 @@ __device__ __forceinline__ float row_sum_to_15(float x) {
   asm volatile("" : "+v"(x));
   return x;
 }
+// Row sums of two quantities in one reduction.  Lane l holds x, its own
+// share of quantity (l & 1), and y, its share of the other one.  After the
+// exchange with the neighbour (quad_perm [1,0,3,2]) each lane holds a lane
+// pair's total of quantity (l & 1); the even and the odd lanes of the row
+// are then summed apart.  In lane 15, q1 is quantity 1's row sum and q0
+// quantity 0's (taken from lane 14).
+__device__ __forceinline__ void row_pair_sum_to_15(float x, float y, float& q0, float& q1) {
+  float z = x + dpp_f32<0xB1, 0xF, false>(y);
+  z += dpp_f32<0x112, 0xF, true>(z);
+  z += dpp_f32<0x114, 0xF, true>(z);
+  z += dpp_f32<0x118, 0xF, true>(z);
+  asm volatile("" : "+v"(z));
+  q1 = z;
+  q0 = dpp_f32<0x111, 0xF, true>(z);
+}
 __device__ __forceinline__ double row_sum_to_15(double x) {
 #pragma unroll
   for (int off = 1; off < 16; off <<= 1) {
@@ -197,6 +212,16 @@ __device__ __forceinline__ double row_sum_to_15(double x) {
     if ((__lane_id() & 15) >= off) x += y;
   }
   return x;
+}
+__device__ __forceinline__ void row_pair_sum_to_15(double x, double y, double& q0, double& q1) {
+  double z = x + __shfl_xor(y, 1, 16);
+#pragma unroll
+  for (int off = 2; off < 16; off <<= 1) {
+    const double w = __shfl_up(z, off, 16);
+    if ((__lane_id() & 15) >= off) z += w;
+  }
+  q1 = z;
+  q0 = __shfl_up(z, 1, 16);
 }
 
 

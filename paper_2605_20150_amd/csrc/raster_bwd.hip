@@ -23,8 +23,8 @@ struct __attribute__((aligned(sizeof(T)))) Rec9 {
 // starting from the background).  The per-pixel update is branch-free; the
 // four pixels of a lane are summed in registers, each row of 16 lanes is
 // reduced with DPP and the four row sums are parked in LDS; once a batch of
-// 32 entries is done, lane k adds entry k's four row sums and stores its
-// partial.  (Batches of 32 keep the parked sums at the LDS size that 64
+// 32 entries is done, lane k adds entry k's four row sums, applies the
+// entry's factors (opacity, conic) and stores its partial.  (Batches of 32 keep the parked sums at the LDS size that 64
 // entries with rows added in pairs took, so occupancy is unchanged, and each
 // taken entry saves the nine pair additions.)  Entries no pixel reaches get
 // zero partials.
@@ -46,7 +46,7 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
   const int py0 = ty * kTile + (lane >> 4);
   const T fxp = (T)px + (T)0.5;
   const int64_t HW = (int64_t)H * W;
-  // Pb = (colour behind the current entry) . dL/dpixel, per pixel: the only
+  // Pb = -(colour behind the current entry) . dL/dpixel, per pixel: the only
   // way the backward needs the colour behind, so it is carried as one scalar.
   T fyp[4], Tr[4], g0[4], g1[4], g2[4], Pb[4];
   uint32_t lst[4];
@@ -65,8 +65,17 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
     } else {
       Tr[q] = 1; lst[q] = 0; g0[q] = g1[q] = g2[q] = 0;
     }
-    Pb[q] = bg0 * g0[q] + bg1 * g1[q] + bg2 * g2[q];
+    Pb[q] = -(bg0 * g0[q] + bg1 * g1[q] + bg2 * g2[q]);
     maxl = lst[q] > maxl ? lst[q] : maxl;
+  }
+  // red and green are reduced together (row_pair_sum_to_15): an odd lane
+  // carries green in g0 and red in g1, so its first accumulator sums green
+  const bool odd = (lane & 1) != 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const T a = g0[q], b = g1[q];
+    g0[q] = odd ? b : a;
+    g1[q] = odd ? a : b;
   }
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
@@ -106,15 +115,10 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
       }
       const uint32_t pos = (uint32_t)(lo + k);
       const T v = s_v[k], Ch = s_Ch[k], op = s_o[k];
-      const T B = s_B[k], C = s_C[k];
       const T cr = s_r[k], cg = s_g[k], cb = s_b[k];
+      const T c0 = odd ? cg : cr, c1 = odd ? cr : cg;   // in the lane's g0/g1 order
       const T dx = fxp - s_u[k];
       const T adx2 = s_Ah[k] * dx * dx, bdx = s_Bh[k] * dx;
-      const T Bdx = B * dx, dx2 = dx * dx;
-      // a lane's four pixels share dx, so the conic and mean gradients are
-      // accumulated as moments of dp over dy and finished once per lane:
-      // d/dA = dx^2 S0, d/dB = dx S1, d/dC = S2 (times -1/2, -1, -1/2 below),
-      // d/du = A dx S0 + B S1, d/dv = B dx S0 + C S1.
       // G first: an entry no pixel takes (pass and before the pixel's last
       // contributor) leaves every pixel's state and the entry's partial at
       // zero, so the wave skips the rest.
@@ -131,7 +135,14 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
       const bool any_hit = __ballot(hit) != 0;
       if (lane == 0) s_hit[k] = any_hit ? 1u : 0u;
       if (!any_hit) continue;
-      T S0 = 0, S1 = 0, S2 = 0, a_o = 0, a_r = 0, a_g = 0, a_b = 0;
+      // Per pixel, t = dL/dalpha G is the opacity gradient's share and
+      // opacity t = dL/dpower (alpha below the clamp), so the power's
+      // moments over dy are summed without the opacity and the entry's
+      // factors are applied once, in the batch's store below.  A lane's four
+      // pixels share dx: d/du = op (A dx S0 + B S1), d/dv = op (B dx S0 + C S1),
+      // d/dA = -op dx^2 S0 / 2, d/dB = -op dx S1, d/dC = -op S2 / 2, with
+      // S0 = sum t, S1 = sum t dy, S2 = sum t dy^2.
+      T S0 = 0, S1 = 0, S2 = 0, a_0 = 0, a_1 = 0, a_b = 0;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const T dy = fyp[q] - v;
@@ -142,32 +153,32 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
         const bool okg = ok && araw < (T)0.99;   // alpha clamped at 0.99: no input dependence
         const T a_ok = ok ? alpha : (T)0;
         const T G_ok = okg ? G : (T)0;
-        const T r_ok = okg ? araw : (T)0;
         // a pixel the entry does not reach keeps its T: a_ok = 0 and the
         // hardware reciprocal of 1 is exactly 1 (exact at powers of two), so
         // no select is needed after the product
         const T Tn = Tr[q] * Mth<T>::rcp_fast((T)1 - a_ok);
         Tr[q] = Tn;
         const T w = a_ok * Tn;
-        a_r += w * g0[q]; a_g += w * g1[q]; a_b += w * g2[q];
-        const T e = (cr * g0[q] + cg * g1[q] + cb * g2[q]) - Pb[q];   // (c - behind) . dL/dpixel
+        a_0 += w * g0[q]; a_1 += w * g1[q]; a_b += w * g2[q];
+        const T e = c0 * g0[q] + (c1 * g1[q] + (cb * g2[q] + Pb[q]));   // (c - behind) . dL/dpixel
         const T dal = Tn * e;
-        Pb[q] += a_ok * e;
-        a_o += dal * G_ok;
-        const T dp = dal * r_ok;
-        const T dpdy = dp * dy;
-        S0 += dp; S1 += dpdy; S2 += dpdy * dy;
+        Pb[q] -= a_ok * e;
+        const T t = dal * G_ok;
+        S0 += t;
+        const T tdy = t * dy;
+        S1 += tdy; S2 += tdy * dy;
       }
-      T a_u = s_A[k] * dx * S0 + B * S1;
-      T a_v = Bdx * S0 + C * S1;
-      T a_A = dx2 * S0, a_B = dx * S1, a_C = S2;
-      a_u = row_sum_to_15(a_u); a_v = row_sum_to_15(a_v); a_A = row_sum_to_15(a_A);
-      a_B = row_sum_to_15(a_B); a_C = row_sum_to_15(a_C); a_o = row_sum_to_15(a_o);
-      a_r = row_sum_to_15(a_r); a_g = row_sum_to_15(a_g); a_b = row_sum_to_15(a_b);
+      T p1 = dx * S0;
+      T a_A = dx * p1, a_B = dx * S1, a_C = S2;
+      T q_r, q_g;
+      p1 = row_sum_to_15(p1); S1 = row_sum_to_15(S1); a_A = row_sum_to_15(a_A);
+      a_B = row_sum_to_15(a_B); a_C = row_sum_to_15(a_C); S0 = row_sum_to_15(S0);
+      row_pair_sum_to_15(a_0, a_1, q_r, q_g);
+      a_b = row_sum_to_15(a_b);
       if ((lane & 15) == 15) {
         T* S = s_part[k][lane >> 4];
-        S[0] = a_u; S[1] = a_v; S[2] = a_A; S[3] = a_B; S[4] = a_C;
-        S[5] = a_o; S[6] = a_r; S[7] = a_g; S[8] = a_b;
+        S[0] = p1; S[1] = S1; S[2] = a_A; S[3] = a_B; S[4] = a_C;
+        S[5] = S0; S[6] = q_r; S[7] = q_g; S[8] = a_b;
       }
     }
     __syncthreads();
@@ -177,10 +188,15 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
 #pragma unroll
         for (int m = 0; m < kG2; ++m)
           r.v[m] = (s_part[lane][0][m] + s_part[lane][1][m]) + (s_part[lane][2][m] + s_part[lane][3][m]);
-        // dpower/dA = -dx^2/2, dpower/dB = -dx dy, dpower/dC = -dy^2/2
-        r.v[2] *= (T)-0.5;
-        r.v[3] = -r.v[3];
-        r.v[4] *= (T)-0.5;
+        // dpower/du = A dx + B dy, dpower/dv = B dx + C dy, dpower/dA =
+        // -dx^2/2, dpower/dB = -dx dy, dpower/dC = -dy^2/2; dL/dpower =
+        // opacity t
+        const T op = s_o[lane], p1 = r.v[0], s1 = r.v[1];
+        r.v[0] = op * (s_A[lane] * p1 + s_B[lane] * s1);
+        r.v[1] = op * (s_B[lane] * p1 + s_C[lane] * s1);
+        r.v[2] *= (T)-0.5 * op;
+        r.v[3] *= -op;
+        r.v[4] *= (T)-0.5 * op;
       } else {
 #pragma unroll
         for (int m = 0; m < kG2; ++m) r.v[m] = 0;
