@@ -4,7 +4,7 @@ Workload (one step = the whole hot path over one batch): the aerial scene of
 1,000,000 Gaussians (200 blobs, sigma 5 m, over 500 x 500 m), 4 views of
 1920x1080 per batch on a 250 m-radius orbit at 150 m altitude; per step
 preprocess -> bin/sort -> composite -> loss (0.8 L1 + 0.2 D-SSIM) ->
-adjoint -> masked Adam, all through libtide.so.  Inputs are seeded and
+adjoint with the masked Adam update fused in, all through libtide.so.  Inputs are seeded and
 synthetic; targets are rendered once (untimed) from perturbed parameters and
 kept in HBM.
 
@@ -39,7 +39,7 @@ FLOPS_PER_FWD_VISIT = 21
 FLOPS_PER_BWD_VISIT = 52
 # Kernels bound by HBM: their algorithmic GB/s is reported as a fraction of
 # the 8 TB/s peak as well.
-HBM_BOUND = ("preprocess", "reduce_pairs", "adjoint", "adam", "loss_fwd", "loss_bwd")
+HBM_BOUND = ("preprocess", "reduce_pairs", "adjoint", "adam", "adjoint_adam", "loss_fwd", "loss_bwd")
 # HBM traffic per launch of the dominant kernel from two rocprofv3 counter
 # passes (FETCH_SIZE, WRITE_SIZE) of this benchmark, each scaled by what the
 # counter reads for a plain 1 GiB device copy (x1.9999 and x1.0000), and the
@@ -54,8 +54,12 @@ TRAFFIC = {"render_bwd": {"bytes": 3960.0e6, "sources": ["raster_bwd.hip", "rast
 # reported while the kernel's sources are those the counters were taken on.
 ISSUE = {"render_bwd": {"valu_wave_instr": 1083.45e6, "cycles_per_valu_per_simd": 3.61,
                         "sources": ["raster_bwd.hip", "raster.h"], "sha256_16": TRAFFIC["render_bwd"]["sha256_16"]}}
+# The step runs the backward's last stage and the masked Adam update as one
+# kernel (adjoint_adam); adjoint and adam are the same two stages as separate
+# kernels (gradient stored in between), timed in a pass of their own.
 KERNELS = ["preprocess", "compact_vis", "emit", "render_fwd", "loss_fwd", "loss_bwd", "render_bwd",
-           "reduce_pairs", "adjoint", "adam"]
+           "reduce_pairs", "adjoint_adam"]
+UNFUSED = ["adjoint", "adam"]
 
 
 def parse():
@@ -109,6 +113,8 @@ def algorithmic_bytes(kernel, n_pidx, n_kept, n_vis, n_inst, n_active, pixels, V
         return n_active * (236 + 236 + 8) + n_vis * 36
     if kernel == "adam":   # p, m, v read and written, g read
         return n_active * (7 * 236)
+    if kernel == "adjoint_adam":   # p, m, v read and written, step read and written, flags
+        return n_active * (6 * 236 + 8 + 8) + n_vis * 36
     if kernel in ("loss_fwd",):
         return pixels * 3 * (4 + 4 + 12)
     if kernel in ("loss_bwd",):
@@ -675,12 +681,15 @@ def resident_run(args, theta, cams, W, H, workload, with_cpu_baseline):
     grad = torch.empty((59, pool.n_pidx), dtype=torch.float32, device=dev)
     cam_batches = [cams[V * (b % used): V * (b % used) + V] for b in range(used)]
 
-    def step(b, stats=None):
+    def step(b, stats=None, fused=True):
         cb = cam_batches[b % used]
         proj, bins, fr = rast.forward(pool, cb)
         loss, dimg = rast.loss(fr.image, targets[b % used])
-        rast.backward(pool, cb, proj, bins, fr, dimg, grad=grad)
-        rast.adam(pool, proj, grad, cfg, spheres, dirty)
+        if fused:
+            rast.backward_adam(pool, cb, proj, bins, fr, dimg, cfg, spheres, dirty)
+        else:
+            rast.backward(pool, cb, proj, bins, fr, dimg, grad=grad)
+            rast.adam(pool, proj, grad, cfg, spheres, dirty)
         if stats is not None:
             # counters the kernels keep themselves: no extra reductions in the
             # timed region (the Gaussians kept by some camera are the active set)
@@ -690,15 +699,18 @@ def resident_run(args, theta, cams, W, H, workload, with_cpu_baseline):
     # materialised by one record) before any measured pass
     P = min(args.steps, 10)
     ev = {k: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(P)] for k in KERNELS}
-    handles = {k: [(C_void(a), C_void(z)) for a, z in ev[k]] for k in KERNELS}
-    names = {k: k.encode() for k in KERNELS}
+              for _ in range(P)] for k in KERNELS + UNFUSED}
+    handles = {k: [(C_void(a), C_void(z)) for a, z in ev[k]] for k in KERNELS + UNFUSED}
+    names = {k: k.encode() for k in KERNELS + UNFUSED}
     # warm-up steps run what the measured passes run (events armed, the
     # per-step statistics gathered), so first-use allocations happen here
     for b in range(args.warmup):
         for k in KERNELS:
             lib.tide_timer_arm(names[k], handles[k][0][0], handles[k][0][1])
         step(b, [])
+    for k in UNFUSED:
+        lib.tide_timer_arm(names[k], handles[k][0][0], handles[k][0][1])
+    step(0, [], fused=False)
     torch.cuda.synchronize()
 
     # per-kernel times: P steps (the first P batches of the timed region)
@@ -709,9 +721,14 @@ def resident_run(args, theta, cams, W, H, workload, with_cpu_baseline):
         for k in KERNELS:
             lib.tide_timer_arm(names[k], handles[k][s][0], handles[k][s][1])
         step(args.warmup + s, [])
+    # the same steps with the gradient stored between the backward and Adam
+    for s in range(P):
+        for k in UNFUSED:
+            lib.tide_timer_arm(names[k], handles[k][s][0], handles[k][s][1])
+        step(args.warmup + s, [], fused=False)
     torch.cuda.synchronize()
     lib.tide_timer_clear()
-    kern_ms = {k: float(np.mean([a.elapsed_time(z) for a, z in ev[k]])) for k in KERNELS}
+    kern_ms = {k: float(np.mean([a.elapsed_time(z) for a, z in ev[k]])) for k in KERNELS + UNFUSED}
     dominant = max(KERNELS, key=lambda k: kern_ms[k])
     ev_dom = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(args.steps)]
@@ -752,7 +769,7 @@ def resident_run(args, theta, cams, W, H, workload, with_cpu_baseline):
     iters = args.steps / wall
 
     kernels = {}
-    for k in KERNELS:
+    for k in KERNELS + UNFUSED:
         by = algorithmic_bytes(k, pool.n_pidx, n_kept, n_vis, n_inst, n_active, pixels, V)
         kernels[k] = {"ms": round(kern_ms[k], 4),
                       "alg_GBps": round(by / (kern_ms[k] * 1e-3) / 1e9, 1) if kern_ms[k] > 0 else None}
@@ -791,7 +808,9 @@ def resident_run(args, theta, cams, W, H, workload, with_cpu_baseline):
                      "fwd_visits": int(fwd_visits), "bwd_visits": int(bwd_visits)},
         "kernels": kernels,
         "kernels_note": f"ms of the dominant kernel from its events in the timed region; the others from an "
-                        f"untimed pass of {P} steps with every kernel's events armed",
+                        f"untimed pass of {P} steps with every kernel's events armed; adjoint and adam from "
+                        f"{P} further steps that store the gradient between the backward and the update "
+                        f"(the timed steps run them as one kernel, adjoint_adam)",
         "stall_s_per_iter": None,
         "roofline": roof,
     }

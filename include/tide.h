@@ -298,6 +298,27 @@ tide_status tide_adam_sparse(tide_pool* pool, const tide_proj* proj, const void*
                              void* stream);
 
 /* ------------------------------------------------------------------------
+ * tide_render_bwd followed by tide_adam_sparse without the gradient in
+ * between: the training step's backward and optimiser (Sec. 3.2, Stage 3;
+ * Appendix A, masked update equation).  The last backward stage hands each
+ * active row's 59 gradient values straight to that row's masked Adam update
+ * (step += 1, moments, parameters), then the dirty marks and the sphere
+ * refresh run as in tide_adam_sparse.  The pool's parameters, moments and
+ * step counters end bit-identical to tide_render_bwd then tide_adam_sparse
+ * on the same inputs; no gradient is stored.
+ *   arguments  as tide_render_bwd (without grad) and tide_adam_sparse
+ *              (without grad and its workspace)
+ *   ws         tide_render_bwd_ws_bytes(bins, dtype) bytes
+ * Errors as the two calls it replaces; nothing is launched on an argument
+ * error.
+ * ---------------------------------------------------------------------- */
+tide_status tide_render_bwd_adam(tide_pool* pool, const tide_camera* cams, int32_t n_cams,
+                                 const tide_proj* proj, const tide_bins* bins,
+                                 const tide_frame* frame, const float* bg, const void* d_dimage,
+                                 const tide_adam_cfg* cfg, float* spheres, uint8_t* dirty,
+                                 int64_t n_blocks, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Out-of-core block tier (Sec. 3.3 to 3.5; Alg. 1).  A host object owns the
  * SSD log store (an immutable base segment plus append-only patch segments
  * and Index[k] = (file_id, offset, size, version), Sec. 3.4), a host LRU
@@ -597,7 +618,8 @@ tide_status tide_block_sphere(const float* params, int64_t ld, int64_t rows, dou
  * kernel records ev_start immediately before and ev_stop immediately after
  * it, on the launch stream, until tide_timer_clear().  Kernel names:
  * "preprocess", "compact_vis", "radix_scatter", "emit", "render_fwd",
- * "loss_fwd", "loss_bwd", "render_bwd", "reduce_pairs", "adjoint", "adam".
+ * "loss_fwd", "loss_bwd", "render_bwd", "reduce_pairs", "adjoint", "adam",
+ * "adjoint_adam".
  * At most 16 names are armed at once; re-arming a name replaces its events.
  * The events are not owned by the library.
  * ---------------------------------------------------------------------- */

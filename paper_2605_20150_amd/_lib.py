@@ -125,6 +125,9 @@ SIGNATURES = {
     "tide_adam_ws_bytes": (C.c_size_t, [C.c_int64]),
     "tide_adam_sparse": (C.c_int32, [_P(tide_pool), _P(tide_proj), _vp, C.c_int64, _P(tide_adam_cfg), _vp, _vp,
                                      C.c_int64, _vp, C.c_size_t, _vp]),
+    "tide_render_bwd_adam": (C.c_int32, [_P(tide_pool), _P(tide_camera), C.c_int32, _P(tide_proj), _P(tide_bins),
+                                         _P(tide_frame), _P(C.c_float), _vp, _P(tide_adam_cfg), _vp, _vp, C.c_int64,
+                                         _vp, C.c_size_t, _vp]),
     "tide_timer_arm": (C.c_int32, [C.c_char_p, _vp, _vp]),
     "tide_residency_create": (C.c_int32, [_P(tide_store_cfg), _P(tide_pool), _vp, _vp, _P(_vp)]),
     "tide_residency_destroy": (C.c_int32, [_vp]),

@@ -24,11 +24,9 @@ __global__ void __launch_bounds__(256) k_adam_rows(uint32_t* __restrict__ step, 
   if (i >= n_pidx || !active[i]) return;
   const int64_t k = i / B;
   const int32_t row = (int32_t)(i - k * B);
-  const int64_t si = (int64_t)order[k] * B + row;
-  const uint32_t t = step[si] + 1u;
-  step[si] = t;
-  const double c1 = 1.0 - exp2((double)t * lb1), c2 = 1.0 - exp2((double)t * lb2);
-  bias[i] = make_double2(1.0 / c1, 1.0 / sqrt(c2));
+  double bcx, bcy;
+  adam_step_bias<double>(step + (int64_t)order[k] * B + row, lb1, lb2, bcx, bcy);
+  bias[i] = make_double2(bcx, bcy);
 }
 
 template <typename T>
@@ -77,18 +75,15 @@ __global__ void __launch_bounds__(256) k_adam_sweep(T* __restrict__ params, T* _
   const T* gp = grad + (int64_t)act_idx[i];
   // the row's step and bias corrections (what k_adam_rows computes for the
   // column-grid update), in the same precision
-  const int64_t si = (int64_t)order[k] * B + row;
-  const uint32_t t = step[si] + 1u;
-  step[si] = t;
-  const double c1 = 1.0 - exp2((double)t * lb1), c2 = 1.0 - exp2((double)t * lb2);
-  const float2 bc = make_float2((float)(1.0 / c1), (float)(1.0 / sqrt(c2)));
+  T bcx, bcy;
+  adam_step_bias<T>(step + (int64_t)order[k] * B + row, lb1, lb2, bcx, bcy);
 #pragma unroll 4
   for (int j = 0; j < kD; ++j) {
     const int64_t o = o0 + (int64_t)j * B;
     const T g = __builtin_nontemporal_load(gp + (int64_t)j * ld);
     T p = __builtin_nontemporal_load(params + o);
     T m = __builtin_nontemporal_load(m1 + o), v = __builtin_nontemporal_load(m2 + o);
-    adam_col<T>(p, m, v, g, K.lr[j], K.b1, K.b2, K.eps, (T)bc.x, (T)bc.y);
+    adam_col<T>(p, m, v, g, K.lr[j], K.b1, K.b2, K.eps, bcx, bcy);
     __builtin_nontemporal_store(m, m1 + o);
     __builtin_nontemporal_store(v, m2 + o);
     __builtin_nontemporal_store(p, params + o);
@@ -148,6 +143,20 @@ __global__ void __launch_bounds__(256) k_adam_bounds(const T* __restrict__ param
   }
 }
 
+void launch_adam_bounds(const tide_pool* pool, const tide_proj* proj, float kappa, float* spheres, uint8_t* dirty,
+                        hipStream_t st) {
+  const int64_t n = proj->n_pidx;
+  if (n == 0 || (!spheres && !dirty)) return;
+  // workgroups of kBoundRows indices, never straddling a block
+  const uint32_t gb = (uint32_t)((int64_t)pool->n_order * ceil_div(pool->block_rows, kBoundRows));
+  if (pool->dtype == TIDE_F32)
+    hipLaunchKernelGGL(k_adam_bounds<float>, dim3(gb), dim3(256), 0, st, (const float*)pool->params, pool->order,
+                       pool->slot_block, pool->block_rows, n, proj->active, kappa, spheres, dirty);
+  else
+    hipLaunchKernelGGL(k_adam_bounds<double>, dim3(gb), dim3(256), 0, st, (const double*)pool->params, pool->order,
+                       pool->slot_block, pool->block_rows, n, proj->active, kappa, spheres, dirty);
+}
+
 }  // namespace tide
 
 using namespace tide;
@@ -172,38 +181,27 @@ extern "C" tide_status tide_adam_sparse(tide_pool* pool, const tide_proj* proj, 
   const int64_t n = proj->n_pidx;
   if (n == 0) return TIDE_OK;
   const uint32_t gx = (uint32_t)ceil_div(n, 256);
-  // bound workgroups: kBoundRows indices each, never straddling a block
-  const uint32_t gb = (uint32_t)((int64_t)pool->n_order * ceil_div(pool->block_rows, kBoundRows));
   double2* bias = (double2*)ws;
   const double lb1 = std::log2((double)cfg->beta1), lb2 = std::log2((double)cfg->beta2);
   if (pool->dtype == TIDE_F32) {
-    AdamK<float> K;
-    for (int j = 0; j < kD; ++j) K.lr[j] = cfg->lr[j];
-    K.b1 = cfg->beta1; K.b2 = cfg->beta2; K.eps = cfg->eps; K.kappa = cfg->kappa;
+    const AdamK<float> K = make_adam_k<float>(cfg);
     // the row sweep takes the step and bias corrections itself
     TIDE_TIMED("adam", st, hipLaunchKernelGGL(k_adam_sweep<float>, dim3(gx), dim3(256), 0, st,
                                               (float*)pool->params, (float*)pool->exp_avg, (float*)pool->exp_avg_sq,
                                               pool->step, pool->order, pool->block_rows, n, proj->active,
                                               proj->act_idx, (const float*)grad, grad_ld, K, lb1, lb2));
-    if (spheres || dirty)
-      hipLaunchKernelGGL(k_adam_bounds<float>, dim3(gb), dim3(256), 0, st, (const float*)pool->params, pool->order,
-                         pool->slot_block, pool->block_rows, n, proj->active, cfg->kappa, spheres, dirty);
   } else {
     hipLaunchKernelGGL(k_adam_rows, dim3(gx), dim3(256), 0, st, pool->step, pool->order, pool->block_rows, n,
                        proj->active, lb1, lb2, bias);
     TIDE_LAUNCH_CHECK("k_adam_rows");
-    AdamK<double> K;
-    for (int j = 0; j < kD; ++j) K.lr[j] = cfg->lr[j];
-    K.b1 = cfg->beta1; K.b2 = cfg->beta2; K.eps = cfg->eps; K.kappa = cfg->kappa;
+    const AdamK<double> K = make_adam_k<double>(cfg);
     TIDE_TIMED("adam", st, hipLaunchKernelGGL(k_adam_cols<double>, dim3(gx, kD), dim3(256), 0, st,
                                               (double*)pool->params, (double*)pool->exp_avg,
                                               (double*)pool->exp_avg_sq, pool->order, pool->block_rows, n,
                                               proj->active, proj->act_idx, (const double*)grad, grad_ld, K, bias));
-    if (spheres || dirty)
-      hipLaunchKernelGGL(k_adam_bounds<double>, dim3(gb), dim3(256), 0, st, (const double*)pool->params,
-                         pool->order, pool->slot_block, pool->block_rows, n, proj->active, cfg->kappa, spheres,
-                         dirty);
   }
   TIDE_LAUNCH_CHECK("k_adam");
+  launch_adam_bounds(pool, proj, cfg->kappa, spheres, dirty, st);
+  TIDE_LAUNCH_CHECK("k_adam_bounds");
   return TIDE_OK;
 }

@@ -56,6 +56,31 @@ __device__ __forceinline__ void adam_col(T& p, T& m, T& v, T g, T lr, T b1, T b2
   p = p - lr * (m * bcx) / (Mth<T>::sqrt(v) * bcy + eps);
 }
 
+// A row's step counter += 1 and its bias corrections 1/(1 - b1^t),
+// 1/sqrt(1 - b2^t), evaluated in double precision (lb1 = log2 b1,
+// lb2 = log2 b2) and rounded to T.
+template <typename T>
+__device__ __forceinline__ void adam_step_bias(uint32_t* step, double lb1, double lb2, T& bcx, T& bcy) {
+  const uint32_t t = *step + 1u;
+  *step = t;
+  const double c1 = 1.0 - exp2((double)t * lb1), c2 = 1.0 - exp2((double)t * lb2);
+  bcx = (T)(1.0 / c1);
+  bcy = (T)(1.0 / sqrt(c2));
+}
+
+template <typename T>
+inline AdamK<T> make_adam_k(const tide_adam_cfg* cfg) {
+  AdamK<T> K;
+  for (int j = 0; j < kD; ++j) K.lr[j] = cfg->lr[j];
+  K.b1 = cfg->beta1; K.b2 = cfg->beta2; K.eps = cfg->eps; K.kappa = cfg->kappa;
+  return K;
+}
+
+// The dirty marks and the bounding-sphere refresh that follow an Adam update
+// of the active rows (either pointer may be null).
+void launch_adam_bounds(const tide_pool* pool, const tide_proj* proj, float kappa, float* spheres, uint8_t* dirty,
+                        hipStream_t st);
+
 // Tile rectangle with exact integer-vs-real comparisons: tile tx is covered
 // iff 16 tx - r <= u and 16 (tx+1) + r > u (same in y), clamped to the grid.
 // Returns false for an empty rectangle.
@@ -123,18 +148,40 @@ struct Ex<double> {
 
 // Opacity-weighted Gaussian of one list entry at one pixel, shared by the
 // forward and backward kernels so that both take identical skip decisions.
+// A pixel row at +infinity is reached by no entry: the power is -infinity
+// (G = 0) or NaN (both tests fail).
 // The per-entry terms are prepared once per lane column: with the scaled
 // conic Ah = -A k/2, Bh = -B k, Ch = -C k/2 (k = Ex<T>::k) and dx the pixel
 // offset, adx2 = Ah dx dx and bdx = Bh dx; then power = adx2 + bdx dy +
 // Ch dy dy.  ok is false when the entry is skipped (power > 0 or
 // alpha < 1/255); G = exp(power / k), araw = opacity G, alpha = min(0.99, araw).
 template <typename T>
-__device__ __forceinline__ bool entry_alpha(T adx2, T bdx, T Ch, T op, T dy, T& G, T& araw, T& alpha) {
+__device__ __forceinline__ void entry_alpha_tests(T adx2, T bdx, T Ch, T op, T dy, T& G, T& araw, T& alpha,
+                                                  bool& in_power, bool& in_alpha) {
   const T power = adx2 + dy * (bdx + Ch * dy);
   G = Ex<T>::eval(power);
   araw = op * G;
   alpha = araw < (T)0.99 ? araw : (T)0.99;
-  return power <= (T)0 && alpha >= (T)(1.0 / 255.0);
+  in_power = power <= (T)0;
+  // alpha >= 1/255 exactly when araw >= 1/255 (0.99 > 1/255; a NaN araw
+  // comes from a NaN power, which fails in_power)
+  in_alpha = araw >= (T)(1.0 / 255.0);
+}
+// alpha = below ? araw : 0.99 (below = araw < 0.99) as a select on the bit
+// patterns: the same value as min(araw, 0.99), without the canonicalisation
+// a floating-point minimum of a reused value costs.
+__device__ __forceinline__ float alpha_clamped(float araw, bool below) {
+  return __uint_as_float(below ? __float_as_uint(araw) : __float_as_uint(0.99f));
+}
+__device__ __forceinline__ double alpha_clamped(double araw, bool below) {
+  return __longlong_as_double(below ? __double_as_longlong(araw) : __double_as_longlong(0.99));
+}
+
+template <typename T>
+__device__ __forceinline__ bool entry_alpha(T adx2, T bdx, T Ch, T op, T dy, T& G, T& araw, T& alpha) {
+  bool in_power, in_alpha;
+  entry_alpha_tests<T>(adx2, bdx, Ch, op, dy, G, araw, alpha, in_power, in_alpha);
+  return in_power && in_alpha;
 }
 
 // Tile-level test of one list entry, conservative: false only when no pixel

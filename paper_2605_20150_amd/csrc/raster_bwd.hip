@@ -92,12 +92,13 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
   __shared__ T s_u[64], s_v[64], s_Ah[64], s_Bh[64], s_Ch[64], s_A[64], s_B[64], s_C[64], s_o[64], s_r[64],
       s_g[64], s_b[64];
   __shared__ T s_part[32][4][kG2];   // per entry, the sums of the four rows
-  __shared__ uint32_t s_hit[64], s_take[64];
+
   const T ks = (T)Ex<T>::k;
   for (int32_t hi = (int32_t)maxl; hi > 0; hi -= 32) {
     const int32_t lo = hi - 32 > 0 ? hi - 32 : 0;
     const int32_t n = hi - lo;
     uint32_t my_e = 0;
+    bool may = false;
     if (lane < n) {
       my_e = inst_e[start + lo + lane];
       const T* q = rec + (int64_t)inst_rec[my_e] * kRec;
@@ -105,14 +106,15 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
       s_A[lane] = q[2]; s_B[lane] = q[3]; s_C[lane] = q[4];
       s_Ah[lane] = (T)-0.5 * ks * q[2]; s_Bh[lane] = -ks * q[3]; s_Ch[lane] = (T)-0.5 * ks * q[4];
       s_o[lane] = q[5]; s_r[lane] = q[6]; s_g[lane] = q[7]; s_b[lane] = q[8];
-      s_take[lane] = tile_may_take<T>(q[0], q[1], q[2], q[3], q[4], q[5], tx, ty) ? 1u : 0u;
+      may = tile_may_take<T>(q[0], q[1], q[2], q[3], q[4], q[5], tx, ty);
     }
+    // entries some pixel centre of the tile may take (the forward's test),
+    // walked from the back; hit: the entries some pixel took
+    uint64_t rest = __ballot(may), hit = 0;
     __syncthreads();
-    for (int k = n - 1; k >= 0; --k) {
-      if (!s_take[k]) {   // no pixel centre of the tile takes the entry (forward's test)
-        if (lane == 0) s_hit[k] = 0u;
-        continue;
-      }
+    while (rest != 0) {
+      const int k = 63 - __builtin_clzll(rest);
+      rest &= ~(1ull << k);
       const uint32_t pos = (uint32_t)(lo + k);
       const T v = s_v[k], Ch = s_Ch[k], op = s_o[k];
       const T cr = s_r[k], cg = s_g[k], cb = s_b[k];
@@ -122,19 +124,22 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
       // G first: an entry no pixel takes (pass and before the pixel's last
       // contributor) leaves every pixel's state and the entry's partial at
       // zero, so the wave skips the rest.
+      // (each comparison balloted on its own: see the forward)
       T Gq[4];
       bool okq[4];
-      bool hit = false;
+      uint64_t qm[4], hit_m = 0;   // per pixel row q, the lanes whose pixel takes the entry
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         T araw, alpha;
-        const bool pass = entry_alpha<T>(adx2, bdx, Ch, op, fyp[q] - v, Gq[q], araw, alpha);
-        okq[q] = pass && pos < lst[q];
-        hit = hit || okq[q];
+        bool in_power, in_alpha;
+        entry_alpha_tests<T>(adx2, bdx, Ch, op, fyp[q] - v, Gq[q], araw, alpha, in_power, in_alpha);
+        const bool before_last = pos < lst[q];
+        okq[q] = in_power && in_alpha && before_last;
+        qm[q] = __ballot(in_power) & __ballot(in_alpha) & __ballot(before_last);
+        hit_m |= qm[q];
       }
-      const bool any_hit = __ballot(hit) != 0;
-      if (lane == 0) s_hit[k] = any_hit ? 1u : 0u;
-      if (!any_hit) continue;
+      if (hit_m == 0) continue;
+      hit |= 1ull << k;
       // Per pixel, t = dL/dalpha G is the opacity gradient's share and
       // opacity t = dL/dpower (alpha below the clamp), so the power's
       // moments over dy are summed without the opacity and the entry's
@@ -142,15 +147,20 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
       // pixels share dx: d/du = op (A dx S0 + B S1), d/dv = op (B dx S0 + C S1),
       // d/dA = -op dx^2 S0 / 2, d/dB = -op dx S1, d/dC = -op S2 / 2, with
       // S0 = sum t, S1 = sum t dy, S2 = sum t dy^2.
+      // A pixel row (q: rows q*4 .. q*4+3 of the tile, one per lane row) in
+      // which no pixel takes the entry is passed over: its update would
+      // leave every state as it is (a_ok = 0, t = 0).
       T S0 = 0, S1 = 0, S2 = 0, a_0 = 0, a_1 = 0, a_b = 0;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
+        if (qm[q] == 0) continue;
         const T dy = fyp[q] - v;
         const T G = Gq[q];
         const T araw = op * G;
-        const T alpha = araw < (T)0.99 ? araw : (T)0.99;
+        const bool below = araw < (T)0.99;
+        const T alpha = alpha_clamped(araw, below);
         const bool ok = okq[q];
-        const bool okg = ok && araw < (T)0.99;   // alpha clamped at 0.99: no input dependence
+        const bool okg = ok && below;   // alpha clamped at 0.99: no input dependence
         const T a_ok = ok ? alpha : (T)0;
         const T G_ok = okg ? G : (T)0;
         // a pixel the entry does not reach keeps its T: a_ok = 0 and the
@@ -184,7 +194,7 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
     __syncthreads();
     if (lane < n) {
       Rec9<T> r;
-      if (s_hit[lane]) {
+      if ((hit >> lane) & 1u) {
 #pragma unroll
         for (int m = 0; m < kG2; ++m)
           r.v[m] = (s_part[lane][0][m] + s_part[lane][1][m]) + (s_part[lane][2][m] + s_part[lane][3][m]);
@@ -437,25 +447,61 @@ __device__ __forceinline__ void adj_colour_cam(const ShK<T>& K, const DevCam<T>&
 // and SH basis are recomputed per channel), cameras in order.  91 VGPRs and
 // 32 KB of LDS per 256 threads: five waves per SIMD, against two when the
 // 48 SH sums were held together.
+// With kAdam the row's gradient is not stored: each column goes straight
+// into the masked Adam update of that row (the moments and the parameter,
+// the step counter and bias corrections first), with the same arithmetic as
+// the Adam sweep over a stored gradient, so both give the same bits.  A
+// column's parameter is read before it is written and every other access
+// of the row is by this thread; the means are updated last, as the colour
+// pass reads them.
 template <typename T>
-__global__ void __launch_bounds__(256) k_adjoint(const T* __restrict__ params, const int32_t* __restrict__ order,
-                                                 int32_t B, int64_t n_pidx, CamSet<T> cs,
-                                                 const uint32_t* __restrict__ tt, const uint32_t* __restrict__ active,
-                                                 const uint32_t* __restrict__ act_idx, const T* __restrict__ g2d,
-                                                 T* __restrict__ grad, int64_t ld) {
+struct AdamRows {
+  T* m1;
+  T* m2;
+  uint32_t* step;
+  AdamK<T> K;
+  double lb1, lb2;
+};
+
+template <typename T, bool kAdam>
+__device__ __forceinline__ void adjoint_row(T* params, const int32_t* __restrict__ order, int32_t B, int64_t n_pidx,
+                                            const CamSet<T>& cs, const uint32_t* __restrict__ tt,
+                                            const uint32_t* __restrict__ active, const uint32_t* __restrict__ act_idx,
+                                            const T* __restrict__ g2d, T* __restrict__ grad, int64_t ld,
+                                            const AdamRows<T>& ad) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_pidx || !active[i]) return;
   const int64_t k = i / B;
   const int32_t row = (int32_t)(i - k * B);
   const int32_t slot = order[k];
-  const T* P = params + (int64_t)slot * kD * B + row;
+  T* const P = params + (int64_t)slot * kD * B + row;
   const int V = cs.n;
   uint32_t keepm = 0;
 #pragma unroll 1
   for (int c = 0; c < V; ++c) keepm |= (tt[(int64_t)c * n_pidx + i] != 0 ? 1u : 0u) << c;
+  T bcx = 0, bcy = 0;
+  if constexpr (kAdam) adam_step_bias<T>(ad.step + (int64_t)slot * B + row, ad.lb1, ad.lb2, bcx, bcy);
+  // column j of the row's gradient, with the column's parameter value p
+  auto put = [&](int j, T g, T p) {
+    if constexpr (kAdam) {
+      // the update sees g and p as the sweep does, as values from memory: the
+      // compiler may not fuse the update's products into the arithmetic
+      // that made them
+      asm volatile("" : "+v"(g), "+v"(p));
+      const int64_t o = (int64_t)j * B;
+      T m = __builtin_nontemporal_load(ad.m1 + (int64_t)slot * kD * B + row + o);
+      T v = __builtin_nontemporal_load(ad.m2 + (int64_t)slot * kD * B + row + o);
+      adam_col<T>(p, m, v, g, ad.K.lr[j], ad.K.b1, ad.K.b2, ad.K.eps, bcx, bcy);
+      __builtin_nontemporal_store(m, ad.m1 + (int64_t)slot * kD * B + row + o);
+      __builtin_nontemporal_store(v, ad.m2 + (int64_t)slot * kD * B + row + o);
+      __builtin_nontemporal_store(p, P + o);
+    } else {
+      grad[(int64_t)act_idx[i] + (int64_t)j * ld] = g;
+    }
+  };
   const T mu0 = P[0], mu1 = P[B], mu2 = P[2 * (int64_t)B];
-  const T s0 = Mth<T>::exp(P[3 * (int64_t)B]), s1 = Mth<T>::exp(P[4 * (int64_t)B]),
-          s2 = Mth<T>::exp(P[5 * (int64_t)B]);
+  const T ls0 = P[3 * (int64_t)B], ls1 = P[4 * (int64_t)B], ls2 = P[5 * (int64_t)B];
+  const T s0 = Mth<T>::exp(ls0), s1 = Mth<T>::exp(ls1), s2 = Mth<T>::exp(ls2);
   const T qw0 = P[6 * (int64_t)B], qx0 = P[7 * (int64_t)B], qy0 = P[8 * (int64_t)B], qz0 = P[9 * (int64_t)B];
   const T qn = Mth<T>::sqrt(qw0 * qw0 + qx0 * qx0 + qy0 * qy0 + qz0 * qz0);
   const T iq = (T)1 / qn;
@@ -488,7 +534,6 @@ __global__ void __launch_bounds__(256) k_adjoint(const T* __restrict__ params, c
     s_q[c][0][tx] = r.v[5]; s_q[c][1][tx] = r.v[6]; s_q[c][2][tx] = r.v[7]; s_q[c][3][tx] = r.v[8];
     adj_geom_cam<T>(cs.c[c], mu0, mu1, mu2, Sg, r.v[0], r.v[1], r.v[2], r.v[3], r.v[4], dSig, dmu0, dmu1, dmu2);
   }
-  T* G = grad + act_idx[i];
   // Sigma = M M^T: dM = 2 dSig M (dSig symmetric)
   T dM[9];
 #pragma unroll
@@ -511,18 +556,19 @@ __global__ void __launch_bounds__(256) k_adjoint(const T* __restrict__ params, c
   dq[2] = 2 * (-2 * y * g9[0] + x * g9[1] + w * g9[2] + x * g9[3] + z * g9[5] - w * g9[6] + z * g9[7] - 2 * y * g9[8]);
   dq[3] = 2 * (-2 * z * g9[0] - w * g9[1] + x * g9[2] + w * g9[3] - 2 * z * g9[4] + y * g9[5] + x * g9[6] + y * g9[7]);
   const T dqq = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
-  G[3 * ld] = gls[0]; G[4 * ld] = gls[1]; G[5 * ld] = gls[2];
-  G[6 * ld] = (dq[0] - dqq * w) * iq;
-  G[7 * ld] = (dq[1] - dqq * x) * iq;
-  G[8 * ld] = (dq[2] - dqq * y) * iq;
-  G[9 * ld] = (dq[3] - dqq * z) * iq;
+  put(3, gls[0], ls0); put(4, gls[1], ls1); put(5, gls[2], ls2);
+  put(6, (dq[0] - dqq * w) * iq, qw0);
+  put(7, (dq[1] - dqq * x) * iq, qx0);
+  put(8, (dq[2] - dqq * y) * iq, qy0);
+  put(9, (dq[3] - dqq * z) * iq, qz0);
   // opacity
-  const T op = (T)1 / ((T)1 + Mth<T>::exp(-P[10 * (int64_t)B]));
+  const T logit = P[10 * (int64_t)B];
+  const T op = (T)1 / ((T)1 + Mth<T>::exp(-logit));
   T dlogit = 0;
 #pragma unroll 1
   for (int c = 0; c < V; ++c)
     if ((keepm >> c) & 1u) dlogit += s_q[c][0][tx] * op * ((T)1 - op);
-  G[10 * ld] = dlogit;
+  put(10, dlogit, logit);
   // colour, one channel at a time
 #pragma unroll 1
   for (int ch = 0; ch < 3; ++ch) {
@@ -539,17 +585,53 @@ __global__ void __launch_bounds__(256) k_adjoint(const T* __restrict__ params, c
       adj_colour_cam<T>(cs.sh, cs.c[c], mu0, mu1, mu2, sh, gcol, gs, dmu0, dmu1, dmu2);
     }
 #pragma unroll
-    for (int m = 0; m < 16; ++m) G[(int64_t)(11 + 3 * m + ch) * ld] = gs[m];
+    for (int m = 0; m < 16; ++m) put(11 + 3 * m + ch, gs[m], sh[m]);
   }
-  G[0] = dmu0; G[ld] = dmu1; G[2 * ld] = dmu2;
+  put(0, dmu0, mu0); put(1, dmu1, mu1); put(2, dmu2, mu2);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_adjoint(T* params, const int32_t* __restrict__ order, int32_t B,
+                                                 int64_t n_pidx, CamSet<T> cs, const uint32_t* __restrict__ tt,
+                                                 const uint32_t* __restrict__ active,
+                                                 const uint32_t* __restrict__ act_idx, const T* __restrict__ g2d,
+                                                 T* __restrict__ grad, int64_t ld) {
+  adjoint_row<T, false>(params, order, B, n_pidx, cs, tt, active, act_idx, g2d, grad, ld, AdamRows<T>{});
+}
+
+// The fused variant holds the Adam state of the row besides the adjoint's:
+// at most 128 registers keep four waves per SIMD.
+template <typename T>
+__global__ void __launch_bounds__(256, 4) k_adjoint_adam(T* params, const int32_t* __restrict__ order, int32_t B,
+                                                         int64_t n_pidx, CamSet<T> cs,
+                                                         const uint32_t* __restrict__ tt,
+                                                         const uint32_t* __restrict__ active,
+                                                         const uint32_t* __restrict__ act_idx,
+                                                         const T* __restrict__ g2d, AdamRows<T> ad) {
+  adjoint_row<T, true>(params, order, B, n_pidx, cs, tt, active, act_idx, g2d, nullptr, 0, ad);
 }
 
 template <typename T>
 static void launch_adjoint(const tide_pool* pool, const tide_proj* proj, const CamSet<T>& cs, const T* g2d,
                            T* grad, int64_t ld, hipStream_t st) {
   hipLaunchKernelGGL(k_adjoint<T>, dim3((uint32_t)ceil_div(proj->n_pidx, 256)), dim3(256), 0, st,
-                     (const T*)pool->params, pool->order, pool->block_rows, proj->n_pidx, cs, proj->tiles_touched,
+                     (T*)pool->params, pool->order, pool->block_rows, proj->n_pidx, cs, proj->tiles_touched,
                      proj->active, proj->act_idx, g2d, grad, ld);
+}
+
+template <typename T>
+static void launch_adjoint_adam(const tide_pool* pool, const tide_proj* proj, const CamSet<T>& cs, const T* g2d,
+                                const tide_adam_cfg* cfg, hipStream_t st) {
+  AdamRows<T> ad;
+  ad.m1 = (T*)pool->exp_avg;
+  ad.m2 = (T*)pool->exp_avg_sq;
+  ad.step = pool->step;
+  ad.K = make_adam_k<T>(cfg);
+  ad.lb1 = std::log2((double)cfg->beta1);
+  ad.lb2 = std::log2((double)cfg->beta2);
+  hipLaunchKernelGGL(k_adjoint_adam<T>, dim3((uint32_t)ceil_div(proj->n_pidx, 256)), dim3(256), 0, st,
+                     (T*)pool->params, pool->order, pool->block_rows, proj->n_pidx, cs, proj->tiles_touched,
+                     proj->active, proj->act_idx, g2d, ad);
 }
 
 template <typename T>
@@ -566,22 +648,12 @@ extern "C" size_t tide_render_bwd_ws_bytes(const tide_bins* bins, int32_t dtype)
          align_up((size_t)kG2 * bins->n_cams * bins->n_pidx * es) + 256;
 }
 
-extern "C" tide_status tide_render_bwd(const tide_pool* pool, const tide_camera* cams, int32_t n_cams,
-                                       const tide_proj* proj, const tide_bins* bins, const tide_frame* fr,
-                                       const float* bg, const void* d_dimage, void* grad, int64_t grad_ld, void* ws,
-                                       size_t ws_bytes, void* stream) {
-  TIDE_CHECK_ARG(pool && cams && proj && bins && fr && bg && d_dimage && grad && ws, "null argument");
-  TIDE_CHECK_ARG(n_cams == proj->n_cams && n_cams == bins->n_cams, "camera counts differ");
-  TIDE_CHECK_ARG(proj->dtype == pool->dtype, "dtype mismatch");
-  TIDE_CHECK_ARG(grad_ld >= proj->n_pidx, "grad_ld (%lld) < n_pidx (%lld)", (long long)grad_ld,
-                 (long long)proj->n_pidx);
-  TIDE_CHECK_ARG(proj->n_pidx == (int64_t)pool->n_order * pool->block_rows, "proj does not match pool");
-  const size_t need = tide_render_bwd_ws_bytes(bins, proj->dtype);
-  if (ws_bytes < need) {
-    set_error("render_bwd workspace too small (%zu < %zu)", ws_bytes, need);
-    return TIDE_ECAPACITY;
-  }
-  hipStream_t st = (hipStream_t)stream;
+// The three stages on one stream; with cfg the last one applies the masked
+// Adam update instead of storing the gradient.
+static tide_status render_bwd_run(const tide_pool* pool, const tide_camera* cams, int32_t n_cams,
+                                  const tide_proj* proj, const tide_bins* bins, const tide_frame* fr, const float* bg,
+                                  const void* d_dimage, void* grad, int64_t grad_ld, const tide_adam_cfg* cfg,
+                                  void* ws, hipStream_t st) {
   const uint32_t grid = (uint32_t)(bins->n_cams * bins->tiles_x * bins->tiles_y);
   const int64_t nrec = (int64_t)n_cams * proj->n_pidx;
   Carver cv(ws);
@@ -599,8 +671,12 @@ extern "C" tide_status tide_render_bwd(const tide_pool* pool, const tide_camera*
                                                         (const float*)partial, g2d));
     TIDE_LAUNCH_CHECK("k_reduce_pairs");
     const CamSet<float> cs = make_camset<float>(cams, n_cams);
-    if (proj->n_pidx > 0)
-      TIDE_TIMED("adjoint", st, launch_adjoint<float>(pool, proj, cs, g2d, (float*)grad, grad_ld, st));
+    if (proj->n_pidx > 0) {
+      if (cfg)
+        TIDE_TIMED("adjoint_adam", st, launch_adjoint_adam<float>(pool, proj, cs, g2d, cfg, st));
+      else
+        TIDE_TIMED("adjoint", st, launch_adjoint<float>(pool, proj, cs, g2d, (float*)grad, grad_ld, st));
+    }
     TIDE_LAUNCH_CHECK("k_adjoint");
   } else {
     double* partial = cv.take<double>((size_t)(bins->n_inst > 0 ? bins->n_inst : 1) * kG2);
@@ -617,9 +693,63 @@ extern "C" tide_status tide_render_bwd(const tide_pool* pool, const tide_camera*
                                                         (const double*)partial, g2d));
     TIDE_LAUNCH_CHECK("k_reduce_pairs");
     const CamSet<double> cs = make_camset<double>(cams, n_cams);
-    if (proj->n_pidx > 0)
-      TIDE_TIMED("adjoint", st, launch_adjoint<double>(pool, proj, cs, g2d, (double*)grad, grad_ld, st));
+    if (proj->n_pidx > 0) {
+      if (cfg)
+        TIDE_TIMED("adjoint_adam", st, launch_adjoint_adam<double>(pool, proj, cs, g2d, cfg, st));
+      else
+        TIDE_TIMED("adjoint", st, launch_adjoint<double>(pool, proj, cs, g2d, (double*)grad, grad_ld, st));
+    }
     TIDE_LAUNCH_CHECK("k_adjoint");
   }
+  return TIDE_OK;
+}
+
+static tide_status render_bwd_check(const tide_pool* pool, const tide_camera* cams, int32_t n_cams,
+                                    const tide_proj* proj, const tide_bins* bins, const tide_frame* fr,
+                                    const float* bg, const void* d_dimage, void* ws, size_t ws_bytes) {
+  TIDE_CHECK_ARG(pool && cams && proj && bins && fr && bg && d_dimage && ws, "null argument");
+  TIDE_CHECK_ARG(n_cams == proj->n_cams && n_cams == bins->n_cams, "camera counts differ");
+  TIDE_CHECK_ARG(proj->dtype == pool->dtype, "dtype mismatch");
+  TIDE_CHECK_ARG(proj->n_pidx == (int64_t)pool->n_order * pool->block_rows, "proj does not match pool");
+  const size_t need = tide_render_bwd_ws_bytes(bins, proj->dtype);
+  if (ws_bytes < need) {
+    set_error("render_bwd workspace too small (%zu < %zu)", ws_bytes, need);
+    return TIDE_ECAPACITY;
+  }
+  return TIDE_OK;
+}
+
+extern "C" tide_status tide_render_bwd(const tide_pool* pool, const tide_camera* cams, int32_t n_cams,
+                                       const tide_proj* proj, const tide_bins* bins, const tide_frame* fr,
+                                       const float* bg, const void* d_dimage, void* grad, int64_t grad_ld, void* ws,
+                                       size_t ws_bytes, void* stream) {
+  TIDE_CHECK_ARG(grad, "null argument");
+  const tide_status e = render_bwd_check(pool, cams, n_cams, proj, bins, fr, bg, d_dimage, ws, ws_bytes);
+  if (e != TIDE_OK) return e;
+  TIDE_CHECK_ARG(grad_ld >= proj->n_pidx, "grad_ld (%lld) < n_pidx (%lld)", (long long)grad_ld,
+                 (long long)proj->n_pidx);
+  return render_bwd_run(pool, cams, n_cams, proj, bins, fr, bg, d_dimage, grad, grad_ld, nullptr, ws,
+                        (hipStream_t)stream);
+}
+
+extern "C" tide_status tide_render_bwd_adam(tide_pool* pool, const tide_camera* cams, int32_t n_cams,
+                                            const tide_proj* proj, const tide_bins* bins, const tide_frame* fr,
+                                            const float* bg, const void* d_dimage, const tide_adam_cfg* cfg,
+                                            float* spheres, uint8_t* dirty, int64_t n_blocks, void* ws,
+                                            size_t ws_bytes, void* stream) {
+  TIDE_CHECK_ARG(cfg, "null argument");
+  const tide_status e = render_bwd_check(pool, cams, n_cams, proj, bins, fr, bg, d_dimage, ws, ws_bytes);
+  if (e != TIDE_OK) return e;
+  TIDE_CHECK_ARG(pool->params && pool->exp_avg && pool->exp_avg_sq && pool->step && pool->order && pool->slot_block,
+                 "pool has a null pointer");
+  TIDE_CHECK_ARG(cfg->beta1 > 0 && cfg->beta1 < 1 && cfg->beta2 > 0 && cfg->beta2 < 1 && cfg->eps >= 0,
+                 "bad Adam constants");
+  TIDE_CHECK_ARG((!spheres && !dirty) || n_blocks > 0, "n_blocks must be given with spheres/dirty");
+  hipStream_t st = (hipStream_t)stream;
+  const tide_status r =
+      render_bwd_run(pool, cams, n_cams, proj, bins, fr, bg, d_dimage, nullptr, 0, cfg, ws, st);
+  if (r != TIDE_OK) return r;
+  launch_adam_bounds(pool, proj, cfg->kappa, spheres, dirty, st);
+  TIDE_LAUNCH_CHECK("k_adam_bounds");
   return TIDE_OK;
 }

@@ -429,29 +429,31 @@ __global__ void __launch_bounds__(64) k_render_fwd(const uint32_t* __restrict__ 
   const int px = tx * kTile + (lane & 15);
   const int py0 = ty * kTile + (lane >> 4);
   const T fxp = (T)px + (T)0.5;
-  // A pixel is live while Tr > 0; stopping stores -T (the final T, negated),
-  // and pixels outside the image start stopped.
+  // A pixel that stops (or lies outside the image) moves its row to
+  // +infinity, where no entry reaches it, so the per-entry work needs no
+  // liveness test; Tr then keeps its final T.
+  const T kGone = __builtin_inf();
   T fyp[4], Tr[4], C0[4], C1[4], C2[4];
   uint32_t lst[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    fyp[q] = (T)(py0 + 4 * q) + (T)0.5;
-    Tr[q] = (px < W && py0 + 4 * q < H) ? (T)1 : (T)-1;
-    C0[q] = C1[q] = C2[q] = 0;
-    lst[q] = 0;
-  }
-  unsigned long long nvis = 0;   // wave-uniform: live pixels summed over entries
   // live pixels of the wave; every entry reached counts them as visits
   uint32_t nlive = 0;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) nlive += (uint32_t)__popcll(__ballot(Tr[q] > 0));
+  for (int q = 0; q < 4; ++q) {
+    const bool in = px < W && py0 + 4 * q < H;
+    fyp[q] = in ? (T)(py0 + 4 * q) + (T)0.5 : kGone;
+    Tr[q] = 1;
+    C0[q] = C1[q] = C2[q] = 0;
+    lst[q] = 0;
+    nlive += (uint32_t)__popcll(__ballot(in));
+  }
+  unsigned long long nvis = 0;   // wave-uniform: live pixels summed over entries
   const uint32_t start = ranges[2 * g], end = ranges[2 * g + 1];
   __shared__ T s_u[64], s_v[64], s_A[64], s_B[64], s_C[64], s_o[64], s_r[64], s_g[64], s_b[64];
-  __shared__ uint32_t s_take[64];
   const T ks = (T)Ex<T>::k;
   bool any = nlive != 0;
   for (uint32_t b0 = start; b0 < end && any; b0 += 64) {
     const uint32_t j = b0 + lane;
+    bool may = false;
     if (j < end) {
       const T* q = rec + (int64_t)inst_rec[inst_e[j]] * kRec;
       s_u[lane] = q[0]; s_v[lane] = q[1];
@@ -460,51 +462,65 @@ __global__ void __launch_bounds__(64) k_render_fwd(const uint32_t* __restrict__ 
       // entries whose footprint misses every pixel centre of the tile at
       // alpha >= 1/255 (about 40 % of the aerial scene's instances) are
       // passed over without any per-pixel work
-      s_take[lane] = tile_may_take<T>(q[0], q[1], q[2], q[3], q[4], q[5], tx, ty) ? 1u : 0u;
+      may = tile_may_take<T>(q[0], q[1], q[2], q[3], q[4], q[5], tx, ty);
     }
+    // the batch's entries that some pixel centre may take, one bit each: the
+    // walk below visits only those, and the others cost nothing
+    uint64_t rest = __ballot(may);
     __syncthreads();
     const int nb = (int)(end - b0 < 64 ? end - b0 : 64);
-    for (int k = 0; k < nb; ++k) {
-      nvis += nlive;
-      if (!s_take[k]) continue;
+    int counted = 0;   // entries of the batch whose visits are in nvis
+    while (rest != 0) {
+      const int k = __builtin_ctzll(rest);
+      rest &= rest - 1;
+      // every live pixel visits entries counted..k
+      nvis += (unsigned long long)nlive * (unsigned long long)(k + 1 - counted);
+      counted = k + 1;
       const T v = s_v[k], Ch = s_C[k], op = s_o[k];
       const T cr = s_r[k], cg = s_g[k], cb = s_b[k];
       const T dx = fxp - s_u[k];
       const T adx2 = s_A[k] * dx * dx, bdx = s_B[k] * dx;
       const uint32_t idx = b0 - start + (uint32_t)k + 1;
-      // Alphas first: when no live pixel takes the entry (the tile test is
+      // Alphas first: when no pixel takes the entry (the tile test is
       // conservative, and pixels stop), the update below would change
-      // nothing, and the wave skips it.
+      // nothing, and the wave skips it.  Each comparison is balloted on its
+      // own and the masks are combined on the scalar unit (a ballot of a
+      // combined condition costs two vector instructions).
       T al[4];
       bool ps[4];
-      bool take_any = false;
+      uint64_t pm[4], take_m = 0;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         T G, araw;
-        ps[q] = entry_alpha<T>(adx2, bdx, Ch, op, fyp[q] - v, G, araw, al[q]);
-        take_any = take_any || (ps[q] && Tr[q] > 0);
+        bool in_power, in_alpha;
+        entry_alpha_tests<T>(adx2, bdx, Ch, op, fyp[q] - v, G, araw, al[q], in_power, in_alpha);
+        ps[q] = in_power && in_alpha;
+        pm[q] = __ballot(in_power) & __ballot(in_alpha);
+        take_m |= pm[q];
       }
-      if (__ballot(take_any) == 0) continue;
+      if (take_m == 0) continue;
+      uint32_t nstop = 0;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
+        if (pm[q] == 0) continue;   // no pixel of row group q takes the entry: nothing changes
         const T alpha = al[q];
         const bool pass = ps[q];
-        const bool live = Tr[q] > 0;
         const T wr = alpha * Tr[q];
         const T tn = Tr[q] - wr;   // T (1 - alpha)
-        const bool ok = pass && live;
-        const bool stop = ok && tn < (T)1e-4;
-        const bool take = ok && !stop;
+        const bool low = tn < (T)1e-4;
+        const bool stop = pass && low;
+        const bool take = pass && !low;
         const T w = take ? wr : (T)0;
         C0[q] += cr * w; C1[q] += cg * w; C2[q] += cb * w;
-        Tr[q] = take ? tn : (stop ? -Tr[q] : Tr[q]);
+        Tr[q] = take ? tn : Tr[q];
+        fyp[q] = stop ? kGone : fyp[q];
         lst[q] = take ? idx : lst[q];
+        nstop += (uint32_t)__popcll(pm[q] & __ballot(low));
       }
-      nlive = 0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) nlive += (uint32_t)__popcll(__ballot(Tr[q] > 0));
+      nlive -= nstop;
       if (nlive == 0) { any = false; break; }
     }
+    nvis += (unsigned long long)nlive * (unsigned long long)(nb - counted);
     __syncthreads();
   }
   const int64_t HW = (int64_t)H * W;
@@ -515,7 +531,7 @@ __global__ void __launch_bounds__(64) k_render_fwd(const uint32_t* __restrict__ 
     if (px < W && py < H) {
       const int64_t p = (int64_t)py * W + px;
       nback += lst[q];
-      const T tf = Tr[q] < 0 ? -Tr[q] : Tr[q];
+      const T tf = Tr[q];
       image[((int64_t)c * 3 + 0) * HW + p] = C0[q] + tf * bg0;
       image[((int64_t)c * 3 + 1) * HW + p] = C1[q] + tf * bg1;
       image[((int64_t)c * 3 + 2) * HW + p] = C2[q] + tf * bg2;

@@ -314,6 +314,23 @@ class Rasterizer:
                                           C.c_void_p(ws.data_ptr()), ws.numel(), C.c_void_p(_stream())))
 
 
+    def backward_adam(self, pool: Pool, cams, proj: Proj, bins: L.tide_bins, fr: Frame, dimage: torch.Tensor,
+                      cfg: L.tide_adam_cfg, spheres=None, dirty=None, bg=(0.0, 0.0, 0.0)) -> None:
+        """backward then adam, with no gradient stored in between (same bits)."""
+        nb = int(spheres.shape[0]) if spheres is not None else (int(dirty.shape[0]) if dirty is not None else 0)
+        wsb = self.lib.tide_render_bwd_ws_bytes(C.byref(bins), proj.dtype)
+        ws = self.buf.get("bwd_ws", wsb)
+        cam_arr = L.camera_array(cams)
+        bgc = (C.c_float * 3)(*[float(x) for x in bg])
+        pc, qc, fc = pool.c(), proj.c(), fr.c()
+        dimage = dimage.contiguous()
+        L.check(self.lib.tide_render_bwd_adam(C.byref(pc), cam_arr, len(cams), C.byref(qc), C.byref(bins),
+                                              C.byref(fc), bgc, C.c_void_p(dimage.data_ptr()), C.byref(cfg),
+                                              C.c_void_p(spheres.data_ptr() if spheres is not None else 0),
+                                              C.c_void_p(dirty.data_ptr() if dirty is not None else 0), nb,
+                                              C.c_void_p(ws.data_ptr()), ws.numel(), C.c_void_p(_stream())))
+
+
 def dense_grad(proj: Proj, grad: torch.Tensor, n: int) -> torch.Tensor:
     """Compact [59][n_active] gradient -> dense (n, 59) for an all-resident
     pool whose pidx equals the global row id."""

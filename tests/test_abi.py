@@ -53,6 +53,10 @@ def test_null_arguments_rejected_before_launch():
     assert lib.tide_loss(None, None, 1, 8, 8, 0, None, None, None, 0, None) == L.TIDE_EINVAL
     cfg = L.tide_adam_cfg()
     assert lib.tide_adam_sparse(None, None, None, 0, C.byref(cfg), None, None, 0, None, 0, None) == L.TIDE_EINVAL
+    assert lib.tide_render_bwd_adam(None, cam, 1, None, None, None, None, None, C.byref(cfg), None, None, 0, None,
+                                    0, None) == L.TIDE_EINVAL
+    assert lib.tide_render_bwd_adam(C.byref(pool), cam, 1, None, None, None, None, None, None, None, None, 0, None,
+                                    0, None) == L.TIDE_EINVAL
 
 
 def test_noalloc_preprocess_rejects_a_size_beyond_its_scratch_on_the_host():

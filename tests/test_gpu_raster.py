@@ -659,6 +659,56 @@ def test_sparse_adam_matches_oracle_and_leaves_inactive_rows():
         assert sr[b, 3] >= reach[rows].max() * (1 - 1e-6)
 
 
+def fused_vs_separate(theta, cams_seq, dtype, block_rows):
+    """Two training steps each way on two copies of one pool: backward then
+    masked Adam, against the fused call; everything the update writes must
+    match bit for bit."""
+    cfg = adam_cfg(LR59)
+    outs = []
+    for fused in (False, True):
+        rast = Rasterizer("cuda")
+        pool = Pool.from_dense(torch.tensor(np.asarray(theta), dtype=dtype, device="cuda"), block_rows)
+        nblk = pool.n_slots
+        spheres = torch.zeros((nblk, 4), dtype=torch.float32, device="cuda")
+        dirty = torch.zeros((nblk,), dtype=torch.uint8, device="cuda")
+        for it, cams in enumerate(cams_seq):
+            proj, bins, fr = rast.forward(pool, cams)
+            g = torch.Generator().manual_seed(40 + it)
+            dimg = (torch.randn(fr.image.shape, generator=g, dtype=torch.float64) * 1e-3).to("cuda", dtype)
+            if fused:
+                rast.backward_adam(pool, cams, proj, bins, fr, dimg, cfg, spheres, dirty)
+            else:
+                grad = rast.backward(pool, cams, proj, bins, fr, dimg)
+                rast.adam(pool, proj, grad, cfg, spheres, dirty)
+        torch.cuda.synchronize()
+        outs.append([t.cpu().clone() for t in (pool.params, pool.exp_avg, pool.exp_avg_sq, pool.step, spheres,
+                                               dirty)])
+    names = ("params", "exp_avg", "exp_avg_sq", "step", "spheres", "dirty")
+    for name, a, b in zip(names, outs[0], outs[1]):
+        if not torch.equal(a, b):
+            d = (a.double() - b.double()).abs()
+            raise AssertionError(f"{name} differs ({dtype}): {int((a != b).sum())} of {a.numel()} elements, "
+                                 f"max abs {float(d.max()):.3e}")
+    # the steps did update something
+    assert int(outs[1][3].max()) == len(cams_seq)
+
+
+def test_fused_backward_adam_equals_backward_then_adam():
+    say("case: fused backward + masked Adam vs the two calls, dense scene, FP32 and FP64, two steps")
+    th, cams = dense_case()
+    th = th.copy()
+    th[::5, 2] = -10.0   # inactive rows stay untouched both ways
+    for dtype in (torch.float32, torch.float64):
+        fused_vs_separate(th, [cams, cams[::-1]], dtype, 1024)
+
+
+def test_fused_backward_adam_on_an_aerial_view():
+    say("case: fused backward + masked Adam vs the two calls, aerial 1M Gaussians, one 1920x1080 view, blocks of "
+        "65536")
+    theta, cams = synth.aerial_workload()
+    fused_vs_separate(theta, [cams[:1], cams[1:2]], torch.float32, 65536)
+
+
 # --------------------------------------------------- full-size workload
 def test_aerial_full_frames_on_the_gpu_projection():
     say("case: aerial 1M Gaussians, 4 views 1920x1080, blocks of 65536 (the benchmark's launch shape); "
