@@ -25,6 +25,7 @@ constexpr int kSortThreads = 256;
 constexpr int kSortWaves = kSortThreads / kWave;       // 4
 constexpr int kSortRounds = 16;
 constexpr int kSortTile = kSortThreads * kSortRounds;  // 4096
+constexpr int kXcds = 8;                               // workgroup b starts on XCD b % 8
 
 // ------------------------------------------------------------------ scan
 // Input functors: value of element i as u32; load4 reads elements i..i+3
@@ -234,7 +235,8 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint32_t* 
                                                                 const unsigned long long* d_n, int shift,
                                                                 const uint32_t* gofs, int64_t nb,
                                                                 uint32_t* keys_out, uint32_t* vals_out,
-                                                                const uint32_t* gather_src, uint32_t* gather_out);
+                                                                const uint32_t* gather_src, uint32_t* gather_out,
+                                                                int xcd_order);
 
 inline size_t radix_hist_count(int64_t n) { return 256 * (size_t)ceil_div(n > 0 ? n : 1, kSortTile); }
 
@@ -245,11 +247,60 @@ inline size_t radix_hist_count(int64_t n) { return 256 * (size_t)ceil_div(n > 0 
 // *keys_res / *vals_res.  hist needs radix_hist_count(n) u32, partial
 // scan_partial_count(radix_hist_count(n)) u64, total one u64.  With
 // gather_src, the last pass also writes gather_out[j] = gather_src[value j]
-// for every sorted position j.
+// for every sorted position j.  With xcd_order the scatter's tiles are
+// assigned so that each XCD writes a contiguous eighth of them.
 void radix_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int64_t n, int bits,
                       bool identity_vals, uint32_t* hist, unsigned long long* partial,
                       unsigned long long* total, hipStream_t st, uint32_t** keys_res,
                       uint32_t** vals_res, const unsigned long long* d_n = nullptr,
-                      const uint32_t* gather_src = nullptr, uint32_t* gather_out = nullptr);
+                      const uint32_t* gather_src = nullptr, uint32_t* gather_out = nullptr,
+                      bool xcd_order = false);
+
+// ------------------------------------------------- one-sweep radix sort
+// The same stable LSD sort with one kernel per 8-bit pass.  A first kernel
+// counts every pass's digits over all keys at once (LDS bins per block,
+// added to global counts with device-scope atomics).  Each pass kernel then
+// ranks its 4096-key tile as k_radix_scatter does, publishes its digit
+// counts, and finds the counts of all earlier tiles by walking back over
+// their published words until one holds an inclusive prefix (decoupled
+// look-back, kOsWindow words per poll).  A tile publishes its own counts
+// before it waits on anyone and workgroups start in index order on each
+// XCD, so every wait ends; the walk also gives up after kOsSpinLimit polls
+// of one word and sets an error word (the output is then wrong, but every
+// write stays in bounds), so no kernel spins without end.  Used where the
+// keys are few (the depth sort of the visible pairs): there the two
+// launches per pass that it saves weigh more than the look-back.
+//
+// Control words: kOsCtlLen u32 that must read zero when the sort starts
+// (an earlier kernel on the stream clears them).  The global digit counts
+// are kept in kOsCopies copies (histogram block b adds to copy
+// b % kOsCopies, which spreads the atomics), ctl[kOsCtlWords +
+// (kOsMaxPasses c + p) 256 + d] being copy c of pass p's count of digit d.
+constexpr int kOsCtlWords = 8;
+constexpr int kOsMaxPasses = 4;
+constexpr int kOsCopies = 8;
+constexpr int kOsCtlLen = kOsCtlWords + kOsCopies * kOsMaxPasses * 256;
+constexpr int kOsHistBlocks = 1024;
+constexpr int kOsWindow = 4;
+constexpr uint32_t kOsSpinLimit = 1u << 20;
+
+struct OsWork {
+  uint32_t* ctl;                  // kOsCtlLen u32, zero at the start
+  unsigned long long* status;     // onesweep_status_count(n, passes)
+  uint32_t* err;                  // set to nonzero if a look-back gave up
+};
+
+// Tiles of 256 rounds keys, rounds in {4, 8, 16}.
+inline size_t onesweep_status_count(int64_t n, int passes, int rounds) {
+  return (size_t)passes * 256 * (size_t)ceil_div(n > 0 ? n : 1, kSortThreads * rounds);
+}
+
+// As radix_sort_pairs (bits <= 32, at most kOsMaxPasses passes) over tiles
+// of 256 rounds keys; n is the launch bound and d_n, when given, the count
+// on the device.
+void onesweep_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int64_t n, int bits, int rounds,
+                         bool identity_vals, const OsWork& w, hipStream_t st, uint32_t** keys_res,
+                         uint32_t** vals_res, const unsigned long long* d_n = nullptr,
+                         const uint32_t* gather_src = nullptr, uint32_t* gather_out = nullptr);
 
 }  // namespace tide

@@ -253,10 +253,15 @@ static tide_status check_proj(const tide_proj* p) {
 }
 
 // ---------------------------------------------------------------- binning
+// The grid also clears clear32[0, n_clear) (the sorts' control words) and
+// *clear64 (the binning's error word).
 __global__ void k_compact_vis(const uint32_t* __restrict__ tt, const float* __restrict__ depth,
                               const uint32_t* __restrict__ vis_off, int64_t n, uint32_t* __restrict__ key,
-                              uint32_t* __restrict__ val) {
+                              uint32_t* __restrict__ val, uint32_t* __restrict__ clear32, int64_t n_clear,
+                              unsigned long long* __restrict__ clear64) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_clear) clear32[i] = 0u;
+  if (i == 0) *clear64 = 0ull;
   if (i >= n || tt[i] == 0) return;
   const uint32_t o = vis_off[i];
   key[o] = __float_as_uint(depth[i]);   // depth > 0: the bit pattern orders like the value
@@ -289,7 +294,8 @@ __global__ void __launch_bounds__(64) k_emit(const uint32_t* __restrict__ vis_re
     if (lane <= np) s_off[lane] = inst_off[s0 + lane];
     if (lane == 0 && np == kWave) s_off[kWave] = inst_off[s0 + kWave];
     if (lane < np) {
-      const uint32_t r = vis_rec[s0 + lane];
+      uint32_t r = vis_rec[s0 + lane];
+      r = (int64_t)r < nv_max ? r : 0u;   // in bounds even after a failed sort
       const uint32_t c = (uint32_t)(r / (uint64_t)n_pidx);
       const uint32_t a = rect[2 * (int64_t)r], b = rect[2 * (int64_t)r + 1];
       const uint32_t x0 = a & 0xffff, y0 = a >> 16, x1 = b & 0xffff;
@@ -321,9 +327,17 @@ __global__ void __launch_bounds__(64) k_emit(const uint32_t* __restrict__ vis_re
 // device (grid-stride).  A thread takes four consecutive keys (one 16-byte
 // load when kVec: the keys are 16-byte aligned) and compares each with its
 // neighbours; ~0u stands in past either end (keys are below 2^31).
+// After a failed sort (*err set) the ranges stay empty, so the compositing
+// reads no entry, and the flag is copied to host_err for the host.
 template <bool kVec>
 __global__ void k_ranges(const uint32_t* __restrict__ key, int64_t n_max, const unsigned long long* __restrict__ d_n,
-                         uint32_t* __restrict__ ranges) {
+                         uint32_t* __restrict__ ranges, const uint32_t* __restrict__ err,
+                         unsigned long long* __restrict__ host_err) {
+  const uint32_t failed = *err;
+  if (failed) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *host_err = failed;
+    return;
+  }
   const int64_t n = dev_count(n_max, d_n);
   const int64_t stride = 4 * (int64_t)gridDim.x * blockDim.x;
   for (int64_t j0 = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x); j0 < n; j0 += stride) {
@@ -350,27 +364,136 @@ __global__ void k_ranges(const uint32_t* __restrict__ key, int64_t n_max, const 
 
 // Launch order of the compositing kernels: tiles by descending list length
 // (ties in tile order), so that the longest lists start first and the tail
-// of the launch is made of short ones.  Launch-order key of a tile: its list length on a log scale with 16 steps
-// per octave (the leading bit's position and the next four bits of len + 1),
-// longest first; lengths of 2^16 and more share the first bucket.  One 8-bit
-// radix pass orders them; ties keep tile order.
-__global__ void k_tile_keys(const uint32_t* __restrict__ ranges, int64_t n, uint32_t* __restrict__ key) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
+// of the launch is made of short ones.  A tile's key is its list length on a
+// log scale with 16 steps per octave (the leading bit's position and the
+// next four bits of len + 1), longest first; lengths of 2^16 and more share
+// the first bucket.
+__device__ inline uint32_t tile_len_key(const uint32_t* __restrict__ ranges, int64_t g) {
   const uint32_t x = ranges[2 * g + 1] - ranges[2 * g] + 1u;
   const uint32_t e = 31u - (uint32_t)__clz(x);
   const uint32_t f = e >= 4u ? (x >> (e - 4u)) & 15u : (x << (4u - e)) & 15u;
   const uint32_t b = 16u * e + f;
-  key[g] = 255u - (b < 255u ? b : 255u);
+  return 255u - (b < 255u ? b : 255u);
 }
 
+__global__ void k_tile_keys(const uint32_t* __restrict__ ranges, int64_t n, uint32_t* __restrict__ key) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < n) key[g] = tile_len_key(ranges, g);
+}
+
+// The tiles sorted by that key, stably, in two small launches over
+// kOrderTiles-tile blocks (one thread per tile): k_order_hist counts each
+// block's keys (hist[block 256 + key]); k_order_place adds up,
+// per key, the counts of all blocks and of the blocks before its own, and
+// places its tiles at that start plus their rank among the block's earlier
+// tiles of the same key (earlier waves' counts, then ballot peer masks
+// within the wave).  Used while nb <= kOrderMaxBlocks (every block reads
+// all nb counts of each key); larger grids take the radix sort.
+constexpr int kOrderTiles = 256;
+constexpr int64_t kOrderMaxBlocks = 1024;
+
+__device__ __forceinline__ uint64_t key_peers(uint32_t d, bool ok) {
+  uint64_t peers = __ballot(ok);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t mk = __ballot(bit);
+    peers &= bit ? mk : ~mk;
+  }
+  return peers;
+}
+
+// Per wave of the block: counts of each key among its 64 tiles, into
+// cnt[wave][key] (zero on entry); returns the tile's key and peer mask.
+__device__ __forceinline__ uint32_t order_count(const uint32_t* __restrict__ ranges, int64_t n,
+                                                uint32_t (*cnt)[256], bool& ok, uint64_t& peers) {
+  const int64_t g = (int64_t)blockIdx.x * kOrderTiles + threadIdx.x;
+  ok = g < n;
+  const uint32_t d = ok ? tile_len_key(ranges, g) : 0u;
+  peers = key_peers(d, ok);
+  if (ok && (peers & lanemask_lt()) == 0) cnt[threadIdx.x / kWave][d] = (uint32_t)__popcll(peers);
+  return d;
+}
+
+__global__ void __launch_bounds__(kOrderTiles) k_order_hist(const uint32_t* __restrict__ ranges, int64_t n,
+                                                            uint32_t* __restrict__ hist) {
+  __shared__ uint32_t cnt[kOrderTiles / kWave][256];
+  for (int k = threadIdx.x; k < (kOrderTiles / kWave) * 256; k += kOrderTiles) (&cnt[0][0])[k] = 0;
+  __syncthreads();
+  bool ok;
+  uint64_t peers;
+  order_count(ranges, n, cnt, ok, peers);
+  __syncthreads();
+  uint32_t c = 0;
+#pragma unroll
+  for (int w = 0; w < kOrderTiles / kWave; ++w) c += cnt[w][threadIdx.x];
+  hist[(int64_t)blockIdx.x * 256 + threadIdx.x] = c;
+}
+
+__global__ void __launch_bounds__(kOrderTiles) k_order_place(const uint32_t* __restrict__ ranges, int64_t n,
+                                                             const uint32_t* __restrict__ hist,
+                                                             uint32_t* __restrict__ order) {
+  __shared__ uint32_t cnt[kOrderTiles / kWave][256];
+  __shared__ uint32_t start[256], wsum[kOrderTiles / kWave];
+  for (int k = threadIdx.x; k < (kOrderTiles / kWave) * 256; k += kOrderTiles) (&cnt[0][0])[k] = 0;
+  // key k = threadIdx.x: all blocks' count and the earlier blocks' count
+  const int k = threadIdx.x, w = threadIdx.x / kWave, lane = __lane_id();
+  uint32_t tot = 0, pre = 0;
+  const uint32_t nbk = gridDim.x;
+  uint32_t b = 0;
+  for (; b + 8 <= nbk; b += 8) {   // eight coalesced rows in flight
+    uint32_t c[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) c[u] = hist[(int64_t)(b + u) * 256 + k];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      tot += c[u];
+      pre += b + u < blockIdx.x ? c[u] : 0u;
+    }
+  }
+  for (; b < nbk; ++b) {
+    const uint32_t c = hist[(int64_t)b * 256 + k];
+    tot += c;
+    pre += b < blockIdx.x ? c : 0u;
+  }
+  const uint32_t inc = wave_incl_scan(tot);
+  if (lane == kWave - 1) wsum[w] = inc;
+  __syncthreads();
+  uint32_t base = inc - tot + pre;
+  for (int q = 0; q < w; ++q) base += wsum[q];
+  start[k] = base;
+  bool ok;
+  uint64_t peers;
+  const uint32_t d = order_count(ranges, n, cnt, ok, peers);
+  __syncthreads();
+  if (ok) {
+    uint32_t pos = start[d] + (uint32_t)__popcll(peers & lanemask_lt());
+    for (int q = 0; q < w; ++q) pos += cnt[q][d];
+    order[pos] = (uint32_t)((int64_t)blockIdx.x * kOrderTiles + threadIdx.x);
+  }
+}
+
+// Keys per thread of the depth sort's tiles (256 threads): 4096-key tiles
+// were faster than 2048 or 1024 (fewer look-back words to publish and read).
+constexpr int kDepthRounds = 16;
+
 struct BinLayout {
-  uint32_t *vis_off, *ka, *va, *kb, *vb, *inst_off, *tka, *tva, *tkb, *tvb, *inst_rec, *ranges, *hist;
-  uint32_t *oka, *ova, *okb, *ovb;   // tile launch-order sort
+  uint32_t *vis_off, *ka, *va, *kb, *vb, *inst_off, *tka, *tva, *tkb, *tvb, *inst_rec, *ranges, *order;
+  uint32_t *oka, *ova, *okb, *ovb;   // launch-order radix sort (grids beyond kOrderMaxBlocks blocks)
+  uint32_t* ctl;                     // control words of the depth sort
+  unsigned long long* status;        // its look-back words
+  uint32_t* hist;                    // per-tile digit counts of the tile sort
   unsigned long long* tvis;          // per-tile visit counts of the compositing
   unsigned long long *partial, *totals;
   size_t bytes;
 };
+
+// Bits of the tile sort's key (camera-major tile id), at least one pass.
+static int tile_key_bits(int n_cams, int64_t n_tiles) {
+  int bits = 0;
+  while ((1ll << bits) < (int64_t)n_cams * n_tiles) ++bits;
+  return bits < 8 ? 8 : bits;
+}
 
 static BinLayout bin_layout(void* ws, int n_cams, int64_t n_pidx, int64_t n_tiles, int64_t cap) {
   const int64_t nv = (int64_t)n_cams * n_pidx;
@@ -387,19 +510,23 @@ static BinLayout bin_layout(void* ws, int n_cams, int64_t n_pidx, int64_t n_tile
   L.tkb = cv.take<uint32_t>(cap);
   L.tvb = cv.take<uint32_t>(cap);
   L.inst_rec = cv.take<uint32_t>(cap);
-  L.ranges = cv.take<uint32_t>(2 * (size_t)n_cams * n_tiles);
   const int64_t ntt = (int64_t)n_cams * n_tiles;
-  L.oka = cv.take<uint32_t>(ntt);
-  L.ova = cv.take<uint32_t>(ntt);
-  L.okb = cv.take<uint32_t>(ntt);
-  L.ovb = cv.take<uint32_t>(ntt);
+  L.ranges = cv.take<uint32_t>(2 * (size_t)ntt);
+  L.order = cv.take<uint32_t>(ntt);
   L.tvis = cv.take<unsigned long long>(2 * ntt);
-  int64_t big = nv > cap ? nv : cap;
-  big = big > ntt ? big : ntt;
-  const size_t nh = radix_hist_count(big);
+  L.ctl = cv.take<uint32_t>(kOsCtlLen);
+  L.status = cv.take<unsigned long long>(onesweep_status_count(nv, 4, kDepthRounds));
+  const int64_t nob = ceil_div(ntt, kOrderTiles);
+  const bool order_radix = nob > kOrderMaxBlocks;
+  L.oka = cv.take<uint32_t>(order_radix ? ntt : 0);
+  L.ova = cv.take<uint32_t>(order_radix ? ntt : 0);
+  L.okb = cv.take<uint32_t>(order_radix ? ntt : 0);
+  L.ovb = cv.take<uint32_t>(order_radix ? ntt : 0);
+  size_t nh = radix_hist_count(cap);
+  const size_t nho = order_radix ? radix_hist_count(ntt) : 256 * (size_t)nob;
+  nh = nh > nho ? nh : nho;
   L.hist = cv.take<uint32_t>(nh);
-  const size_t np = scan_partial_count((int64_t)(nh > (size_t)big ? nh : (size_t)big));
-  L.partial = cv.take<unsigned long long>(np);
+  L.partial = cv.take<unsigned long long>(scan_partial_count(nv > (int64_t)nh ? nv : (int64_t)nh));
   L.totals = cv.take<unsigned long long>(4);
   L.bytes = cv.used;
   return L;
@@ -690,33 +817,42 @@ extern "C" tide_status tide_bin_sort(const tide_proj* proj, int32_t tiles_x, int
 
   // 1. visible pairs, compacted in (camera, pidx) order, keyed by depth bits
   //    (a kernel of its own: the scan's down-sweep gives a thread 16
-  //    consecutive items, so writing the pairs there would not coalesce)
+  //    consecutive items, so writing the pairs there would not coalesce);
+  //    its grid also clears the sorts' control words and the error word
   scan_exclusive(NonzeroIn{proj->tiles_touched}, nv, L.vis_off, L.partial, &L.totals[0], st);
-  if (nv > 0)
-    TIDE_TIMED("compact_vis", st, hipLaunchKernelGGL(k_compact_vis, dim3((uint32_t)ceil_div(nv, 256)), dim3(256), 0, st,
-                                                     proj->tiles_touched, proj->depth, L.vis_off, nv, L.ka, L.va));
+  {
+    const int64_t n_clear = kOsCtlLen;
+    const int64_t nthreads = nv > n_clear ? nv : n_clear;
+    TIDE_TIMED("compact_vis", st, hipLaunchKernelGGL(k_compact_vis, dim3((uint32_t)ceil_div(nthreads, 256)), dim3(256), 0,
+                                                     st, proj->tiles_touched, proj->depth, L.vis_off, nv, L.ka, L.va,
+                                                     L.ctl, n_clear, &L.totals[3]));
+  }
   TIDE_LAUNCH_CHECK("visibility compaction");
+  uint32_t* err = reinterpret_cast<uint32_t*>(&L.totals[3]);
   // 2. stable sort of the visible pairs by depth; grids are sized by the
-  //    upper bound and the kernels read the visible count from the device
-  uint32_t *vk, *vrec;
+  //    upper bound and the kernels read the visible count from the device;
   //    the last pass also gathers each pair's tile count into depth order
   //    (into vis_off, free once the compaction has run)
-  radix_sort_pairs(L.ka, L.va, L.kb, L.vb, nv, 32, false, L.hist, L.partial, &L.totals[1], st, &vk, &vrec,
-                   &L.totals[0], proj->tiles_touched, L.vis_off);
+  uint32_t *vk, *vrec;
+  onesweep_sort_pairs(L.ka, L.va, L.kb, L.vb, nv, 32, kDepthRounds, false, OsWork{L.ctl, L.status, err}, st, &vk, &vrec,
+                      &L.totals[0], proj->tiles_touched, L.vis_off);
+  TIDE_LAUNCH_CHECK("depth sort");
   // 3. instance offsets in depth order, closed by inst_off[n_vis] = n_inst
   scan_exclusive(ArrayIn{L.vis_off}, nv, L.inst_off, L.partial, &L.totals[2], st, &L.totals[0],
                  ScanTail{nullptr, L.inst_off});
   TIDE_LAUNCH_CHECK("instance scan");
-  // 4. the counts travel to the host while the rest of the binning is queued
-  //    behind them: those kernels are sized by the instance capacity and read
-  //    the counts on the device, so the GPU does not wait for the host
+  // 4. the counts (and the depth sort's error word) travel to the host while
+  //    the rest of the binning is queued behind them: those kernels are sized
+  //    by the instance capacity and read the counts on the device, so the GPU
+  //    does not wait for the host
   CountSlot& slot = count_slot();
   std::lock_guard<std::mutex> lk(slot.mu);
   if (!slot.host) {
-    TIDE_HIP(hipHostMalloc((void**)&slot.host, 4 * sizeof(unsigned long long), hipHostMallocDefault));
+    TIDE_HIP(hipHostMalloc((void**)&slot.host, 8 * sizeof(unsigned long long), hipHostMallocDefault));
+    slot.host[4] = 0;
     TIDE_HIP(hipEventCreateWithFlags(&slot.ev, hipEventDisableTiming));
   }
-  TIDE_HIP(hipMemcpyAsync(slot.host, L.totals, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+  TIDE_HIP(hipMemcpyAsync(slot.host, L.totals, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
   TIDE_HIP(hipEventRecord(slot.ev, st));
   // 5. emit instances in depth order, keyed by global tile id (and clear
   //    the tile ranges)
@@ -728,35 +864,52 @@ extern "C" tide_status tide_bin_sort(const tide_proj* proj, int32_t tiles_x, int
                                               tiles_y, L.tka, L.inst_rec, L.ranges, nr));
   }
   TIDE_LAUNCH_CHECK("k_emit");
-  // 6. stable sort by tile; values are emission indices
-  int bits = 0;
-  while ((1ll << bits) < (int64_t)V * nt) ++bits;
-  bits = bits < 8 ? 8 : bits;
+  // 6. stable sort by tile; values are emission indices (histogram, scan
+  //    and scatter per pass: with this many keys the look-back would cost
+  //    more than the launches it saves)
+  const int bits = tile_key_bits(V, nt);
   uint32_t *tk, *te;
-  radix_sort_pairs(L.tka, L.tva, L.tkb, L.tvb, cap, bits, true, L.hist, L.partial, &L.totals[3], st, &tk, &te,
-                   &L.totals[2]);
-  // 7. per-tile ranges
+  radix_sort_pairs(L.tka, L.tva, L.tkb, L.tvb, cap, bits, true, L.hist, L.partial, &L.totals[1], st, &tk, &te,
+                   &L.totals[2], nullptr, nullptr, /*xcd_order=*/true);
+  TIDE_LAUNCH_CHECK("tile sort");
+  // 7. per-tile ranges (left empty, and the failure reported, if the depth
+  //    sort gave up)
   if (cap > 0) {
     const int64_t nb = ceil_div(ceil_div(cap, 4), 256);
     const dim3 grid((uint32_t)(nb < 65536 ? nb : 65536));
     if (((uintptr_t)tk & 15) == 0)
-      hipLaunchKernelGGL(k_ranges<true>, grid, dim3(256), 0, st, tk, cap, &L.totals[2], L.ranges);
+      hipLaunchKernelGGL(k_ranges<true>, grid, dim3(256), 0, st, tk, cap, &L.totals[2], L.ranges, err, slot.host + 4);
     else
-      hipLaunchKernelGGL(k_ranges<false>, grid, dim3(256), 0, st, tk, cap, &L.totals[2], L.ranges);
+      hipLaunchKernelGGL(k_ranges<false>, grid, dim3(256), 0, st, tk, cap, &L.totals[2], L.ranges, err, slot.host + 4);
   }
   TIDE_LAUNCH_CHECK("k_ranges");
   // 8. launch order of the tiles: longest lists first
   const int64_t ntt = (int64_t)V * nt;
-  hipLaunchKernelGGL(k_tile_keys, dim3((uint32_t)ceil_div(ntt, 256)), dim3(256), 0, st, L.ranges, ntt, L.oka);
-  TIDE_LAUNCH_CHECK("k_tile_keys");
-  uint32_t *ok, *order;
-  radix_sort_pairs(L.oka, L.ova, L.okb, L.ovb, ntt, 8, true, L.hist, L.partial, &L.totals[3], st, &ok, &order);
-  // 9. the counts, once they are on the host
+  const int64_t nob = ceil_div(ntt, kOrderTiles);
+  if (nob <= kOrderMaxBlocks) {
+    hipLaunchKernelGGL(k_order_hist, dim3((uint32_t)nob), dim3(kOrderTiles), 0, st, L.ranges, ntt, L.hist);
+    hipLaunchKernelGGL(k_order_place, dim3((uint32_t)nob), dim3(kOrderTiles), 0, st, L.ranges, ntt, L.hist, L.order);
+  } else {
+    hipLaunchKernelGGL(k_tile_keys, dim3((uint32_t)ceil_div(ntt, 256)), dim3(256), 0, st, L.ranges, ntt, L.oka);
+    uint32_t *ok, *ord;
+    radix_sort_pairs(L.oka, L.ova, L.okb, L.ovb, ntt, 8, true, L.hist, L.partial, &L.totals[1], st, &ok, &ord);
+    TIDE_HIP(hipMemcpyAsync(L.order, ord, ntt * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+  }
+  TIDE_LAUNCH_CHECK("tile launch order");
+  // 9. the counts, once they are on the host; a sort that gave up in this
+  //    call's depth sort, or in an earlier call's tile sort on this device
+  //    (whose report has landed by now), is an error
   TIDE_HIP(hipEventSynchronize(slot.ev));
   const int64_t n_vis = (int64_t)slot.host[0];
   const int64_t n_inst = (int64_t)slot.host[2];
+  const unsigned long long failed = slot.host[3] | slot.host[4];
   out->n_vis = n_vis;
   out->n_inst = n_inst;
+  if (failed) {
+    slot.host[4] = 0;
+    set_error("binning: a radix sort's look-back exceeded its spin limit; this call's or the previous call's lists are invalid");
+    return TIDE_EHIP;
+  }
   if (n_inst >= (int64_t)UINT32_MAX) {
     set_error("instance count %lld exceeds 32-bit indexing", (long long)n_inst);
     return TIDE_EINVAL;
@@ -766,6 +919,7 @@ extern "C" tide_status tide_bin_sort(const tide_proj* proj, int32_t tiles_x, int
     set_error("bin_sort needs %lld instances, workspace holds %lld", (long long)n_inst, (long long)cap);
     return TIDE_ECAPACITY;
   }
+  uint32_t* order = L.order;
   out->tile_order = order;
   out->tile_visits = L.tvis;
   out->vis_rec = vrec;
