@@ -61,11 +61,17 @@ struct OffsetsOut {   // out[i] = off
   bool aligned() const { return ((uintptr_t)out & 15) == 0; }
 };
 
-// Extras written by whichever block holds the total: a u32 copy of it, and
-// end[n] = total (the closing offset of an offsets array).
+// Extras written by whichever block holds the total: a u32 copy of it,
+// end[n] = total (the closing offset of an offsets array), and a copy of
+// copy_n u64 words from copy_src (read after the total is stored, so it may
+// include it) to copy_dst (say, pinned host memory the host reads after an
+// event: no copy kernel needed).
 struct ScanTail {
-  uint32_t* total32;
-  uint32_t* end;
+  uint32_t* total32 = nullptr;
+  uint32_t* end = nullptr;
+  const unsigned long long* copy_src = nullptr;
+  unsigned long long* copy_dst = nullptr;
+  int copy_n = 0;
 };
 
 // Element counts: n_max bounds the launch; when d_n is given the kernels
@@ -120,6 +126,7 @@ __global__ void __launch_bounds__(1024) k_scan_partials(unsigned long long* part
 __device__ inline void write_tail(const ScanTail& tail, unsigned long long t, int64_t n) {
   if (tail.total32) *tail.total32 = (uint32_t)t;
   if (tail.end) tail.end[n] = (uint32_t)t;
+  for (int k = 0; k < tail.copy_n; ++k) tail.copy_dst[k] = tail.copy_src[k];
 }
 
 // kSums: partial holds the blocks' sums (not yet scanned); each block adds
@@ -190,7 +197,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_down(In in, int64_t n_max
 // ceil(n_max/4096) u64 entries; d_n as for dev_count.
 template <typename In, typename Out>
 inline void scan_to(In in, int64_t n, Out out, unsigned long long* partial, unsigned long long* total,
-                    hipStream_t st, const unsigned long long* d_n = nullptr, ScanTail tail = ScanTail{nullptr, nullptr}) {
+                    hipStream_t st, const unsigned long long* d_n = nullptr, ScanTail tail = ScanTail{}) {
   const int64_t nb = ceil_div(n > 0 ? n : 1, kScanTile);
   const bool vec = in.aligned() && out.aligned();
   if (vec)
@@ -219,7 +226,7 @@ inline void scan_to(In in, int64_t n, Out out, unsigned long long* partial, unsi
 template <typename In>
 inline void scan_exclusive(In in, int64_t n, uint32_t* out, unsigned long long* partial,
                            unsigned long long* total, hipStream_t st, const unsigned long long* d_n = nullptr,
-                           ScanTail tail = ScanTail{nullptr, nullptr}) {
+                           ScanTail tail = ScanTail{}) {
   scan_to(in, n, OffsetsOut{out}, partial, total, st, d_n, tail);
 }
 

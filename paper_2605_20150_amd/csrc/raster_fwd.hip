@@ -253,19 +253,92 @@ static tide_status check_proj(const tide_proj* p) {
 }
 
 // ---------------------------------------------------------------- binning
-// The grid also clears clear32[0, n_clear) (the sorts' control words) and
-// *clear64 (the binning's error word).
-__global__ void k_compact_vis(const uint32_t* __restrict__ tt, const float* __restrict__ depth,
-                              const uint32_t* __restrict__ vis_off, int64_t n, uint32_t* __restrict__ key,
-                              uint32_t* __restrict__ val, uint32_t* __restrict__ clear32, int64_t n_clear,
-                              unsigned long long* __restrict__ clear64) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n_clear) clear32[i] = 0u;
-  if (i == 0) *clear64 = 0ull;
-  if (i >= n || tt[i] == 0) return;
-  const uint32_t o = vis_off[i];
-  key[o] = __float_as_uint(depth[i]);   // depth > 0: the bit pattern orders like the value
-  val[o] = (uint32_t)i;
+// Down-sweep of the visibility scan fused with the compaction.  Thread t of
+// block b owns elements [4096 b + 16 t, + 16) of the flattened (camera,
+// pidx) array (read in 16-byte pieces when vec); a visible element's place
+// among the block's visible elements (exclusive scan of the flags) puts its
+// key (the depth's bit pattern: depth > 0, so it orders like the value) and
+// its index in LDS, and the block's run is written out contiguously at the
+// block's start, the sum of the earlier blocks' counts (kSums: added up here
+// from the blocks' sums, one launch fewer; else partial holds their scan).
+// Block 0 writes the count of visible pairs.  The grid also clears
+// clear32[0, n_clear) (the depth sort's control words) and *clear64 (the
+// binning's error word).
+template <bool kSums>
+__global__ void __launch_bounds__(kScanThreads) k_vis_compact(const uint32_t* __restrict__ tt,
+                                                              const float* __restrict__ depth, int64_t n,
+                                                              const unsigned long long* __restrict__ partial,
+                                                              int64_t nb, unsigned long long* __restrict__ total,
+                                                              uint32_t* __restrict__ key, uint32_t* __restrict__ val,
+                                                              uint32_t* __restrict__ clear32, int64_t n_clear,
+                                                              unsigned long long* __restrict__ clear64, int vec) {
+  for (int64_t i = (int64_t)blockIdx.x * kScanThreads + threadIdx.x; i < n_clear;
+       i += (int64_t)gridDim.x * kScanThreads)
+    clear32[i] = 0u;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *clear64 = 0ull;
+  constexpr int kW = kScanThreads / kWave;
+  __shared__ unsigned long long bpre[kW + 1];
+  __shared__ uint32_t wtot[kW];
+  __shared__ uint32_t skey[kScanTile], sval[kScanTile];
+  const int w = threadIdx.x / kWave, lane = __lane_id();
+  if (kSums) {
+    const int64_t upto = blockIdx.x == 0 ? nb : (int64_t)blockIdx.x;
+    unsigned long long a = 0;
+    for (int64_t q = threadIdx.x; q < upto; q += kScanThreads) a += partial[q];
+    a = wave_sum(a);
+    if (lane == 0) bpre[w] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long t = 0;
+      for (int q = 0; q < kW; ++q) t += bpre[q];
+      if (blockIdx.x == 0) *total = t;
+      bpre[kW] = blockIdx.x == 0 ? 0ull : t;
+    }
+    __syncthreads();
+  }
+  const unsigned long long bp = kSums ? bpre[kW] : partial[blockIdx.x];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t f[kScanItems], d[kScanItems];
+  if (vec && base + kScanItems <= n) {
+#pragma unroll
+    for (int j = 0; j < kScanItems; j += 4) {
+      const uint4 a = *reinterpret_cast<const uint4*>(tt + base + j);
+      const uint4 b = *reinterpret_cast<const uint4*>(depth + base + j);
+      f[j] = a.x != 0u; f[j + 1] = a.y != 0u; f[j + 2] = a.z != 0u; f[j + 3] = a.w != 0u;
+      d[j] = b.x; d[j + 1] = b.y; d[j + 2] = b.z; d[j + 3] = b.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      const bool in = base + k < n;
+      f[k] = in && tt[base + k] != 0u;
+      d[k] = f[k] ? __float_as_uint(depth[base + k]) : 0u;
+    }
+  }
+  uint32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) sum += f[k];
+  const uint32_t inc = wave_incl_scan(sum);
+  if (lane == kWave - 1) wtot[w] = inc;
+  __syncthreads();
+  uint32_t off = inc - sum, cnt = 0;
+  for (int q = 0; q < kW; ++q) {
+    off += q < w ? wtot[q] : 0u;
+    cnt += wtot[q];
+  }
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (f[k]) {
+      skey[off] = d[k];
+      sval[off] = (uint32_t)(base + k);
+      ++off;
+    }
+  }
+  __syncthreads();
+  for (uint32_t j = threadIdx.x; j < cnt; j += kScanThreads) {
+    key[bp + j] = skey[j];
+    val[bp + j] = sval[j];
+  }
 }
 
 // Instances of the depth-ordered visible pairs, each pair's tiles in
@@ -327,17 +400,12 @@ __global__ void __launch_bounds__(64) k_emit(const uint32_t* __restrict__ vis_re
 // device (grid-stride).  A thread takes four consecutive keys (one 16-byte
 // load when kVec: the keys are 16-byte aligned) and compares each with its
 // neighbours; ~0u stands in past either end (keys are below 2^31).
-// After a failed sort (*err set) the ranges stay empty, so the compositing
-// reads no entry, and the flag is copied to host_err for the host.
+// After a failed depth sort (*err set) the ranges stay empty, so the
+// compositing reads no entry.
 template <bool kVec>
 __global__ void k_ranges(const uint32_t* __restrict__ key, int64_t n_max, const unsigned long long* __restrict__ d_n,
-                         uint32_t* __restrict__ ranges, const uint32_t* __restrict__ err,
-                         unsigned long long* __restrict__ host_err) {
-  const uint32_t failed = *err;
-  if (failed) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *host_err = failed;
-    return;
-  }
+                         uint32_t* __restrict__ ranges, const uint32_t* __restrict__ err) {
+  if (*err) return;
   const int64_t n = dev_count(n_max, d_n);
   const int64_t stride = 4 * (int64_t)gridDim.x * blockDim.x;
   for (int64_t j0 = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x); j0 < n; j0 += stride) {
@@ -815,17 +883,32 @@ extern "C" tide_status tide_bin_sort(const tide_proj* proj, int32_t tiles_x, int
   if (cap < 0) cap = 0;
   BinLayout L = bin_layout(ws, V, N, nt, cap);
 
-  // 1. visible pairs, compacted in (camera, pidx) order, keyed by depth bits
-  //    (a kernel of its own: the scan's down-sweep gives a thread 16
-  //    consecutive items, so writing the pairs there would not coalesce);
-  //    its grid also clears the sorts' control words and the error word
-  scan_exclusive(NonzeroIn{proj->tiles_touched}, nv, L.vis_off, L.partial, &L.totals[0], st);
+  // 1. visible pairs, compacted in (camera, pidx) order, keyed by depth
+  //    bits: the blocks' counts, then the down-sweep that writes each
+  //    block's pairs through LDS (and clears the depth sort's control words
+  //    and the error word)
   {
-    const int64_t n_clear = kOsCtlLen;
-    const int64_t nthreads = nv > n_clear ? nv : n_clear;
-    TIDE_TIMED("compact_vis", st, hipLaunchKernelGGL(k_compact_vis, dim3((uint32_t)ceil_div(nthreads, 256)), dim3(256), 0,
-                                                     st, proj->tiles_touched, proj->depth, L.vis_off, nv, L.ka, L.va,
-                                                     L.ctl, n_clear, &L.totals[3]));
+    const int64_t nbv = ceil_div(nv > 0 ? nv : 1, kScanTile);
+    const bool vec = aligned16(proj->tiles_touched) && aligned16(proj->depth);
+    if (vec)
+      hipLaunchKernelGGL((k_scan_reduce<NonzeroIn, true>), dim3((uint32_t)nbv), dim3(kScanThreads), 0, st,
+                         NonzeroIn{proj->tiles_touched}, nv, nullptr, L.partial);
+    else
+      hipLaunchKernelGGL((k_scan_reduce<NonzeroIn, false>), dim3((uint32_t)nbv), dim3(kScanThreads), 0, st,
+                         NonzeroIn{proj->tiles_touched}, nv, nullptr, L.partial);
+    if (nbv <= 1024) {
+      TIDE_TIMED("compact_vis", st, hipLaunchKernelGGL(k_vis_compact<true>, dim3((uint32_t)nbv), dim3(kScanThreads), 0,
+                                                       st, proj->tiles_touched, proj->depth, nv, L.partial, nbv,
+                                                       &L.totals[0], L.ka, L.va, L.ctl, (int64_t)kOsCtlLen,
+                                                       &L.totals[3], vec ? 1 : 0));
+    } else {
+      hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, L.partial, nbv, &L.totals[0], ScanTail{}, nv,
+                         nullptr);
+      TIDE_TIMED("compact_vis", st, hipLaunchKernelGGL(k_vis_compact<false>, dim3((uint32_t)nbv), dim3(kScanThreads),
+                                                       0, st, proj->tiles_touched, proj->depth, nv, L.partial, nbv,
+                                                       &L.totals[0], L.ka, L.va, L.ctl, (int64_t)kOsCtlLen,
+                                                       &L.totals[3], vec ? 1 : 0));
+    }
   }
   TIDE_LAUNCH_CHECK("visibility compaction");
   uint32_t* err = reinterpret_cast<uint32_t*>(&L.totals[3]);
@@ -837,22 +920,27 @@ extern "C" tide_status tide_bin_sort(const tide_proj* proj, int32_t tiles_x, int
   onesweep_sort_pairs(L.ka, L.va, L.kb, L.vb, nv, 32, kDepthRounds, false, OsWork{L.ctl, L.status, err}, st, &vk, &vrec,
                       &L.totals[0], proj->tiles_touched, L.vis_off);
   TIDE_LAUNCH_CHECK("depth sort");
-  // 3. instance offsets in depth order, closed by inst_off[n_vis] = n_inst
-  scan_exclusive(ArrayIn{L.vis_off}, nv, L.inst_off, L.partial, &L.totals[2], st, &L.totals[0],
-                 ScanTail{nullptr, L.inst_off});
-  TIDE_LAUNCH_CHECK("instance scan");
-  // 4. the counts (and the depth sort's error word) travel to the host while
-  //    the rest of the binning is queued behind them: those kernels are sized
-  //    by the instance capacity and read the counts on the device, so the GPU
-  //    does not wait for the host
+  // 3. instance offsets in depth order, closed by inst_off[n_vis] = n_inst;
+  //    the block that holds the total also copies the counts and the depth
+  //    sort's error word into the pinned host slot, whose event the host
+  //    waits on after queueing the rest of the binning (those kernels are
+  //    sized by the instance capacity and read the counts on the device, so
+  //    the GPU does not wait for the host)
   CountSlot& slot = count_slot();
   std::lock_guard<std::mutex> lk(slot.mu);
   if (!slot.host) {
-    TIDE_HIP(hipHostMalloc((void**)&slot.host, 8 * sizeof(unsigned long long), hipHostMallocDefault));
-    slot.host[4] = 0;
+    TIDE_HIP(hipHostMalloc((void**)&slot.host, 4 * sizeof(unsigned long long), hipHostMallocDefault));
     TIDE_HIP(hipEventCreateWithFlags(&slot.ev, hipEventDisableTiming));
   }
-  TIDE_HIP(hipMemcpyAsync(slot.host, L.totals, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+  {
+    ScanTail tail;
+    tail.end = L.inst_off;
+    tail.copy_src = L.totals;
+    tail.copy_dst = slot.host;
+    tail.copy_n = 4;
+    scan_exclusive(ArrayIn{L.vis_off}, nv, L.inst_off, L.partial, &L.totals[2], st, &L.totals[0], tail);
+  }
+  TIDE_LAUNCH_CHECK("instance scan");
   TIDE_HIP(hipEventRecord(slot.ev, st));
   // 5. emit instances in depth order, keyed by global tile id (and clear
   //    the tile ranges)
@@ -872,15 +960,14 @@ extern "C" tide_status tide_bin_sort(const tide_proj* proj, int32_t tiles_x, int
   radix_sort_pairs(L.tka, L.tva, L.tkb, L.tvb, cap, bits, true, L.hist, L.partial, &L.totals[1], st, &tk, &te,
                    &L.totals[2], nullptr, nullptr, /*xcd_order=*/true);
   TIDE_LAUNCH_CHECK("tile sort");
-  // 7. per-tile ranges (left empty, and the failure reported, if the depth
-  //    sort gave up)
+  // 7. per-tile ranges (left empty if the depth sort gave up)
   if (cap > 0) {
     const int64_t nb = ceil_div(ceil_div(cap, 4), 256);
     const dim3 grid((uint32_t)(nb < 65536 ? nb : 65536));
     if (((uintptr_t)tk & 15) == 0)
-      hipLaunchKernelGGL(k_ranges<true>, grid, dim3(256), 0, st, tk, cap, &L.totals[2], L.ranges, err, slot.host + 4);
+      hipLaunchKernelGGL(k_ranges<true>, grid, dim3(256), 0, st, tk, cap, &L.totals[2], L.ranges, err);
     else
-      hipLaunchKernelGGL(k_ranges<false>, grid, dim3(256), 0, st, tk, cap, &L.totals[2], L.ranges, err, slot.host + 4);
+      hipLaunchKernelGGL(k_ranges<false>, grid, dim3(256), 0, st, tk, cap, &L.totals[2], L.ranges, err);
   }
   TIDE_LAUNCH_CHECK("k_ranges");
   // 8. launch order of the tiles: longest lists first
@@ -896,18 +983,15 @@ extern "C" tide_status tide_bin_sort(const tide_proj* proj, int32_t tiles_x, int
     TIDE_HIP(hipMemcpyAsync(L.order, ord, ntt * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
   }
   TIDE_LAUNCH_CHECK("tile launch order");
-  // 9. the counts, once they are on the host; a sort that gave up in this
-  //    call's depth sort, or in an earlier call's tile sort on this device
-  //    (whose report has landed by now), is an error
+  // 9. the counts, once they are on the host; a depth sort whose look-back
+  //    gave up is an error (its lists are invalid and its ranges empty)
   TIDE_HIP(hipEventSynchronize(slot.ev));
   const int64_t n_vis = (int64_t)slot.host[0];
   const int64_t n_inst = (int64_t)slot.host[2];
-  const unsigned long long failed = slot.host[3] | slot.host[4];
   out->n_vis = n_vis;
   out->n_inst = n_inst;
-  if (failed) {
-    slot.host[4] = 0;
-    set_error("binning: a radix sort's look-back exceeded its spin limit; this call's or the previous call's lists are invalid");
+  if (slot.host[3]) {
+    set_error("binning: the depth sort's look-back exceeded its spin limit; the lists of this call are invalid");
     return TIDE_EHIP;
   }
   if (n_inst >= (int64_t)UINT32_MAX) {
