@@ -169,8 +169,9 @@ tide_status tide_preprocess_noalloc(const tide_pool* pool, const tide_camera* ca
  * (camera, Gaussian) pair is
  * duplicated once per covered tile and the instances are ordered by
  * (camera, tile, depth, pidx): first the visible pairs are sorted stably by
- * depth (LSD radix, 8-bit digits), then the instances, emitted in that depth
- * order, are sorted stably by global tile id (camera * tiles + tile).
+ * depth (LSD radix, 8-bit digits, one kernel per digit whose tiles find
+ * their offsets by decoupled look-back), then the instances, emitted in that
+ * depth order, are sorted stably by global tile id (camera * tiles + tile).
  * Results live in the caller's workspace; tide_bins points into it.
  * ---------------------------------------------------------------------- */
 typedef struct {
@@ -205,7 +206,11 @@ size_t tide_bin_sort_ws_bytes(int32_t n_cams, int64_t n_pidx, int32_t tiles_x, i
  * GPU keeps working meanwhile.  The counts go through a pinned host slot
  * allocated on the first call, one per device, which concurrent calls on a
  * device take in turn.  On TIDE_ECAPACITY, out->ws_required holds the size
- * to retry with (the projection records are unchanged and may be reused). */
+ * to retry with (the projection records are unchanged and may be reused).
+ * TIDE_EHIP also reports a depth-sort tile whose look-back wait exceeded
+ * its poll limit (a guard that ends the wait instead of hanging; it does not
+ * fire while workgroups start in index order): the lists of that call are
+ * then invalid and its tile ranges empty. */
 tide_status tide_bin_sort(const tide_proj* proj, int32_t tiles_x, int32_t tiles_y, void* ws,
                           size_t ws_bytes, tide_bins* out, void* stream);
 
