@@ -305,6 +305,48 @@ def test_binning_and_compositing_on_the_gpu_projection():
     stage_isolated_on_the_gpu_projection(rast, proj, bins, fr, cams, range(3))
 
 
+def launch_order_is_stable_by_length(order, ranges):
+    """The launch order is a permutation of the tiles, longest lists first on
+    a log scale of 16 steps per octave of len + 1 (ties in tile order)."""
+    lens = (ranges[:, 1] - ranges[:, 0]).astype(np.int64)
+    assert sorted(order.tolist()) == list(range(len(lens)))
+    x = lens + 1
+    e = np.floor(np.log2(x)).astype(np.int64)
+    frac = np.floor((x / 2.0 ** e - 1.0) * 16).astype(np.int64)
+    bucket = np.minimum(255, 16 * e + frac)
+    assert np.array_equal(order, np.argsort(-bucket, kind="stable"))
+
+
+def test_launch_order_beyond_the_two_kernel_grid():
+    """Eight 4096x2064 views: 264 192 tiles, past the 262 144 (1024 blocks of
+    256) that the two launch-order kernels take, so the launch order comes
+    from the radix sort instead; it must still be the stable order by list
+    length, and view 0's lists must equal the oracle's O6 on the GPU's own
+    projection."""
+    say("case: dense scene, 8 cameras 4096x2064 (264192 tiles), block 1024; launch order by radix sort")
+    th, _ = dense_case()
+    eyes = [(0.4, -0.3, -3.2), (-0.6, 0.2, -2.9), (0.0, 0.8, -3.0), (0.9, 0.1, -2.8),
+            (-0.2, -0.7, -3.1), (0.5, 0.5, -3.3), (-0.8, -0.2, -3.0), (0.1, 0.0, -3.4)]
+    cams = [synth.look_at(e, (0, 0, 0), (0, -1, 0), 4096, 2064, 1800.0) for e in eyes]
+    rast, pool, proj, bins, fr = gpu_forward(th, cams, block_rows=1024)
+    assert bins.n_cams * bins.tiles_x * bins.tiles_y == 264192
+    b = bins_views(rast, bins)
+    ranges = b["ranges"].cpu().numpy().astype(np.int64)
+    launch_order_is_stable_by_length(b["tile_order"].cpu().numpy().astype(np.int64), ranges)
+    V, N = proj.n_cams, proj.n_pidx
+    rec = proj.rec.view(V, N, 12).cpu().numpy().astype(np.float64)
+    dep = proj.depth.view(V, N).cpu().numpy().astype(np.float64)
+    keep = proj.tiles_touched.view(V, N).cpu().numpy() > 0
+    rad = rec[..., 10].astype(np.int32)
+    glst, grng, _ = gpu_lists(rast, bins, N)
+    T = bins.tiles_x * bins.tiles_y
+    gid, orng = oracle.bin_sort(rec[:1, :, 0], rec[:1, :, 1], dep[:1], rad[:1], keep[:1],
+                                synth.cams_array(cams)[:1])
+    assert np.array_equal(normalised_ranges(orng), normalised_ranges(grng[:T]))
+    assert np.array_equal(gid, glst[:len(gid)])
+    say(f"{bins.n_inst} instances; launch order stable by length, view 0's {len(gid)} entries identical")
+
+
 def test_binning_is_bit_exact_on_oracle_inputs():
     say("case: dense scene, 3000 Gaussians, 3 cameras 150x110 (ragged tiles), block 1024; oracle inputs")
     th, cams = dense_case()
@@ -320,16 +362,9 @@ def test_binning_is_bit_exact_on_oracle_inputs():
     assert np.array_equal(g_ranges, ranges)
     g_list = inst_rec[inst_e] % proj.n_pidx
     assert np.array_equal(g_list, gid)
-    # the launch order is a permutation of the tiles, longest lists first on
-    # a log scale of 16 steps per octave of len + 1 (ties in tile order)
     order = b["tile_order"].cpu().numpy().astype(np.int64)
+    launch_order_is_stable_by_length(order, ranges)
     lens = (ranges[:, 1] - ranges[:, 0]).astype(np.int64)
-    assert sorted(order.tolist()) == list(range(len(lens)))
-    x = lens + 1
-    e = np.floor(np.log2(x)).astype(np.int64)
-    frac = np.floor((x / 2.0 ** e - 1.0) * 16).astype(np.int64)
-    bucket = np.minimum(255, 16 * e + frac)
-    assert np.array_equal(order, np.argsort(-bucket, kind="stable"))
     assert (np.diff(lens[order].astype(float)) <= 0).mean() > 0.5
     say(f"instances {bins.n_inst}, visible pairs {bins.n_vis}: lists identical")
 
