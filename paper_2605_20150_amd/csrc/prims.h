@@ -26,6 +26,7 @@ constexpr int kSortWaves = kSortThreads / kWave;       // 4
 constexpr int kSortRounds = 16;
 constexpr int kSortTile = kSortThreads * kSortRounds;  // 4096
 constexpr int kXcds = 8;                               // workgroup b starts on XCD b % 8
+constexpr int64_t kRadixMaxGrid = 8192;                // radix histogram workgroups at most
 
 // ------------------------------------------------------------------ scan
 // Input functors: value of element i as u32; load4 reads elements i..i+3
@@ -236,7 +237,8 @@ inline size_t scan_partial_count(int64_t n) { return (size_t)ceil_div(n > 0 ? n 
 template <bool kVec>
 __global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint32_t* keys, int64_t n_max,
                                                              const unsigned long long* d_n, int shift,
-                                                             uint32_t* ghist, int64_t nb);
+                                                             uint32_t* ghist, int64_t nb,
+                                                             unsigned long long* nscan);
 __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint32_t* keys_in,
                                                                 const uint32_t* vals_in, int64_t n_max,
                                                                 const unsigned long long* d_n, int shift,
@@ -247,12 +249,135 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint32_t* 
 
 inline size_t radix_hist_count(int64_t n) { return 256 * (size_t)ceil_div(n > 0 ? n : 1, kSortTile); }
 
+// Adds this lane's run (digit d, count c) to the wave's bins: one add for
+// the whole wave when every lane holds the same digit (the top digits of
+// sorted or narrow-range keys), else one LDS atomic per lane.
+__device__ __forceinline__ void hist_add(uint32_t* hw, uint32_t d, uint32_t c) {
+  const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+  if (__all(d == d0)) {
+    const uint32_t t = wave_sum(c);
+    if (__lane_id() == 0) atomicAdd(&hw[d0], t);   // atomic: other lanes' earlier runs may add to it too
+  } else {
+    atomicAdd(&hw[d], c);
+  }
+}
+
+// Shared LDS of a sort tile's ranking and scatter (tiles of 256 R keys).
+template <int R>
+struct TileLds {
+  uint32_t wcnt[kSortWaves][256];
+  uint32_t gbase[256], lstart[256], wsum[kSortWaves];
+  uint32_t skey[kSortThreads * R], sval[kSortThreads * R];
+};
+
+// Ranks the keys of tile [b0, b0 + 256 R) ∩ [0, n) by digit (key >> shift) &
+// 255: wave w holds R rounds of 64 consecutive keys; rank[r] is the key's
+// rank among the keys of its digit held by the wave in earlier rounds and
+// lower lanes, and L.wcnt[w][d] ends as the wave's count of digit d.
+// L.wcnt must be zero on entry; the caller synchronises afterwards.
+template <int R>
+__device__ __forceinline__ void tile_rank(const uint32_t* keys_in, const uint32_t* vals_in, int64_t n, int64_t b0,
+                                          int shift, TileLds<R>& L, uint32_t* key, uint32_t* val, uint32_t* rank) {
+  const int w = threadIdx.x / kWave, lane = __lane_id();
+  const uint64_t lt = lanemask_lt();
+  const int64_t base = b0 + (int64_t)w * (kWave * R);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t i = base + (int64_t)r * kWave + lane;
+    const bool ok = i < n;
+    key[r] = ok ? keys_in[i] : 0u;
+    val[r] = ok ? (vals_in ? vals_in[i] : (uint32_t)i) : 0u;
+    const uint32_t d = (key[r] >> shift) & 255u;
+    uint64_t peers = __ballot(ok);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t mk = __ballot(bit);
+      peers &= bit ? mk : ~mk;
+    }
+    uint32_t r0 = 0;
+    if (ok) r0 = L.wcnt[w][d];
+    rank[r] = r0 + (uint32_t)__popcll(peers & lt);
+    // the lowest lane of each digit group advances the wave's counter
+    if (ok && (peers & lt) == 0) L.wcnt[w][d] = r0 + (uint32_t)__popcll(peers);
+  }
+}
+
+// Thread d: turns L.wcnt[.][d] into the waves' offsets within digit d,
+// writes the digit's start in the tile to L.lstart[d] and returns the
+// tile's count of digit d.  Synchronises.
+template <int R>
+__device__ __forceinline__ uint32_t tile_digit_offsets(TileLds<R>& L) {
+  const int d = threadIdx.x, w = threadIdx.x / kWave, lane = __lane_id();
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int q = 0; q < kSortWaves; ++q) {
+    const uint32_t c = L.wcnt[q][d];
+    L.wcnt[q][d] = cnt;
+    cnt += c;
+  }
+  const uint32_t inc = wave_incl_scan(cnt);
+  if (lane == kWave - 1) L.wsum[w] = inc;
+  __syncthreads();
+  uint32_t pre = 0;
+  for (int q = 0; q < w; ++q) pre += L.wsum[q];
+  L.lstart[d] = pre + inc - cnt;
+  return cnt;
+}
+
+// Places the ranked keys in LDS in (digit, rank) order (L.lstart and L.wcnt
+// must be visible).
+template <int R>
+__device__ __forceinline__ void tile_stage(int64_t n, int64_t b0, int shift, TileLds<R>& L, const uint32_t* key,
+                                           const uint32_t* val, const uint32_t* rank) {
+  const int w = threadIdx.x / kWave, lane = __lane_id();
+  const int64_t base = b0 + (int64_t)w * (kWave * R);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t i = base + (int64_t)r * kWave + lane;
+    if (i < n) {
+      const uint32_t dd = (key[r] >> shift) & 255u;
+      const uint32_t j = L.lstart[dd] + L.wcnt[w][dd] + rank[r];
+      L.skey[j] = key[r];
+      L.sval[j] = val[r];
+    }
+  }
+}
+
+// Writes the staged keys out to L.gbase[digit] + their place in the digit's
+// run, so a digit's run lands on consecutive addresses (L.gbase and the
+// staged keys must be visible): out(position, key, value) stores one.
+template <int R, typename Out>
+__device__ __forceinline__ void tile_write(int m, int shift, const TileLds<R>& L, const Out& out) {
+  for (int j = threadIdx.x; j < m; j += kSortThreads) {
+    const uint32_t k = L.skey[j];
+    const uint32_t dd = (k >> shift) & 255u;
+    out(L.gbase[dd] + (uint32_t)j - L.lstart[dd], k, L.sval[j]);
+  }
+}
+
+// The plain output of a pass: key and value, and with gather_src also
+// gather_out[position] = gather_src[value].
+struct PairsOut {
+  uint32_t* keys;
+  uint32_t* vals;
+  const uint32_t* gather_src;
+  uint32_t* gather_out;
+  __device__ void operator()(uint32_t pos, uint32_t k, uint32_t v) const {
+    keys[pos] = k;
+    vals[pos] = v;
+    if (gather_src) gather_out[pos] = gather_src[v];
+  }
+};
+
 // Sorts (keys, vals) stably by bits [0, bits) of the key, 8 bits per pass.
 // Input in (ka, va); with identity_vals the input values are taken to be
 // the input indices and va is only used as storage.  Buffers (ka, va) and
 // (kb, vb) ping-pong; the sorted result pointers are returned through
 // *keys_res / *vals_res.  hist needs radix_hist_count(n) u32, partial
-// scan_partial_count(radix_hist_count(n)) u64, total one u64.  With
+// scan_partial_count(radix_hist_count(n)) u64, total one u64 (two with d_n:
+// then only the tiles that hold the device count's keys are counted,
+// scanned and scattered, the second u64 holding the scan's length).  With
 // gather_src, the last pass also writes gather_out[j] = gather_src[value j]
 // for every sorted position j.  With xcd_order the scatter's tiles are
 // assigned so that each XCD writes a contiguous eighth of them.
@@ -302,12 +427,6 @@ inline size_t onesweep_status_count(int64_t n, int passes, int rounds) {
   return (size_t)passes * 256 * (size_t)ceil_div(n > 0 ? n : 1, kSortThreads * rounds);
 }
 
-// As radix_sort_pairs (bits <= 32, at most kOsMaxPasses passes) over tiles
-// of 256 rounds keys; n is the launch bound and d_n, when given, the count
-// on the device.
-void onesweep_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int64_t n, int bits, int rounds,
-                         bool identity_vals, const OsWork& w, hipStream_t st, uint32_t** keys_res,
-                         uint32_t** vals_res, const unsigned long long* d_n = nullptr,
-                         const uint32_t* gather_src = nullptr, uint32_t* gather_out = nullptr);
+// The sort itself: onesweep_sort_pairs in onesweep.h.
 
 }  // namespace tide

@@ -5,6 +5,7 @@
 #include <cstring>
 #include <mutex>
 
+#include "onesweep.h"
 #include "prims.h"
 #include "raster.h"
 
@@ -341,41 +342,58 @@ __global__ void __launch_bounds__(kScanThreads) k_vis_compact(const uint32_t* __
   }
 }
 
+// What the depth sort's last pass writes for each visible pair, in depth
+// order: the key of its rectangle's first tile (camera-major tile id), its
+// record index, the rectangle's width and its tile count.  The rectangle is
+// gathered here, once per pair, so that the emit reads all of it coalesced.
+struct PairRectOut {
+  uint32_t* first;
+  uint32_t* rec;
+  uint32_t* width;
+  uint32_t* count;
+  const uint32_t* rect;
+  int64_t nv_max, n_pidx;
+  uint32_t n_tiles, tiles_x;
+  __device__ void operator()(uint32_t pos, uint32_t, uint32_t r) const {
+    r = (int64_t)r < nv_max ? r : 0u;   // in bounds even after a failed sort
+    const uint2 q = *reinterpret_cast<const uint2*>(rect + 2 * (int64_t)r);
+    const uint32_t x0 = q.x & 0xffff, y0 = q.x >> 16, x1 = q.y & 0xffff, y1 = q.y >> 16;
+    const uint32_t c = (uint32_t)(r / (uint64_t)n_pidx);
+    first[pos] = c * n_tiles + y0 * tiles_x + x0;
+    rec[pos] = r;
+    width[pos] = x1 - x0;
+    count[pos] = (x1 - x0) * (y1 - y0);
+  }
+};
+
 // Instances of the depth-ordered visible pairs, each pair's tiles in
 // row-major order.  A wave64 workgroup takes 64 consecutive pairs at a time
 // (grid-stride over the pair count read on the device) and walks their
-// contiguous instance range [inst_off[s0], inst_off[s0 + 64]) 64 at a time
+// contiguous instance range [inst_off[s0], inst_off[s0 + 64])) 64 at a time
 // (coalesced writes); a lane finds its pair by binary search over the 64
-// offsets and its tile from the pair's rectangle.  Balanced whatever the
-// footprint sizes.  Instances at or past cap are not written (the call then
-// reports the count it needs).  The grid also clears zero[0, n_zero) (the
-// tile ranges, filled in later).
-__global__ void __launch_bounds__(64) k_emit(const uint32_t* __restrict__ vis_rec,
-                                             const uint32_t* __restrict__ inst_off,
-                                             const uint32_t* __restrict__ rect, int64_t nv_max,
-                                             const unsigned long long* __restrict__ d_nvis, int64_t cap,
-                                             int64_t n_pidx, int32_t Tx, int32_t Ty, uint32_t* __restrict__ tkey,
-                                             uint32_t* __restrict__ inst_rec, uint32_t* __restrict__ zero,
-                                             int64_t n_zero) {
+// offsets and its tile from the pair's first tile and width.  Balanced
+// whatever the footprint sizes.  Instances at or past cap are not written
+// (the call then reports the count it needs).  The grid also clears
+// zero[0, n_zero) (the tile ranges, filled in later).
+__global__ void __launch_bounds__(64) k_emit(const uint32_t* __restrict__ first, const uint32_t* __restrict__ width,
+                                             const uint32_t* __restrict__ vis_rec,
+                                             const uint32_t* __restrict__ inst_off, int64_t nv_max,
+                                             const unsigned long long* __restrict__ d_nvis, int64_t cap, int32_t Tx,
+                                             uint32_t* __restrict__ tkey, uint32_t* __restrict__ inst_rec,
+                                             uint32_t* __restrict__ zero, int64_t n_zero) {
   const int lane = threadIdx.x;
   for (int64_t i = (int64_t)blockIdx.x * kWave + lane; i < n_zero; i += (int64_t)gridDim.x * kWave) zero[i] = 0u;
   const int64_t n_vis = dev_count(nv_max, d_nvis);
   __shared__ uint32_t s_off[kWave + 1];
-  __shared__ uint32_t s_rec[kWave], s_base[kWave], s_x0[kWave], s_w[kWave];
+  __shared__ uint32_t s_rec[kWave], s_first[kWave], s_w[kWave];
   for (int64_t s0 = (int64_t)blockIdx.x * kWave; s0 < n_vis; s0 += (int64_t)gridDim.x * kWave) {
     const int np = (int)(n_vis - s0 < kWave ? n_vis - s0 : kWave);
     if (lane <= np) s_off[lane] = inst_off[s0 + lane];
     if (lane == 0 && np == kWave) s_off[kWave] = inst_off[s0 + kWave];
     if (lane < np) {
-      uint32_t r = vis_rec[s0 + lane];
-      r = (int64_t)r < nv_max ? r : 0u;   // in bounds even after a failed sort
-      const uint32_t c = (uint32_t)(r / (uint64_t)n_pidx);
-      const uint32_t a = rect[2 * (int64_t)r], b = rect[2 * (int64_t)r + 1];
-      const uint32_t x0 = a & 0xffff, y0 = a >> 16, x1 = b & 0xffff;
-      s_rec[lane] = r;
-      s_x0[lane] = x0;
-      s_w[lane] = x1 - x0;
-      s_base[lane] = c * (uint32_t)(Tx * Ty) + y0 * (uint32_t)Tx;   // key of the rectangle's first row, column 0
+      s_rec[lane] = vis_rec[s0 + lane];
+      s_first[lane] = first[s0 + lane];
+      s_w[lane] = width[s0 + lane];
     }
     __syncthreads();
     const uint32_t e0 = s_off[0];
@@ -388,8 +406,18 @@ __global__ void __launch_bounds__(64) k_emit(const uint32_t* __restrict__ vis_re
         else hi = mid;
       }
       const uint32_t k = e - s_off[lo], w = s_w[lo];
-      const uint32_t row = k / w, col = k - row * w;
-      tkey[e] = s_base[lo] + row * (uint32_t)Tx + s_x0[lo] + col;
+      // row = k / w: below 2^24 from the float reciprocal, corrected by one
+      // step (the estimate is off by less than one: row < 2^16)
+      uint32_t row;
+      if (k < (1u << 24)) {
+        row = (uint32_t)((float)k * __builtin_amdgcn_rcpf((float)w));
+        row = row * w > k ? row - 1u : row;
+        row = (row + 1u) * w <= k ? row + 1u : row;
+      } else {
+        row = k / w;
+      }
+      const uint32_t col = k - row * w;
+      tkey[e] = s_first[lo] + row * (uint32_t)Tx + col;
       inst_rec[e] = s_rec[lo];
     }
     __syncthreads();
@@ -548,6 +576,7 @@ constexpr int kDepthRounds = 16;
 struct BinLayout {
   uint32_t *vis_off, *ka, *va, *kb, *vb, *inst_off, *tka, *tva, *tkb, *tvb, *inst_rec, *ranges, *order;
   uint32_t *oka, *ova, *okb, *ovb;   // launch-order radix sort (grids beyond kOrderMaxBlocks blocks)
+  uint32_t* pwidth;                  // per visible pair in depth order, its rectangle's width
   uint32_t* ctl;                     // control words of the depth sort
   unsigned long long* status;        // its look-back words
   uint32_t* hist;                    // per-tile digit counts of the tile sort
@@ -573,6 +602,7 @@ static BinLayout bin_layout(void* ws, int n_cams, int64_t n_pidx, int64_t n_tile
   L.kb = cv.take<uint32_t>(nv);
   L.vb = cv.take<uint32_t>(nv);
   L.inst_off = cv.take<uint32_t>(nv + 1);
+  L.pwidth = cv.take<uint32_t>(nv);
   L.tka = cv.take<uint32_t>(cap);
   L.tva = cv.take<uint32_t>(cap);
   L.tkb = cv.take<uint32_t>(cap);
@@ -595,7 +625,7 @@ static BinLayout bin_layout(void* ws, int n_cams, int64_t n_pidx, int64_t n_tile
   nh = nh > nho ? nh : nho;
   L.hist = cv.take<uint32_t>(nh);
   L.partial = cv.take<unsigned long long>(scan_partial_count(nv > (int64_t)nh ? nv : (int64_t)nh));
-  L.totals = cv.take<unsigned long long>(4);
+  L.totals = cv.take<unsigned long long>(6);   // n_vis, -, n_inst, error word, tile sort's scan total and length
   L.bytes = cv.used;
   return L;
 }
@@ -914,11 +944,14 @@ extern "C" tide_status tide_bin_sort(const tide_proj* proj, int32_t tiles_x, int
   uint32_t* err = reinterpret_cast<uint32_t*>(&L.totals[3]);
   // 2. stable sort of the visible pairs by depth; grids are sized by the
   //    upper bound and the kernels read the visible count from the device;
-  //    the last pass also gathers each pair's tile count into depth order
-  //    (into vis_off, free once the compaction has run)
-  uint32_t *vk, *vrec;
-  onesweep_sort_pairs(L.ka, L.va, L.kb, L.vb, nv, 32, kDepthRounds, false, OsWork{L.ctl, L.status, err}, st, &vk, &vrec,
-                      &L.totals[0], proj->tiles_touched, L.vis_off);
+  //    the last pass writes, per pair in depth order, its first tile's key
+  //    (over the keys, not needed after the sort), its record index, its
+  //    rectangle's width and its tile count (into vis_off, free once the
+  //    compaction has run)
+  uint32_t *pfirst, *vrec;
+  onesweep_sort_pairs<kDepthRounds>(
+      L.ka, L.va, L.kb, L.vb, nv, 32, false, OsWork{L.ctl, L.status, err}, st, &pfirst, &vrec, &L.totals[0],
+      PairRectOut{L.ka, L.va, L.pwidth, L.vis_off, proj->rect, nv, N, (uint32_t)nt, (uint32_t)tiles_x});
   TIDE_LAUNCH_CHECK("depth sort");
   // 3. instance offsets in depth order, closed by inst_off[n_vis] = n_inst;
   //    the block that holds the total also copies the counts and the depth
@@ -948,8 +981,8 @@ extern "C" tide_status tide_bin_sort(const tide_proj* proj, int32_t tiles_x, int
   {
     const int64_t chunks = ceil_div(nv > 0 ? nv : 1, kWave);
     TIDE_TIMED("emit", st, hipLaunchKernelGGL(k_emit, dim3((uint32_t)(chunks < 32768 ? chunks : 32768)), dim3(kWave), 0,
-                                              st, vrec, L.inst_off, proj->rect, nv, &L.totals[0], cap, N, tiles_x,
-                                              tiles_y, L.tka, L.inst_rec, L.ranges, nr));
+                                              st, pfirst, L.pwidth, vrec, L.inst_off, nv, &L.totals[0], cap, tiles_x,
+                                              L.tka, L.inst_rec, L.ranges, nr));
   }
   TIDE_LAUNCH_CHECK("k_emit");
   // 6. stable sort by tile; values are emission indices (histogram, scan
@@ -957,7 +990,7 @@ extern "C" tide_status tide_bin_sort(const tide_proj* proj, int32_t tiles_x, int
   //    more than the launches it saves)
   const int bits = tile_key_bits(V, nt);
   uint32_t *tk, *te;
-  radix_sort_pairs(L.tka, L.tva, L.tkb, L.tvb, cap, bits, true, L.hist, L.partial, &L.totals[1], st, &tk, &te,
+  radix_sort_pairs(L.tka, L.tva, L.tkb, L.tvb, cap, bits, true, L.hist, L.partial, &L.totals[4], st, &tk, &te,
                    &L.totals[2], nullptr, nullptr, /*xcd_order=*/true);
   TIDE_LAUNCH_CHECK("tile sort");
   // 7. per-tile ranges (left empty if the depth sort gave up)
