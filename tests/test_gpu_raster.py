@@ -266,7 +266,7 @@ def stage_isolated_on_the_gpu_projection(rast, proj, bins, fr, cams, views):
     dep = proj.depth.view(V, N).cpu().numpy().astype(np.float64)
     tt = proj.tiles_touched.view(V, N).cpu().numpy().astype(np.int64)
     keep = tt > 0
-    rad = rec[..., 10].astype(np.int32)
+    rad = np.where(keep, rec[..., 10], 0.0).astype(np.int32)   # culled pairs' records are not written
     grect = gpu_rects(proj, V, N)
     orect = oracle.tile_rects(rec[..., 0][keep], rec[..., 1][keep], rad[keep], Tx, Ty)
     assert np.array_equal(orect, grect[keep]), f"{int((orect != grect[keep]).any(1).sum())} rectangles differ"
@@ -337,7 +337,7 @@ def test_launch_order_beyond_the_two_kernel_grid():
     rec = proj.rec.view(V, N, 12).cpu().numpy().astype(np.float64)
     dep = proj.depth.view(V, N).cpu().numpy().astype(np.float64)
     keep = proj.tiles_touched.view(V, N).cpu().numpy() > 0
-    rad = rec[..., 10].astype(np.int32)
+    rad = np.where(keep, rec[..., 10], 0.0).astype(np.int32)   # culled pairs' records are not written
     glst, grng, _ = gpu_lists(rast, bins, N)
     T = bins.tiles_x * bins.tiles_y
     gid, orng = oracle.bin_sort(rec[:1, :, 0], rec[:1, :, 1], dep[:1], rad[:1], keep[:1],
