@@ -12,21 +12,25 @@ namespace tide {
 // tiles b, b + G, ... of the actual count, clears their status words for
 // every pass, counts into LDS bins and adds its nonzero bins to its copy of
 // the global counts (device-scope atomics, at most 256 per pass and block).
-template <bool kVec, int R>
+template <bool kVec>
 __global__ void __launch_bounds__(kSortThreads) k_os_hist(const uint32_t* keys, int64_t n_max,
                                                           const unsigned long long* d_n, int passes,
-                                                          int64_t nb_max, uint32_t* ctl,
+                                                          int64_t nb_max, int64_t tile_keys, uint32_t* ctl,
                                                           unsigned long long* status) {
   const int64_t n = dev_count(n_max, d_n);
-  const int64_t nb = (n + kSortThreads * R - 1) / (kSortThreads * R);
+  // the look-back words of the passes' tiles (tile_keys keys each) below the count
+  const int64_t nbp = (n + tile_keys - 1) / tile_keys;
+  for (int64_t t = blockIdx.x; t < nbp; t += gridDim.x)
+    for (int p = 0; p < passes; ++p) status[((int64_t)p * nb_max + t) * 256 + threadIdx.x] = 0ull;
+  // the counts, over chunks of 4096 keys
+  const int64_t nb = (n + kSortTile - 1) / kSortTile;
   __shared__ uint32_t h[kOsMaxPasses][256];
   for (int k = threadIdx.x; k < kOsMaxPasses * 256; k += kSortThreads) (&h[0][0])[k] = 0;
   __syncthreads();
   for (int64_t t = blockIdx.x; t < nb; t += gridDim.x) {
-    for (int p = 0; p < passes; ++p) status[((int64_t)p * nb_max + t) * 256 + threadIdx.x] = 0ull;
-    const int64_t base = t * (kSortThreads * R);
+    const int64_t base = t * kSortTile;
 #pragma unroll
-    for (int r = 0; r < R / 4; ++r) {
+    for (int r = 0; r < kSortRounds / 4; ++r) {
       const int64_t i = base + 4 * ((int64_t)r * kSortThreads + threadIdx.x);
       uint32_t k4[4];
       int cnt = 0;   // valid keys of the four (a prefix)
@@ -84,41 +88,46 @@ __global__ void __launch_bounds__(kSortThreads) k_os_hist(const uint32_t* keys, 
 // atomics serialise at about 12 ns each: 0.15 ms per binning.)
 constexpr unsigned long long kOsAgg = 1ull << 32, kOsIncl = 2ull << 32;
 
-template <int R, typename Out>
-__global__ void __launch_bounds__(kSortThreads) k_os_pass(const uint32_t* keys_in, const uint32_t* vals_in,
-                                                          int64_t n_max, const unsigned long long* d_n, int shift,
-                                                          unsigned long long* status,
-                                                          uint32_t* ctl, int pass, uint32_t* err, Out out) {
-  __shared__ TileLds<R> L;
-  for (int k = threadIdx.x; k < kSortWaves * 256; k += kSortThreads) (&L.wcnt[0][0])[k] = 0;
+template <int R, int W, typename Out>
+__global__ void __launch_bounds__(kWave * W) k_os_pass(const uint32_t* keys_in, const uint32_t* vals_in,
+                                                       int64_t n_max, const unsigned long long* d_n, int shift,
+                                                       unsigned long long* status, uint32_t* ctl, int pass,
+                                                       uint32_t* err, Out out) {
+  constexpr int kTile = kWave * W * R;
+  __shared__ TileLds<R, W> L;
+  for (int k = threadIdx.x; k < W * 256; k += kWave * W) (&L.wcnt[0][0])[k] = 0;
   __syncthreads();
   const int64_t t = blockIdx.x;
   const int64_t n = dev_count(n_max, d_n);
-  const int64_t b0 = t * (kSortThreads * R);
+  const int64_t b0 = t * kTile;
   if (b0 >= n) return;
-  const int m = (int)(n - b0 < kSortThreads * R ? n - b0 : kSortThreads * R);
+  const int m = (int)(n - b0 < kTile ? n - b0 : kTile);
   uint32_t key[R], val[R], rank[R];
   tile_rank(keys_in, vals_in, n, b0, shift, L, key, val, rank);
   __syncthreads();
   const uint32_t cnt = tile_digit_offsets(L);
+  // threads 0..255 own one digit each from here on
   const int d = threadIdx.x;
+  const bool dig = d < 256;
   unsigned long long* mine = status + t * 256 + d;
-  __hip_atomic_store(mine, (t == 0 ? kOsIncl : kOsAgg) | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (dig) __hip_atomic_store(mine, (t == 0 ? kOsIncl : kOsAgg) | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   // the tile goes to LDS before the look-back, so its registers are free
   // while the look-back waits
   __syncthreads();
   tile_stage(n, b0, shift, L, key, val, rank);
-  // look-back: kOsWindow earlier tiles' words per poll, nearest first; the
-  // aggregates before the first inclusive word are added, and a word not
-  // yet published is polled again (after the aggregates before it)
   // this digit's count over all keys (its copies added up): a digit no key
   // holds needs no start, so its words stay aggregates of zero and no tile
   // walks back for it (most of the top byte's digits, say)
   uint32_t gc = 0;
+  if (dig) {
 #pragma unroll
-  for (int c = 0; c < kOsCopies; ++c) gc += ctl[kOsCtlWords + (c * kOsMaxPasses + pass) * 256 + d];
+    for (int c = 0; c < kOsCopies; ++c) gc += ctl[kOsCtlWords + (c * kOsMaxPasses + pass) * 256 + d];
+  }
+  // look-back: kOsWindow earlier tiles' words per poll, nearest first; the
+  // aggregates before the first inclusive word are added, and a word not
+  // yet published is polled again (after the aggregates before it)
   uint32_t excl = 0;
-  if (t > 0 && gc > 0) {
+  if (dig && t > 0 && gc > 0) {
     int64_t j = t - 1;
     uint32_t spins = 0;
     for (;;) {
@@ -157,40 +166,44 @@ __global__ void __launch_bounds__(kSortThreads) k_os_pass(const uint32_t* keys_i
     }
     __hip_atomic_store(mine, kOsIncl | (excl + cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  // the digit's start: exclusive scan of the global digit counts
+  // the digit's start: exclusive scan of the global digit counts (waves 0..3)
   const uint32_t ginc = wave_incl_scan(gc);
   const int w = threadIdx.x / kWave;
   __syncthreads();   // L.wsum is free again
-  if (__lane_id() == kWave - 1) L.wsum[w] = ginc;
+  if (dig && __lane_id() == kWave - 1) L.wsum[w] = ginc;
   __syncthreads();
-  uint32_t gpre = 0;
-  for (int q = 0; q < w; ++q) gpre += L.wsum[q];
-  L.gbase[d] = gpre + ginc - gc + excl;
+  if (dig) {
+    uint32_t gpre = 0;
+    for (int q = 0; q < w; ++q) gpre += L.wsum[q];
+    L.gbase[d] = gpre + ginc - gc + excl;
+  }
   __syncthreads();
   tile_write(m, shift, L, out);
 }
 
-template <int R, typename LastOut>
+template <int R, int W, typename LastOut>
 void onesweep_run(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int64_t n, int passes, bool identity_vals,
                   const OsWork& w, hipStream_t st, uint32_t** keys_res, uint32_t** vals_res,
                   const unsigned long long* d_n, const LastOut& last_out) {
   uint32_t *ki = ka, *vi = va, *ko = kb, *vo = vb;
-  const int64_t nb = ceil_div(n, kSortThreads * R);
-  const uint32_t g = (uint32_t)(nb < kOsHistBlocks ? nb : kOsHistBlocks);
+  constexpr int64_t kTile = kWave * W * R;
+  const int64_t nb = ceil_div(n, kTile);
+  const int64_t nc = ceil_div(n, kSortTile);
+  const uint32_t g = (uint32_t)(nc < kOsHistBlocks ? nc : kOsHistBlocks);
   if (((uintptr_t)ki & 15) == 0)
-    hipLaunchKernelGGL((k_os_hist<true, R>), dim3(g), dim3(kSortThreads), 0, st, ki, n, d_n, passes, nb, w.ctl,
+    hipLaunchKernelGGL(k_os_hist<true>, dim3(g), dim3(kSortThreads), 0, st, ki, n, d_n, passes, nb, kTile, w.ctl,
                        w.status);
   else
-    hipLaunchKernelGGL((k_os_hist<false, R>), dim3(g), dim3(kSortThreads), 0, st, ki, n, d_n, passes, nb, w.ctl,
+    hipLaunchKernelGGL(k_os_hist<false>, dim3(g), dim3(kSortThreads), 0, st, ki, n, d_n, passes, nb, kTile, w.ctl,
                        w.status);
   for (int p = 0; p < passes; ++p) {
     const uint32_t* vin = (identity_vals && p == 0) ? nullptr : vi;
     unsigned long long* sp = w.status + (size_t)p * nb * 256;
     if (p + 1 == passes)
-      hipLaunchKernelGGL((k_os_pass<R, LastOut>), dim3((uint32_t)nb), dim3(kSortThreads), 0, st, ki, vin, n, d_n,
+      hipLaunchKernelGGL((k_os_pass<R, W, LastOut>), dim3((uint32_t)nb), dim3(kWave * W), 0, st, ki, vin, n, d_n,
                          8 * p, sp, w.ctl, p, w.err, last_out);
     else
-      hipLaunchKernelGGL((k_os_pass<R, PairsOut>), dim3((uint32_t)nb), dim3(kSortThreads), 0, st, ki, vin, n, d_n,
+      hipLaunchKernelGGL((k_os_pass<R, W, PairsOut>), dim3((uint32_t)nb), dim3(kWave * W), 0, st, ki, vin, n, d_n,
                          8 * p, sp, w.ctl, p, w.err, PairsOut{ko, vo, nullptr, nullptr});
     uint32_t* t = ki; ki = ko; ko = t;
     t = vi; vi = vo; vo = t;
@@ -200,23 +213,24 @@ void onesweep_run(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int64_
 }
 
 // As radix_sort_pairs (bits <= 32, at most kOsMaxPasses passes) over tiles
-// of 256 R keys, R in {4, 8, 16}; n is the launch bound and d_n, when given,
-// the count on the device.  The last pass writes through last_out(position,
-// key, value) instead of the ping-pong buffer it would fill (PairsOut over
-// that buffer gives the sorted keys and values; another functor can write
-// what the caller needs of each sorted pair instead), and *keys_res /
-// *vals_res name that buffer as if it had.
-template <int R, typename LastOut>
+// of 64 W R keys (W waves of R rounds, W >= 4); n is the launch bound and
+// d_n, when given, the count on the device.  The last pass writes through
+// last_out(position, key, value) instead of the ping-pong buffer it would
+// fill (PairsOut over that buffer gives the sorted keys and values; another
+// functor can write what the caller needs of each sorted pair instead), and
+// *keys_res / *vals_res name that buffer as if it had.
+template <int R, int W, typename LastOut>
 void onesweep_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int64_t n, int bits,
                          bool identity_vals, const OsWork& w, hipStream_t st, uint32_t** keys_res,
                          uint32_t** vals_res, const unsigned long long* d_n, const LastOut& last_out) {
+  static_assert(W >= 4, "256 threads own the digits");
   const int passes = (bits + 7) / 8;
   if (n <= 0 || passes <= 0) {
     *keys_res = ka;
     *vals_res = va;
     return;
   }
-  onesweep_run<R>(ka, va, kb, vb, n, passes, identity_vals, w, st, keys_res, vals_res, d_n, last_out);
+  onesweep_run<R, W>(ka, va, kb, vb, n, passes, identity_vals, w, st, keys_res, vals_res, d_n, last_out);
 }
 
 }  // namespace tide

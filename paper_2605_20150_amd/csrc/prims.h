@@ -234,19 +234,6 @@ inline void scan_exclusive(In in, int64_t n, uint32_t* out, unsigned long long* 
 inline size_t scan_partial_count(int64_t n) { return (size_t)ceil_div(n > 0 ? n : 1, kScanTile); }
 
 // ------------------------------------------------------------- radix sort
-template <bool kVec>
-__global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint32_t* keys, int64_t n_max,
-                                                             const unsigned long long* d_n, int shift,
-                                                             uint32_t* ghist, int64_t nb,
-                                                             unsigned long long* nscan);
-__global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint32_t* keys_in,
-                                                                const uint32_t* vals_in, int64_t n_max,
-                                                                const unsigned long long* d_n, int shift,
-                                                                const uint32_t* gofs, int64_t nb,
-                                                                uint32_t* keys_out, uint32_t* vals_out,
-                                                                const uint32_t* gather_src, uint32_t* gather_out,
-                                                                int xcd_order);
-
 inline size_t radix_hist_count(int64_t n) { return 256 * (size_t)ceil_div(n > 0 ? n : 1, kSortTile); }
 
 // Adds this lane's run (digit d, count c) to the wave's bins: one add for
@@ -262,22 +249,23 @@ __device__ __forceinline__ void hist_add(uint32_t* hw, uint32_t d, uint32_t c) {
   }
 }
 
-// Shared LDS of a sort tile's ranking and scatter (tiles of 256 R keys).
-template <int R>
+// Shared LDS of a sort tile's ranking and scatter (tiles of 64 W R keys:
+// W waves of R rounds).
+template <int R, int W = kSortWaves>
 struct TileLds {
-  uint32_t wcnt[kSortWaves][256];
-  uint32_t gbase[256], lstart[256], wsum[kSortWaves];
-  uint32_t skey[kSortThreads * R], sval[kSortThreads * R];
+  uint32_t wcnt[W][256];
+  uint32_t gbase[256], lstart[256], wsum[4];
+  uint32_t skey[kWave * W * R], sval[kWave * W * R];
 };
 
-// Ranks the keys of tile [b0, b0 + 256 R) ∩ [0, n) by digit (key >> shift) &
-// 255: wave w holds R rounds of 64 consecutive keys; rank[r] is the key's
+// Ranks the keys of tile [b0, b0 + 64 W R) ∩ [0, n) by digit (key >> shift)
+// & 255: wave w holds R rounds of 64 consecutive keys; rank[r] is the key's
 // rank among the keys of its digit held by the wave in earlier rounds and
 // lower lanes, and L.wcnt[w][d] ends as the wave's count of digit d.
 // L.wcnt must be zero on entry; the caller synchronises afterwards.
-template <int R>
+template <int R, int W>
 __device__ __forceinline__ void tile_rank(const uint32_t* keys_in, const uint32_t* vals_in, int64_t n, int64_t b0,
-                                          int shift, TileLds<R>& L, uint32_t* key, uint32_t* val, uint32_t* rank) {
+                                          int shift, TileLds<R, W>& L, uint32_t* key, uint32_t* val, uint32_t* rank) {
   const int w = threadIdx.x / kWave, lane = __lane_id();
   const uint64_t lt = lanemask_lt();
   const int64_t base = b0 + (int64_t)w * (kWave * R);
@@ -303,32 +291,37 @@ __device__ __forceinline__ void tile_rank(const uint32_t* keys_in, const uint32_
   }
 }
 
-// Thread d: turns L.wcnt[.][d] into the waves' offsets within digit d,
-// writes the digit's start in the tile to L.lstart[d] and returns the
-// tile's count of digit d.  Synchronises.
-template <int R>
-__device__ __forceinline__ uint32_t tile_digit_offsets(TileLds<R>& L) {
+// Thread d < 256: turns L.wcnt[.][d] into the waves' offsets within digit
+// d, writes the digit's start in the tile to L.lstart[d] and returns the
+// tile's count of digit d (threads from 256 on return 0).  Synchronises.
+template <int R, int W>
+__device__ __forceinline__ uint32_t tile_digit_offsets(TileLds<R, W>& L) {
   const int d = threadIdx.x, w = threadIdx.x / kWave, lane = __lane_id();
+  const bool dig = d < 256;
   uint32_t cnt = 0;
+  if (dig) {
 #pragma unroll
-  for (int q = 0; q < kSortWaves; ++q) {
-    const uint32_t c = L.wcnt[q][d];
-    L.wcnt[q][d] = cnt;
-    cnt += c;
+    for (int q = 0; q < W; ++q) {
+      const uint32_t c = L.wcnt[q][d];
+      L.wcnt[q][d] = cnt;
+      cnt += c;
+    }
   }
   const uint32_t inc = wave_incl_scan(cnt);
-  if (lane == kWave - 1) L.wsum[w] = inc;
+  if (dig && lane == kWave - 1) L.wsum[w] = inc;
   __syncthreads();
-  uint32_t pre = 0;
-  for (int q = 0; q < w; ++q) pre += L.wsum[q];
-  L.lstart[d] = pre + inc - cnt;
+  if (dig) {
+    uint32_t pre = 0;
+    for (int q = 0; q < w; ++q) pre += L.wsum[q];
+    L.lstart[d] = pre + inc - cnt;
+  }
   return cnt;
 }
 
 // Places the ranked keys in LDS in (digit, rank) order (L.lstart and L.wcnt
 // must be visible).
-template <int R>
-__device__ __forceinline__ void tile_stage(int64_t n, int64_t b0, int shift, TileLds<R>& L, const uint32_t* key,
+template <int R, int W>
+__device__ __forceinline__ void tile_stage(int64_t n, int64_t b0, int shift, TileLds<R, W>& L, const uint32_t* key,
                                            const uint32_t* val, const uint32_t* rank) {
   const int w = threadIdx.x / kWave, lane = __lane_id();
   const int64_t base = b0 + (int64_t)w * (kWave * R);
@@ -347,9 +340,9 @@ __device__ __forceinline__ void tile_stage(int64_t n, int64_t b0, int shift, Til
 // Writes the staged keys out to L.gbase[digit] + their place in the digit's
 // run, so a digit's run lands on consecutive addresses (L.gbase and the
 // staged keys must be visible): out(position, key, value) stores one.
-template <int R, typename Out>
-__device__ __forceinline__ void tile_write(int m, int shift, const TileLds<R>& L, const Out& out) {
-  for (int j = threadIdx.x; j < m; j += kSortThreads) {
+template <int R, int W, typename Out>
+__device__ __forceinline__ void tile_write(int m, int shift, const TileLds<R, W>& L, const Out& out) {
+  for (int j = threadIdx.x; j < m; j += kWave * W) {
     const uint32_t k = L.skey[j];
     const uint32_t dd = (k >> shift) & 255u;
     out(L.gbase[dd] + (uint32_t)j - L.lstart[dd], k, L.sval[j]);
@@ -422,9 +415,9 @@ struct OsWork {
   uint32_t* err;                  // set to nonzero if a look-back gave up
 };
 
-// Tiles of 256 rounds keys, rounds in {4, 8, 16}.
-inline size_t onesweep_status_count(int64_t n, int passes, int rounds) {
-  return (size_t)passes * 256 * (size_t)ceil_div(n > 0 ? n : 1, kSortThreads * rounds);
+// Look-back words of a sort of n keys in tiles of tile_keys keys.
+inline size_t onesweep_status_count(int64_t n, int passes, int64_t tile_keys) {
+  return (size_t)passes * 256 * (size_t)ceil_div(n > 0 ? n : 1, tile_keys);
 }
 
 // The sort itself: onesweep_sort_pairs in onesweep.h.

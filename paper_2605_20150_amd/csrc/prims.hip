@@ -101,7 +101,13 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint32_t* key
   }
 }
 
-__global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint32_t* keys_in,
+// The scatter's 4096-key tiles as eight waves of eight rounds: a tile's
+// ranking is a chain of rounds, and eight waves ran the two tile-sort passes
+// over 14 M keys in 56.5 + 60.6 us against 61.4 + 66.8 us with four.
+constexpr int kScatterWaves = 8;
+constexpr int kScatterRounds = kSortTile / (kWave * kScatterWaves);
+
+__global__ void __launch_bounds__(kWave * kScatterWaves) k_radix_scatter(const uint32_t* keys_in,
                                                                 const uint32_t* vals_in, int64_t n_max,
                                                                 const unsigned long long* d_n, int shift,
                                                                 const uint32_t* gofs, int64_t nb,
@@ -126,11 +132,11 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint32_t* 
   if (tile >= nba) return;
   const int64_t b0 = tile * kSortTile;
   const int m = (int)(n - b0 < kSortTile ? n - b0 : kSortTile);   // elements of this tile
-  __shared__ TileLds<kSortRounds> L;
-  for (int k = threadIdx.x; k < kSortWaves * 256; k += kSortThreads) (&L.wcnt[0][0])[k] = 0;
-  L.gbase[threadIdx.x] = gofs[(int64_t)threadIdx.x * nba + tile];
+  __shared__ TileLds<kScatterRounds, kScatterWaves> L;
+  for (int k = threadIdx.x; k < kScatterWaves * 256; k += kWave * kScatterWaves) (&L.wcnt[0][0])[k] = 0;
+  if (threadIdx.x < 256) L.gbase[threadIdx.x] = gofs[(int64_t)threadIdx.x * nba + tile];
   __syncthreads();
-  uint32_t key[kSortRounds], val[kSortRounds], rank[kSortRounds];
+  uint32_t key[kScatterRounds], val[kScatterRounds], rank[kScatterRounds];
   tile_rank(keys_in, vals_in, n, b0, shift, L, key, val, rank);
   __syncthreads();
   tile_digit_offsets(L);
@@ -162,7 +168,8 @@ void radix_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, in
                            nb, nscan);
       scan_exclusive(ArrayIn{hist}, 256 * nb, hist, partial, total, st, nscan);
       const bool last = shift + 8 >= bits;
-      hipLaunchKernelGGL(k_radix_scatter, dim3((uint32_t)nb), dim3(kSortThreads), 0, st, ki, ident ? nullptr : vi, n,
+      hipLaunchKernelGGL(k_radix_scatter, dim3((uint32_t)nb), dim3(kWave * kScatterWaves), 0, st, ki,
+                         ident ? nullptr : vi, n,
                          d_n, shift, hist, nb, ko, vo, last ? gather_src : nullptr, last ? gather_out : nullptr,
                          xcd_order ? 1 : 0);
       ident = false;

@@ -569,9 +569,13 @@ __global__ void __launch_bounds__(kOrderTiles) k_order_place(const uint32_t* __r
   }
 }
 
-// Keys per thread of the depth sort's tiles (256 threads): 4096-key tiles
-// were faster than 2048 or 1024 (fewer look-back words to publish and read).
-constexpr int kDepthRounds = 16;
+// The depth sort's tiles: kDepthWaves waves of kDepthRounds keys per lane.
+// 4096-key tiles were faster than 2048 or 1024 (fewer look-back words to
+// publish and read), and eight waves of eight rounds faster than four of
+// sixteen (124 against 144 us for the four passes over 2.25 M keys: a
+// tile's ranking is a chain of rounds), sixteen of four no faster.
+constexpr int kDepthWaves = 8;
+constexpr int kDepthRounds = 64 / kDepthWaves;
 
 struct BinLayout {
   uint32_t *vis_off, *ka, *va, *kb, *vb, *inst_off, *tka, *tva, *tkb, *tvb, *inst_rec, *ranges, *order;
@@ -613,7 +617,7 @@ static BinLayout bin_layout(void* ws, int n_cams, int64_t n_pidx, int64_t n_tile
   L.order = cv.take<uint32_t>(ntt);
   L.tvis = cv.take<unsigned long long>(2 * ntt);
   L.ctl = cv.take<uint32_t>(kOsCtlLen);
-  L.status = cv.take<unsigned long long>(onesweep_status_count(nv, 4, kDepthRounds));
+  L.status = cv.take<unsigned long long>(onesweep_status_count(nv, 4, (int64_t)kWave * kDepthWaves * kDepthRounds));
   const int64_t nob = ceil_div(ntt, kOrderTiles);
   const bool order_radix = nob > kOrderMaxBlocks;
   L.oka = cv.take<uint32_t>(order_radix ? ntt : 0);
@@ -949,7 +953,7 @@ extern "C" tide_status tide_bin_sort(const tide_proj* proj, int32_t tiles_x, int
   //    rectangle's width and its tile count (into vis_off, free once the
   //    compaction has run)
   uint32_t *pfirst, *vrec;
-  onesweep_sort_pairs<kDepthRounds>(
+  onesweep_sort_pairs<kDepthRounds, kDepthWaves>(
       L.ka, L.va, L.kb, L.vb, nv, 32, false, OsWork{L.ctl, L.status, err}, st, &pfirst, &vrec, &L.totals[0],
       PairRectOut{L.ka, L.va, L.pwidth, L.vis_off, proj->rect, nv, N, (uint32_t)nt, (uint32_t)tiles_x});
   TIDE_LAUNCH_CHECK("depth sort");
