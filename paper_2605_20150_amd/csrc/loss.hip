@@ -102,10 +102,13 @@ __global__ void __launch_bounds__(kWave) k_ssim_fwd(const T* __restrict__ X, con
         if (o < H && inc) {
           const T sxx = mxx - mx * mx, syy = myy - my * my, sxy = mxy - mx * my;
           const T Np = 2 * mx * my + C1, Ns = 2 * sxy + C2, Dp = mx * mx + my * my + C1, Ds = sxx + syy + C2;
-          const T iD = (T)1 / (Dp * Ds);
+          // two reciprocals (the hardware's, within an ulp in FP32) in place
+          // of three divisions: Dp >= C1 and Ds is about C2 or more
+          const T iDp = Mth<T>::rcp_fast(Dp), iDs = Mth<T>::rcp_fast(Ds);
+          const T iD = iDp * iDs;
           const T sv = Np * Ns * iD;
-          const T ds_dmx = 2 * my * Ns * iD - sv * 2 * mx / Dp;
-          const T ds_dsx = -sv / Ds;
+          const T ds_dmx = 2 * my * Ns * iD - sv * 2 * mx * iDp;
+          const T ds_dsx = -sv * iDs;
           const T ds_dsxy = 2 * Np * iD;
           const int64_t p = plane * HW + (int64_t)o * W + c;
           dmaps[p] = ds_dmx - 2 * mx * ds_dsx - my * ds_dsxy;
