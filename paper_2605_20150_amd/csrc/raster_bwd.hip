@@ -98,14 +98,32 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
   __shared__ T s_part[32][4][kG2];   // per entry, the sums of the four rows
 
   const T ks = (T)Ex<T>::k;
+  // The batch ending at h covers entries [max(h - 32, 0), h).  An entry's
+  // record lies two indices deep (its emission index, then that emission's
+  // record); both are loaded a batch ahead (e_c, r_c for this batch, e_n,
+  // r_n for the next), so a batch waits only for its records' fields.
+  uint32_t e_c = 0, r_c = 0, e_n = 0, r_n = 0;
+  {
+    const int32_t h0 = (int32_t)maxl, h1 = h0 - 32;
+    const int32_t l0 = h0 - 32 > 0 ? h0 - 32 : 0, l1 = h1 - 32 > 0 ? h1 - 32 : 0;
+    const bool v0 = h0 > 0 && lane < h0 - l0, v1 = h1 > 0 && lane < h1 - l1;
+    if (v0) e_c = inst_e[start + l0 + lane];
+    if (v1) e_n = inst_e[start + l1 + lane];
+    if (v0) r_c = inst_rec[e_c];
+    if (v1) r_n = inst_rec[e_n];
+  }
   for (int32_t hi = (int32_t)maxl; hi > 0; hi -= 32) {
     const int32_t lo = hi - 32 > 0 ? hi - 32 : 0;
     const int32_t n = hi - lo;
+    const int32_t h2 = hi - 64, l2 = h2 - 32 > 0 ? h2 - 32 : 0;
+    const bool v2 = h2 > 0 && lane < h2 - l2;
+    uint32_t e2 = 0;
+    if (v2) e2 = inst_e[start + l2 + lane];
     uint32_t my_e = 0;
     bool may = false;
     if (lane < n) {
-      my_e = inst_e[start + lo + lane];
-      const T* q = rec + (int64_t)inst_rec[my_e] * kRec;
+      my_e = e_c;
+      const T* q = rec + (int64_t)r_c * kRec;
       s_u[lane] = q[0]; s_v[lane] = q[1];
       s_A[lane] = q[2]; s_B[lane] = q[3]; s_C[lane] = q[4];
       s_Ah[lane] = (T)-0.5 * ks * q[2]; s_Bh[lane] = -ks * q[3]; s_Ch[lane] = (T)-0.5 * ks * q[4];
@@ -217,6 +235,10 @@ __global__ void __launch_bounds__(64) k_render_bwd(const uint32_t* __restrict__ 
       }
       *reinterpret_cast<Rec9<T>*>(partial + (int64_t)my_e * kG2) = r;
     }
+    uint32_t r2 = 0;
+    if (v2) r2 = inst_rec[e2];
+    e_c = e_n; r_c = r_n;
+    e_n = e2; r_n = r2;
     __syncthreads();
   }
 }
